@@ -1,0 +1,176 @@
+/*
+ * cggm.h -- C ABI of the MI355X (gfx950) alternating Newton coordinate descent
+ * solver for the l1-regularized conditional Gaussian graphical model (CGGM).
+ *
+ * Problem (McCarter & Kim, AISTATS 2016, Sec. 2.1, Eq. (1)): given X (n x p)
+ * and Y (n x q), minimise over symmetric positive definite Lambda (q x q) and
+ * Theta (p x q)
+ *
+ *   f(Lambda, Theta) = -log det Lambda + tr(Syy Lambda) + 2 tr(Sxy^T Theta)
+ *                      + tr(Lambda^{-1} Theta^T Sxx Theta)
+ *                      + lamL ||Lambda||_1 + lamT ||Theta||_1
+ *
+ * with Sxx = X^T X / n, Sxy = X^T Y / n, Syy = Y^T Y / n (uncentred), and the
+ * l1 norms elementwise over all entries (diagonal and both triangles).
+ *
+ * Conventions for every entry point:
+ *   - All matrices are dense, row-major, contiguous, float64, in DEVICE memory
+ *     of the current HIP device, unless a parameter says "host".
+ *   - `stream` is a hipStream_t (NULL = the default stream).  All device work
+ *     is ordered on it.  Entry points that return host scalars synchronise it.
+ *   - Input pointers are only read during the call and never retained.
+ *   - Return value: CGGM_OK (0), a warning (> 0: results are valid) or an error
+ *     (< 0: outputs are left untouched).  cggm_last_error() gives a message for
+ *     the last failing call on the calling thread.
+ *   - No entry point throws; the library allocates its own device workspace
+ *     per call with hipMalloc and frees it before returning.
+ */
+#ifndef CGGM_H
+#define CGGM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define CGGM_OK 0
+#define CGGM_MAXITER 1        /* warning: iteration cap reached, result valid   */
+#define CGGM_EINVAL (-1)      /* bad size, NULL pointer, non-finite value       */
+#define CGGM_ENOTPD (-2)      /* Lambda (given or warm start) not pos. definite */
+#define CGGM_ELINESEARCH (-3) /* no Armijo step found (last iterate returned)   */
+#define CGGM_ENOMEM (-4)      /* workspace over budget or hipMalloc failed      */
+#define CGGM_EHIP (-5)        /* a HIP runtime call failed                      */
+
+/* ---- coordinate-descent sweep schedules ------------------------------ */
+#define CGGM_SWEEP_TILED 0      /* conflict-free parallel tile waves (default)   */
+#define CGGM_SWEEP_SEQUENTIAL 1 /* one coordinate at a time in lexicographic
+                                   order: the order of the paper's Algorithm 1
+                                   and of the CPU reference                      */
+
+/* One record per outer iteration (Algorithm 1), filled when options.trace is
+ * non-NULL.  Values describe the iterate at the top of iteration `iter`. */
+typedef struct {
+    int iter;
+    int ls_trials;        /* Cholesky trials in the line search                 */
+    int sweep_fallbacks;  /* sweeps redone tile-sequentially by the descent guard */
+    int _pad;
+    double f;             /* objective at the top of the iteration (FP64)       */
+    double subgrad_l1;    /* l1 norm of the minimum-norm subgradient            */
+    double l1;            /* ||Lambda||_1 + ||Theta||_1                          */
+    double alpha;         /* accepted Lambda step size (0: no step)             */
+    int64_t m_Lambda;     /* |S_Lambda| (upper triangle incl. diagonal)         */
+    int64_t m_Theta;      /* |S_Theta|                                          */
+    int64_t nnz_Lambda;   /* nonzeros of Lambda (both triangles)                */
+    int64_t nnz_Theta;    /* nonzeros of Theta                                  */
+    double t_end_ms;      /* wall time from the start of the solve to the end
+                             of this record's top-of-iteration evaluation       */
+    double ms_gradient;   /* products, gradients, screen, objective             */
+    double ms_lambda_cd;  /* Lambda coordinate-descent sweep                     */
+    double ms_line_search;/* line search incl. the accepted factor's inverse    */
+    double ms_theta_cd;   /* V = Theta Sigma and the Theta sweep                 */
+} cggm_trace_entry;
+
+typedef struct {
+    int max_iter;          /* outer iterations (default 500)                   */
+    int max_ls;            /* line-search trials (default 30)                  */
+    double ls_beta;        /* step shrink factor (default 0.5)                 */
+    double ls_sigma;       /* Armijo sufficient-decrease constant (1e-3)       */
+    int stall_iters;       /* stop after this many iterations without progress
+                              in f or the subgradient (default 3; 0 = off)     */
+    int sweep;             /* CGGM_SWEEP_TILED or CGGM_SWEEP_SEQUENTIAL        */
+    int tile;              /* CD tile edge for CGGM_SWEEP_TILED (0 = default)  */
+    int _pad;
+    size_t workspace_budget;   /* bytes of device workspace allowed (0 = any)  */
+    const double *warm_Lambda; /* device q x q start (NULL = identity)         */
+    const double *warm_Theta;  /* device p x q start (NULL = zero)             */
+    cggm_trace_entry *trace;   /* host array of trace_cap records, or NULL     */
+    int trace_cap;
+    int trace_len;             /* out: records written                          */
+} cggm_options;
+
+/* Fill `opt` with the defaults above. */
+void cggm_default_options(cggm_options *opt);
+
+/* Device bytes cggm_solve would allocate for this shape (the footprint the
+ * workspace_budget option is compared against). */
+size_t cggm_solve_workspace_bytes(int64_t n, int64_t p, int64_t q);
+
+typedef struct cggm_result cggm_result;   /* opaque, owns device CSR arrays */
+
+/*
+ * Alternating Newton coordinate descent (Algorithm 1): from Lambda = I,
+ * Theta = 0 (or the warm start), each outer iteration
+ *   1. factors Lambda = L L^T, forms Sigma = Lambda^{-1}, log det Lambda,
+ *      R = X Theta Sigma, Psi = R^T R / n and the gradients of Eq. (3),
+ *   2. screens the active sets |grad| > lambda or param != 0 (Sec. 2.2),
+ *   3. finds the generalized Newton direction D of Eq. (6) by one
+ *      coordinate-descent pass over S_Lambda, maintaining U = D Sigma,
+ *   4. takes the Armijo step Lambda + alpha D that keeps Lambda positive
+ *      definite (Algorithm 1, line search),
+ *   5. minimises Eq. (7) over Theta by one coordinate-descent pass over
+ *      S_Theta, maintaining V = Theta Sigma (Sec. 3.2).
+ * It stops when ||grad^S||_1 < tol (||Lambda||_1 + ||Theta||_1) (the paper's
+ * stopping rule of Sec. 5.1 with 0.01 replaced by tol), when the iterate stops
+ * moving (stall_iters), or after max_iter iterations (CGGM_MAXITER).
+ *
+ * X: n x p, Y: n x q (device).  lamL, lamT >= 0.  On success *out receives a
+ * result handle (free with cggm_result_free).  The call is blocking: it
+ * synchronises `stream` to take the line-search and stopping decisions.
+ * Errors: CGGM_EINVAL (n, p, q < 1, NULL pointers, negative or non-finite
+ * lambda/tol, non-finite X or Y), CGGM_ENOTPD (warm_Lambda not positive
+ * definite), CGGM_ENOMEM (footprint over workspace_budget or out of memory),
+ * CGGM_EHIP.  CGGM_ELINESEARCH is returned with a valid result when no step
+ * satisfying the Armijo rule exists for a descent direction.
+ */
+int cggm_solve(const double *X, const double *Y, int64_t n, int64_t p, int64_t q,
+               double lamL, double lamT, double tol, cggm_options *opt,
+               cggm_result **out, void *stream);
+
+/* Scalars of a result: nonzeros of Lambda (both triangles) and Theta, the
+ * number of outer iterations, the final objective and the solve status. */
+int cggm_result_info(const cggm_result *res, int64_t *nnz_Lambda, int64_t *nnz_Theta,
+                     int *iters, double *f, int *status);
+
+/* Copy the CSR form of Lambda (q rows, full symmetric) and Theta (p rows) into
+ * caller buffers: rowptr (rows + 1 int64), col (nnz int32), val (nnz float64).
+ * to_host != 0: buffers are host memory; otherwise device memory.  Any of the
+ * six pointers may be NULL to skip that array. */
+int cggm_result_copy(const cggm_result *res, int64_t *L_rowptr, int32_t *L_col,
+                     double *L_val, int64_t *T_rowptr, int32_t *T_col, double *T_val,
+                     int to_host);
+
+/* Copy the dense Lambda (q x q) and Theta (p x q) into caller buffers. */
+int cggm_result_dense(const cggm_result *res, double *Lambda, double *Theta, int to_host);
+
+void cggm_result_free(cggm_result *res);
+
+/*
+ * Objective f(Lambda, Theta) of Eq. (1) at dense device Lambda (q x q,
+ * symmetric) and Theta (p x q); *f_out is a host double.  Returns CGGM_ENOTPD
+ * when Lambda is not positive definite (f is +infinity there).
+ */
+int cggm_objective(const double *X, const double *Y, int64_t n, int64_t p, int64_t q,
+                   const double *Lambda, const double *Theta, double lamL, double lamT,
+                   double *f_out, void *stream);
+
+/*
+ * Gradient of the smooth part g at (Lambda, Theta), Eq. (3):
+ *   G_Lambda = Syy - Sigma - Psi      (q x q, Psi = Sigma Theta^T Sxx Theta Sigma)
+ *   G_Theta  = 2 Sxy + 2 Sxx Theta Sigma   (p x q)
+ * written to caller device buffers.  CGGM_ENOTPD if Lambda is not PD.
+ */
+int cggm_gradient(const double *X, const double *Y, int64_t n, int64_t p, int64_t q,
+                  const double *Lambda, const double *Theta, double *G_Lambda,
+                  double *G_Theta, void *stream);
+
+/* Static text for a status code; thread-local text of the last error. */
+const char *cggm_status_string(int status);
+const char *cggm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CGGM_H */

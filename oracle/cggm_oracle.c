@@ -37,6 +37,9 @@
 /* Relative size of the rounding error of an FP64 objective evaluation. */
 #define ARMIJO_ROUNDING 1e-14
 
+/* Products below this many multiply-adds run on one thread. */
+#define OMP_MIN_WORK 4000000LL
+
 static double *zalloc(size_t count) {
     double *p = (double *)calloc(count ? count : 1, sizeof(double));
     if (!p) abort();
@@ -46,7 +49,7 @@ static double *zalloc(size_t count) {
 /* C = A B (A m x k, B k x nc), skipping zero entries of A. */
 static void matmul(int64_t m, int64_t k, int64_t nc, const double *A, const double *B,
                    double *C) {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (m * k * nc > OMP_MIN_WORK)
     for (int64_t i = 0; i < m; ++i) {
         double *c = C + IDX(i, 0, nc);
         for (int64_t j = 0; j < nc; ++j) c[j] = 0.0;
@@ -62,7 +65,7 @@ static void matmul(int64_t m, int64_t k, int64_t nc, const double *A, const doub
 /* C = A^T B (A k x m, B k x nc), skipping zero entries of A. */
 static void matmul_tn(int64_t m, int64_t k, int64_t nc, const double *A, const double *B,
                       double *C) {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (m * k * nc > OMP_MIN_WORK)
     for (int64_t i = 0; i < m; ++i) {
         double *c = C + IDX(i, 0, nc);
         for (int64_t j = 0; j < nc; ++j) c[j] = 0.0;
@@ -110,7 +113,7 @@ int orc_cholesky(int64_t q, const double *A, double *L) {
         if (!(d > 0.0)) return ORC_NOTPD;
         double ljj = sqrt(d);
         L[IDX(j, j, q)] = ljj;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if ((q - j) * j > OMP_MIN_WORK / 16)
         for (int64_t i = j + 1; i < q; ++i) {
             double s = A[IDX(i, j, q)];
             for (int64_t k = 0; k < j; ++k) s -= L[IDX(i, k, q)] * L[IDX(j, k, q)];
@@ -123,7 +126,7 @@ int orc_cholesky(int64_t q, const double *A, double *L) {
 void orc_inverse_from_cholesky(int64_t q, const double *L, double *Sigma) {
     /* W = L^{-1} by forward substitution on the identity, then Sigma = W^T W. */
     double *W = zalloc((size_t)(q * q));
-#pragma omp parallel for schedule(dynamic, 8)
+#pragma omp parallel for schedule(dynamic, 8) if (q * q * q > OMP_MIN_WORK)
     for (int64_t c = 0; c < q; ++c) {          /* column c of W solves L w = e_c */
         for (int64_t i = c; i < q; ++i) {
             double s = (i == c) ? 1.0 : 0.0;

@@ -1,0 +1,232 @@
+"""Python binding of the gfx950 alternating Newton CD solver for l1-regularized CGGMs.
+
+Argument marshalling only: every arithmetic step runs in the HIP kernels of
+``libcggm.so`` (built from ``csrc/`` by ``build.py``).  PyTorch provides device
+memory and the stream.  There is no CPU fallback: importing works without the
+library, but every call raises if ``libcggm.so`` is missing.
+
+Entry points mirror ``include/cggm.h``: :func:`cggm_solve`,
+:func:`cggm_objective`, :func:`cggm_gradient` (plus ``cggm_status_string``).
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcggm.so")
+
+CGGM_OK, CGGM_MAXITER = 0, 1
+CGGM_EINVAL, CGGM_ENOTPD, CGGM_ELINESEARCH, CGGM_ENOMEM, CGGM_EHIP = -1, -2, -3, -4, -5
+CGGM_SWEEP_TILED, CGGM_SWEEP_SEQUENTIAL = 0, 1
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_i64 = ctypes.c_int64
+_vp = ctypes.c_void_p
+
+
+class TraceEntry(ctypes.Structure):
+    _fields_ = [("iter", ctypes.c_int), ("ls_trials", ctypes.c_int),
+                ("sweep_fallbacks", ctypes.c_int), ("_pad", ctypes.c_int),
+                ("f", ctypes.c_double), ("subgrad_l1", ctypes.c_double),
+                ("l1", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("m_Lambda", ctypes.c_int64), ("m_Theta", ctypes.c_int64),
+                ("nnz_Lambda", ctypes.c_int64), ("nnz_Theta", ctypes.c_int64),
+                ("t_end_ms", ctypes.c_double), ("ms_gradient", ctypes.c_double),
+                ("ms_lambda_cd", ctypes.c_double), ("ms_line_search", ctypes.c_double),
+                ("ms_theta_cd", ctypes.c_double)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int), ("max_ls", ctypes.c_int),
+                ("ls_beta", ctypes.c_double), ("ls_sigma", ctypes.c_double),
+                ("stall_iters", ctypes.c_int), ("sweep", ctypes.c_int),
+                ("tile", ctypes.c_int), ("_pad", ctypes.c_int),
+                ("workspace_budget", ctypes.c_size_t),
+                ("warm_Lambda", _vp), ("warm_Theta", _vp),
+                ("trace", ctypes.POINTER(TraceEntry)), ("trace_cap", ctypes.c_int),
+                ("trace_len", ctypes.c_int)]
+
+
+class CggmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return LIB_PATH
+
+
+def load() -> ctypes.CDLL:
+    """Load libcggm.so; raises when it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run paper_1509_04681_amd/build.py "
+                          "(or __graft_entry__.build()) first")
+    lib = ctypes.CDLL(LIB_PATH)
+    lib.cggm_default_options.argtypes = [ctypes.POINTER(Options)]
+    lib.cggm_default_options.restype = None
+    lib.cggm_solve_workspace_bytes.argtypes = [_i64, _i64, _i64]
+    lib.cggm_solve_workspace_bytes.restype = ctypes.c_size_t
+    lib.cggm_solve.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_double, ctypes.POINTER(Options), ctypes.POINTER(_vp), _vp]
+    lib.cggm_solve.restype = ctypes.c_int
+    lib.cggm_result_info.argtypes = [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
+                                     ctypes.POINTER(ctypes.c_int), _dp,
+                                     ctypes.POINTER(ctypes.c_int)]
+    lib.cggm_result_info.restype = ctypes.c_int
+    lib.cggm_result_copy.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int]
+    lib.cggm_result_copy.restype = ctypes.c_int
+    lib.cggm_result_dense.argtypes = [_vp, _vp, _vp, ctypes.c_int]
+    lib.cggm_result_dense.restype = ctypes.c_int
+    lib.cggm_result_free.argtypes = [_vp]
+    lib.cggm_result_free.restype = None
+    lib.cggm_objective.argtypes = [_vp, _vp, _i64, _i64, _i64, _vp, _vp, ctypes.c_double,
+                                   ctypes.c_double, _dp, _vp]
+    lib.cggm_objective.restype = ctypes.c_int
+    lib.cggm_gradient.argtypes = [_vp, _vp, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _vp]
+    lib.cggm_gradient.restype = ctypes.c_int
+    lib.cggm_status_string.argtypes = [ctypes.c_int]
+    lib.cggm_status_string.restype = ctypes.c_char_p
+    lib.cggm_last_error.argtypes = []
+    lib.cggm_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def cggm_status_string(code: int) -> str:
+    return load().cggm_status_string(code).decode()
+
+
+def _check(code: int, allow_warning: bool = True) -> int:
+    if code < 0 or (code > 0 and not allow_warning):
+        lib = load()
+        raise CggmError(code, f"{lib.cggm_status_string(code).decode()}: "
+                              f"{lib.cggm_last_error().decode()}")
+    return code
+
+
+def _dev(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a torch tensor on a GPU device")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous (row-major)")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+@dataclasses.dataclass
+class SolveResult:
+    Lambda: "torch.Tensor"        # dense q x q (device)
+    Theta: "torch.Tensor"         # dense p x q (device)
+    f: float
+    iters: int
+    status: int
+    nnz_Lambda: int
+    nnz_Theta: int
+    trace: list
+    # host CSR ((rowptr, col, val) of Lambda (full symmetric), same of Theta)
+    # when cggm_solve(..., keep_csr=True)
+    csr: tuple | None = None
+
+
+def cggm_solve(X, Y, lam_Lambda: float, lam_Theta: float, tol: float = 1e-2, *,
+               max_iter: int = 500, max_ls: int = 30, ls_beta: float = 0.5,
+               ls_sigma: float = 1e-3, stall_iters: int = 3, sweep: int = CGGM_SWEEP_TILED,
+               tile: int = 0, workspace_budget: int = 0, warm_Lambda=None, warm_Theta=None,
+               trace_cap: int | None = None, keep_csr: bool = False, stream=None) -> SolveResult:
+    """Alternating Newton CD (Algorithm 1) on device X (n x p) and Y (n x q), float64."""
+    import torch
+    lib = load()
+    n, p = X.shape
+    q = Y.shape[1]
+    opt = Options()
+    lib.cggm_default_options(ctypes.byref(opt))
+    opt.max_iter, opt.max_ls, opt.ls_beta, opt.ls_sigma = max_iter, max_ls, ls_beta, ls_sigma
+    opt.stall_iters, opt.sweep, opt.tile = stall_iters, sweep, tile
+    opt.workspace_budget = workspace_budget
+    if warm_Lambda is not None:
+        opt.warm_Lambda = _dev(warm_Lambda, "warm_Lambda").value
+    if warm_Theta is not None:
+        opt.warm_Theta = _dev(warm_Theta, "warm_Theta").value
+    cap = (max_iter + 1) if trace_cap is None else trace_cap
+    trace_buf = (TraceEntry * max(cap, 1))()
+    opt.trace = ctypes.cast(trace_buf, ctypes.POINTER(TraceEntry)) if cap > 0 else None
+    opt.trace_cap = cap
+    res = ctypes.c_void_p()
+    code = lib.cggm_solve(_dev(X, "X"), _dev(Y, "Y"), n, p, q, float(lam_Lambda),
+                          float(lam_Theta), float(tol), ctypes.byref(opt), ctypes.byref(res),
+                          _stream(stream))
+    if not (code == CGGM_ELINESEARCH and res.value):    # that status still returns a result
+        _check(code)
+    try:
+        nL, nT, it, f, st = _i64(), _i64(), ctypes.c_int(), ctypes.c_double(), ctypes.c_int()
+        _check(lib.cggm_result_info(res, ctypes.byref(nL), ctypes.byref(nT), ctypes.byref(it),
+                                    ctypes.byref(f), ctypes.byref(st)))
+        Lam = torch.empty((q, q), dtype=torch.float64, device=X.device)
+        Th = torch.empty((p, q), dtype=torch.float64, device=X.device)
+        _check(lib.cggm_result_dense(res, ctypes.c_void_p(Lam.data_ptr()),
+                                     ctypes.c_void_p(Th.data_ptr()), 0))
+        csr = None
+        if keep_csr:
+            Lr, Lc, Lv = (np.empty(q + 1, np.int64), np.empty(max(nL.value, 1), np.int32),
+                          np.empty(max(nL.value, 1), np.float64))
+            Tr, Tc, Tv = (np.empty(p + 1, np.int64), np.empty(max(nT.value, 1), np.int32),
+                          np.empty(max(nT.value, 1), np.float64))
+            _check(lib.cggm_result_copy(res, *(ctypes.c_void_p(a.ctypes.data)
+                                               for a in (Lr, Lc, Lv, Tr, Tc, Tv)), 1))
+            csr = ((Lr, Lc[:nL.value], Lv[:nL.value]), (Tr, Tc[:nT.value], Tv[:nT.value]))
+    finally:
+        lib.cggm_result_free(res)
+    trace = [{k: getattr(trace_buf[i], k) for k, _ in TraceEntry._fields_ if k != "_pad"}
+             for i in range(opt.trace_len)]
+    return SolveResult(Lambda=Lam, Theta=Th, f=f.value, iters=it.value, status=st.value,
+                       nnz_Lambda=nL.value, nnz_Theta=nT.value, trace=trace, csr=csr)
+
+
+def cggm_objective(X, Y, Lambda, Theta, lam_Lambda: float, lam_Theta: float,
+                   stream=None) -> float:
+    """f(Lambda, Theta) of Eq. (1); raises CggmError(CGGM_ENOTPD) when Lambda is not PD."""
+    lib = load()
+    n, p = X.shape
+    q = Y.shape[1]
+    f = ctypes.c_double()
+    _check(lib.cggm_objective(_dev(X, "X"), _dev(Y, "Y"), n, p, q, _dev(Lambda, "Lambda"),
+                              _dev(Theta, "Theta"), float(lam_Lambda), float(lam_Theta),
+                              ctypes.byref(f), _stream(stream)))
+    return f.value
+
+
+def cggm_gradient(X, Y, Lambda, Theta, stream=None):
+    """(G_Lambda, G_Theta) of Eq. (3) as new device tensors."""
+    import torch
+    lib = load()
+    n, p = X.shape
+    q = Y.shape[1]
+    GL = torch.empty((q, q), dtype=torch.float64, device=X.device)
+    GT = torch.empty((p, q), dtype=torch.float64, device=X.device)
+    _check(lib.cggm_gradient(_dev(X, "X"), _dev(Y, "Y"), n, p, q, _dev(Lambda, "Lambda"),
+                             _dev(Theta, "Theta"), _dev(GL, "G_Lambda"), _dev(GT, "G_Theta"),
+                             _stream(stream)))
+    return GL, GT
+
+
+def cggm_solve_workspace_bytes(n: int, p: int, q: int) -> int:
+    return int(load().cggm_solve_workspace_bytes(n, p, q))

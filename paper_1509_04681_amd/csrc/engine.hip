@@ -1,0 +1,936 @@
+// engine.hip -- host engine and C ABI of the gfx950 alternating Newton
+// coordinate descent solver (McCarter & Kim, AISTATS 2016, Algorithm 1).
+//
+// Control stays on the host; every arithmetic step runs in the kernels of
+// la.hip and cd.hip on the caller's stream.  The host reads back only scalars:
+// the top-of-iteration statistics, the line-search quantities of each trial.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <memory>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "device_common.hpp"
+#include "internal.hpp"
+
+namespace cggm {
+namespace {
+
+thread_local std::string g_last_error;
+
+// ----------------------------------------------------------- kernels ---------
+__global__ void fill_kernel(int64_t count, double v, double *x) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < count) x[e] = v;
+}
+
+__global__ void add_kernel(int64_t count, const double *a, double *b) {   // b += a
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < count) b[e] += a[e];
+}
+
+// Nonzeros per row of a dense rows x cols matrix (one workgroup per row).
+__global__ __launch_bounds__(BLOCK) void row_nnz_kernel(int64_t cols, const double *A,
+                                                        int64_t *counts) {
+    const int64_t r = blockIdx.x;
+    int64_t c = 0;
+    for (int64_t j = threadIdx.x; j < cols; j += BLOCK) c += (A[r * cols + j] != 0.0);
+    __shared__ int64_t red[BLOCK];
+    red[threadIdx.x] = c;
+    __syncthreads();
+    for (int s = BLOCK / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) counts[r] = red[0];
+}
+
+// CSR fill: one workgroup per row; chunks of BLOCK columns keep column order.
+__global__ __launch_bounds__(BLOCK) void csr_fill_kernel(int64_t cols, const double *A,
+                                                         const int64_t *rowptr, int32_t *col,
+                                                         double *val) {
+    const int64_t r = blockIdx.x;
+    int64_t base = rowptr[r];
+    __shared__ int scan[BLOCK];
+    for (int64_t j0 = 0; j0 < cols; j0 += BLOCK) {
+        const int64_t j = j0 + threadIdx.x;
+        const double v = (j < cols) ? A[r * cols + j] : 0.0;
+        const int nz = (j < cols && v != 0.0) ? 1 : 0;
+        scan[threadIdx.x] = nz;
+        __syncthreads();
+        for (int s = 1; s < BLOCK; s <<= 1) {          // inclusive Hillis-Steele scan
+            const int add = ((int)threadIdx.x >= s) ? scan[threadIdx.x - s] : 0;
+            __syncthreads();
+            scan[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (nz) {
+            const int64_t pos = base + scan[threadIdx.x] - 1;
+            col[pos] = (int32_t)j;
+            val[pos] = v;
+        }
+        const int total = scan[BLOCK - 1];
+        __syncthreads();
+        base += total;
+    }
+}
+
+inline int nblk(int64_t count) { return (int)std::max<int64_t>(1, (count + BLOCK - 1) / BLOCK); }
+
+void fill(hipStream_t s, int64_t count, double v, double *x) {
+    fill_kernel<<<nblk(count), BLOCK, 0, s>>>(count, v, x);
+    CGGM_LAUNCH_CHECK();
+}
+
+// ----------------------------------------------------------- device arena ----
+struct Arena {
+    char *base = nullptr;
+    size_t used = 0, cap = 0;
+    bool measure = false;
+    template <class Tp>
+    Tp *take(int64_t count) {
+        const size_t bytes = ((size_t)std::max<int64_t>(count, 1) * sizeof(Tp) + 255) & ~size_t(255);
+        Tp *p = measure ? nullptr : reinterpret_cast<Tp *>(base + used);
+        used += bytes;
+        return p;
+    }
+};
+
+struct DeviceBuffer {
+    void *p = nullptr;
+    ~DeviceBuffer() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+// Wave schedules of the coordinate-descent sweeps (host lists of rects with
+// offsets of each wave; uploaded once per solve).
+struct Schedule {
+    std::vector<TileRect> rects;
+    std::vector<int> wave_start;   // wave w = rects[wave_start[w], wave_start[w+1])
+    int max_wave = 0;
+    int waves() const { return (int)wave_start.size() - 1; }
+    void finish_wave() {
+        const int prev = wave_start.empty() ? 0 : wave_start.back();
+        max_wave = std::max(max_wave, (int)rects.size() - prev);
+        wave_start.push_back((int)rects.size());
+    }
+};
+
+TileRect rect(int64_t r0, int64_t r1, int64_t c0, int64_t c1) {
+    return TileRect{(int32_t)r0, (int32_t)r1, (int32_t)c0, (int32_t)c1};
+}
+
+// Theta: tile (I, J) belongs to wave (J - I) mod W, W = max(#row blocks,
+// #column blocks); each wave is row- and column-disjoint.
+Schedule theta_schedule(int64_t p, int64_t q, int tile, bool sequential) {
+    Schedule s;
+    s.wave_start.push_back(0);
+    if (sequential) {
+        for (int64_t i = 0; i < p; ++i)
+            for (int64_t j = 0; j < q; ++j) {
+                s.rects.push_back(rect(i, i + 1, j, j + 1));
+                s.finish_wave();
+            }
+        return s;
+    }
+    const int64_t P = (p + tile - 1) / tile, Q = (q + tile - 1) / tile, W = std::max(P, Q);
+    for (int64_t w = 0; w < W; ++w) {
+        for (int64_t I = 0; I < P; ++I) {
+            const int64_t J = (I + w) % W;
+            if (J >= Q) continue;
+            s.rects.push_back(rect(I * tile, std::min(p, (I + 1) * tile), J * tile,
+                                   std::min(q, (J + 1) * tile)));
+        }
+        s.finish_wave();
+    }
+    return s;
+}
+
+// Lambda: first the wave of all diagonal tiles, then the rounds of a
+// round-robin pairing of the column blocks (each block once per round).
+Schedule lambda_schedule(int64_t q, int tile, bool sequential) {
+    Schedule s;
+    s.wave_start.push_back(0);
+    if (sequential) {
+        for (int64_t i = 0; i < q; ++i)
+            for (int64_t j = i; j < q; ++j) {
+                s.rects.push_back(rect(i, i + 1, j, j + 1));
+                s.finish_wave();
+            }
+        return s;
+    }
+    const int64_t Q = (q + tile - 1) / tile;
+    auto blk = [&](int64_t I, int64_t J) {
+        return rect(I * tile, std::min(q, (I + 1) * tile), J * tile, std::min(q, (J + 1) * tile));
+    };
+    for (int64_t I = 0; I < Q; ++I) s.rects.push_back(blk(I, I));
+    s.finish_wave();
+    const int64_t n = Q + (Q & 1);             // even number of slots (one bye if Q odd)
+    for (int64_t r = 0; r + 1 < n; ++r) {
+        std::vector<std::pair<int64_t, int64_t>> pairs;
+        pairs.push_back({r, n - 1});
+        for (int64_t k = 1; k < n / 2; ++k)
+            pairs.push_back({(r + k) % (n - 1), (r - k + (n - 1)) % (n - 1)});
+        bool any = false;
+        for (auto [a, b] : pairs) {
+            if (a >= Q || b >= Q) continue;     // bye
+            const int64_t I = std::min(a, b), J = std::max(a, b);
+            s.rects.push_back(blk(I, J));
+            any = true;
+        }
+        if (any) s.finish_wave();
+    }
+    return s;
+}
+
+// --------------------------------------------------------------- workspace ---
+struct Work {
+    int64_t n = 0, p = 0, q = 0;
+    double *Sxx, *Sxy, *Syy;                       // statistics
+    double *Lam, *LamT, *L, *Lt, *Sig, *Psi, *SP, *GL, *D, *U;   // q x q
+    double *Th, *ThOld, *GT, *V;                   // p x q
+    double *A, *R, *At, *Zt;                       // n x q, q x n
+    double *dT, *dD;                               // per-wave tile deltas
+    double *partials, *scal;                       // reduction scratch, device scalars
+    int *flag, *changed;
+    TileRect *rects_theta, *rects_lambda;
+    int max_tiles = 0;
+};
+
+constexpr int NSCAL = 64;
+
+// Layout of the workspace; with a.measure it only sizes it.
+void layout(Arena &a, Work &w, int64_t n, int64_t p, int64_t q, int64_t ntheta_rects,
+            int64_t nlambda_rects, int max_tiles) {
+    const int64_t qq = q * q, pq = p * q, nq = n * q;
+    w.n = n, w.p = p, w.q = q;
+    w.Sxx = a.take<double>(p * p);
+    w.Sxy = a.take<double>(pq);
+    w.Syy = a.take<double>(qq);
+    w.Lam = a.take<double>(qq);
+    w.LamT = a.take<double>(qq);
+    w.L = a.take<double>(qq);
+    w.Lt = a.take<double>(qq);
+    w.Sig = a.take<double>(qq);
+    w.Psi = a.take<double>(qq);
+    w.SP = a.take<double>(qq);
+    w.GL = a.take<double>(qq);
+    w.D = a.take<double>(qq);
+    w.U = a.take<double>(qq);
+    w.Th = a.take<double>(pq);
+    w.ThOld = a.take<double>(pq);
+    w.GT = a.take<double>(pq);
+    w.V = a.take<double>(pq);
+    w.A = a.take<double>(nq);
+    w.R = a.take<double>(nq);
+    w.At = a.take<double>(nq);
+    w.Zt = a.take<double>(nq);
+    w.max_tiles = max_tiles;
+    w.dT = a.take<double>((int64_t)max_tiles * CD_TILE * CD_TILE);
+    w.dD = a.take<double>((int64_t)max_tiles * CD_TILE * CD_TILE);
+    w.partials = a.take<double>(REDUCE_BLOCKS * 8);
+    w.scal = a.take<double>(NSCAL);
+    w.flag = a.take<int>(4);
+    w.changed = a.take<int>(max_tiles);
+    w.rects_theta = a.take<TileRect>(ntheta_rects);
+    w.rects_lambda = a.take<TileRect>(nlambda_rects);
+}
+
+// Scalars read back at the top of an iteration (offsets into Work::scal).
+enum {
+    S_LAM = 0,       // 5: tr(Syy Lam), |Lam|_1, subgrad, m, nnz
+    S_THETA = 5,     // 5: <Sxy, Theta>, |Theta|_1, subgrad, m, nnz
+    S_AR = 10,       // <A, R>
+    S_LOGDET = 11,   // 2: logdet, bad
+    S_DIR = 13,      // 2: <G, D>, sum |Lam + D| - |Lam|
+    S_TRIAL = 15,    // 2: tr(Syy T), |T|_1
+    S_TLOGDET = 17,  // 2
+    S_ZZ = 19,       // |L^{-1} A^T|_F^2
+    S_NONFIN = 20,   // 2: non-finite counts of X and Y
+};
+
+struct Ctx {
+    hipStream_t s;
+    Work &w;
+    double lamL, lamT;
+};
+
+// Rounding allowance of an FP64 objective evaluation in the Armijo test and
+// the Theta descent guard.
+constexpr double F_ROUNDING = 1e-14;
+
+// Sxx = X^T X / n, Sxy = X^T Y / n, Syy = Y^T Y / n (uncentred, Sec. 2.1).
+void statistics(Ctx &c, const double *X, const double *Y) {
+    Work &w = c.w;
+    const double inv_n = 1.0 / (double)w.n;
+    gemm(c.s, true, false, w.p, w.p, w.n, inv_n, X, w.p, X, w.p, 0.0, w.Sxx, w.p, UPLO_LOWER);
+    symmetrize_from_lower(c.s, w.p, w.Sxx);
+    gemm(c.s, true, false, w.p, w.q, w.n, inv_n, X, w.p, Y, w.q, 0.0, w.Sxy, w.q);
+    gemm(c.s, true, false, w.q, w.q, w.n, inv_n, Y, w.q, Y, w.q, 0.0, w.Syy, w.q, UPLO_LOWER);
+    symmetrize_from_lower(c.s, w.q, w.Syy);
+}
+
+// A = X Theta, R = A Sigma; reductions <A, R>, <Sxy, Theta>-block stats use them.
+void theta_products(Ctx &c, const double *X) {
+    Work &w = c.w;
+    gemm(c.s, false, false, w.n, w.q, w.p, 1.0, X, w.p, w.Th, w.q, 0.0, w.A, w.q);
+    gemm(c.s, false, false, w.n, w.q, w.q, 1.0, w.A, w.q, w.Sig, w.q, 0.0, w.R, w.q);
+}
+
+// Psi = R^T R / n, G_Lambda = Syy - Sigma - Psi, SP = Sigma + Psi,
+// G_Theta = 2 Sxy + (2/n) X^T R  (= 2 Sxy + 2 Sxx Theta Sigma), Eq. (3).
+void gradients(Ctx &c, const double *X) {
+    Work &w = c.w;
+    const double inv_n = 1.0 / (double)w.n;
+    gemm(c.s, true, false, w.q, w.q, w.n, inv_n, w.R, w.q, w.R, w.q, 0.0, w.Psi, w.q,
+         UPLO_LOWER);
+    symmetrize_from_lower(c.s, w.q, w.Psi);
+    assemble_lambda_gradient(c.s, w.q, w.Syy, w.Sig, w.Psi, w.GL, w.SP);
+    scale_copy(c.s, w.p * w.q, 2.0, w.Sxy, w.GT);
+    gemm(c.s, true, false, w.p, w.q, w.n, 2.0 * inv_n, X, w.p, w.R, w.q, 1.0, w.GT, w.q);
+}
+
+struct TopStats {
+    double f, subgrad, l1, trS, sxyT, l1L, l1T, ar, logdet;
+    int64_t mL, mT, nnzL, nnzT;
+};
+
+// Objective and the Theta-side scalars after A, R are current (Lambda side
+// taken from stats already on the device).
+TopStats read_top(Ctx &c, bool with_gradient_stats) {
+    Work &w = c.w;
+    double h[NSCAL];
+    CGGM_HIP(hipMemcpyAsync(h, w.scal, sizeof(h), hipMemcpyDeviceToHost, c.s));
+    CGGM_HIP(hipStreamSynchronize(c.s));
+    TopStats t{};
+    t.trS = h[S_LAM + 0];
+    t.l1L = h[S_LAM + 1];
+    t.sxyT = h[S_THETA + 0];
+    t.l1T = h[S_THETA + 1];
+    t.ar = h[S_AR];
+    t.logdet = h[S_LOGDET];
+    t.f = -t.logdet + t.trS + 2.0 * t.sxyT + t.ar / (double)w.n + c.lamL * t.l1L +
+          c.lamT * t.l1T;
+    if (with_gradient_stats) {
+        t.subgrad = h[S_LAM + 2] + h[S_THETA + 2];
+        t.mL = (int64_t)h[S_LAM + 3];
+        t.mT = (int64_t)h[S_THETA + 3];
+        t.nnzL = (int64_t)h[S_LAM + 4];
+        t.nnzT = (int64_t)h[S_THETA + 4];
+    }
+    t.l1 = t.l1L + t.l1T;
+    return t;
+}
+
+void run_theta_sweep(Ctx &c, const Schedule &sch) {
+    Work &w = c.w;
+    for (int k = 0; k < sch.waves(); ++k) {
+        const int b = sch.wave_start[k], e = sch.wave_start[k + 1];
+        theta_wave(c.s, w.rects_theta + b, e - b, w.p, w.q, w.Sxx, w.Sxy, w.Sig, w.V, w.GT,
+                   w.Th, c.lamT, w.dT, w.changed);
+    }
+}
+
+void run_lambda_sweep(Ctx &c, const Schedule &sch) {
+    Work &w = c.w;
+    fill(c.s, w.q * w.q, 0.0, w.D);
+    fill(c.s, w.q * w.q, 0.0, w.U);
+    for (int k = 0; k < sch.waves(); ++k) {
+        const int b = sch.wave_start[k], e = sch.wave_start[k + 1];
+        lambda_wave(c.s, w.rects_lambda + b, e - b, w.q, w.Sig, w.Psi, w.SP, w.GL, w.Lam,
+                    c.lamL, w.D, w.U, w.dD, w.changed);
+    }
+}
+
+struct ResultImpl {
+    int64_t p = 0, q = 0, nnzL = 0, nnzT = 0;
+    int iters = 0, status = 0;
+    double f = 0.0;
+    double *Lam = nullptr, *Th = nullptr;          // dense, device
+    int64_t *L_rowptr = nullptr, *T_rowptr = nullptr;
+    int32_t *L_col = nullptr, *T_col = nullptr;
+    double *L_val = nullptr, *T_val = nullptr;
+    ~ResultImpl() {
+        for (void *ptr : {(void *)Lam, (void *)Th, (void *)L_rowptr, (void *)T_rowptr,
+                          (void *)L_col, (void *)T_col, (void *)L_val, (void *)T_val})
+            if (ptr) (void)hipFree(ptr);
+    }
+};
+
+void to_csr(hipStream_t s, int64_t rows, int64_t cols, const double *A, int64_t **rowptr,
+            int32_t **col, double **val, int64_t *nnz) {
+    CGGM_HIP(hipMalloc(rowptr, sizeof(int64_t) * (rows + 1)));
+    std::vector<int64_t> counts(rows), ptr(rows + 1, 0);
+    row_nnz_kernel<<<(unsigned)rows, BLOCK, 0, s>>>(cols, A, *rowptr);
+    CGGM_LAUNCH_CHECK();
+    CGGM_HIP(hipMemcpyAsync(counts.data(), *rowptr, sizeof(int64_t) * rows, hipMemcpyDeviceToHost,
+                            s));
+    CGGM_HIP(hipStreamSynchronize(s));
+    for (int64_t r = 0; r < rows; ++r) ptr[r + 1] = ptr[r] + counts[r];
+    *nnz = ptr[rows];
+    CGGM_HIP(hipMemcpyAsync(*rowptr, ptr.data(), sizeof(int64_t) * (rows + 1),
+                            hipMemcpyHostToDevice, s));
+    CGGM_HIP(hipMalloc(col, sizeof(int32_t) * std::max<int64_t>(*nnz, 1)));
+    CGGM_HIP(hipMalloc(val, sizeof(double) * std::max<int64_t>(*nnz, 1)));
+    csr_fill_kernel<<<(unsigned)rows, BLOCK, 0, s>>>(cols, A, *rowptr, *col, *val);
+    CGGM_LAUNCH_CHECK();
+    CGGM_HIP(hipStreamSynchronize(s));
+}
+
+void check_sizes(int64_t n, int64_t p, int64_t q) {
+    if (n < 1 || p < 1 || q < 1) fail(CGGM_EINVAL, "n, p and q must be >= 1");
+    if (p > INT32_MAX || q > INT32_MAX) fail(CGGM_EINVAL, "p and q must fit in int32");
+}
+
+void check_lambda(double lamL, double lamT) {
+    if (!(lamL >= 0.0) || !(lamT >= 0.0) || !isfinite(lamL) || !isfinite(lamT))
+        fail(CGGM_EINVAL, "penalties must be finite and >= 0");
+}
+
+// Non-finite entries of X and Y -> CGGM_EINVAL.
+void check_finite(Ctx &c, const double *X, const double *Y) {
+    Work &w = c.w;
+    reduce_nonfinite(c.s, w.n * w.p, X, w.partials, w.scal + S_NONFIN);
+    reduce_nonfinite(c.s, w.n * w.q, Y, w.partials, w.scal + S_NONFIN + 1);
+    double h[2];
+    CGGM_HIP(hipMemcpyAsync(h, w.scal + S_NONFIN, sizeof(h), hipMemcpyDeviceToHost, c.s));
+    CGGM_HIP(hipStreamSynchronize(c.s));
+    if (h[0] != 0.0 || h[1] != 0.0) fail(CGGM_EINVAL, "X or Y has non-finite entries");
+}
+
+int64_t default_tile(int tile) {
+    if (tile <= 0) return CD_TILE;
+    if (tile > CD_TILE) fail(CGGM_EINVAL, "tile must be <= 32");
+    return tile;
+}
+
+// ------------------------------------------------------------------ solve ----
+int solve_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q, double lamL,
+               double lamT, double tol, cggm_options *opt_in, cggm_result **out,
+               hipStream_t s) {
+    if (!X || !Y || !out) fail(CGGM_EINVAL, "NULL pointer argument");
+    check_sizes(n, p, q);
+    check_lambda(lamL, lamT);
+    if (!(tol >= 0.0) || !isfinite(tol)) fail(CGGM_EINVAL, "tol must be finite and >= 0");
+    cggm_options opt;
+    cggm_default_options(&opt);
+    if (opt_in) opt = *opt_in;
+    if (opt.max_iter < 0 || opt.max_ls < 1 || !(opt.ls_beta > 0.0 && opt.ls_beta < 1.0) ||
+        !(opt.ls_sigma > 0.0 && opt.ls_sigma < 1.0) || opt.stall_iters < 0 ||
+        (opt.sweep != CGGM_SWEEP_TILED && opt.sweep != CGGM_SWEEP_SEQUENTIAL))
+        fail(CGGM_EINVAL, "invalid options");
+    const int64_t tile = default_tile(opt.tile);
+    const bool seq = opt.sweep == CGGM_SWEEP_SEQUENTIAL;
+    const Schedule th_sched = theta_schedule(p, q, (int)tile, seq);
+    const Schedule la_sched = lambda_schedule(q, (int)tile, seq);
+    // Tile-sequential fallbacks of the descent guard: one tile per wave.
+    Schedule th_safe, la_safe;
+    th_safe.wave_start.push_back(0);
+    for (const TileRect &r : th_sched.rects) {
+        th_safe.rects.push_back(r);
+        th_safe.finish_wave();
+    }
+    la_safe.wave_start.push_back(0);
+    for (const TileRect &r : la_sched.rects) {
+        la_safe.rects.push_back(r);
+        la_safe.finish_wave();
+    }
+    const int max_tiles = std::max(1, std::max(th_sched.max_wave, la_sched.max_wave));
+
+    Arena sizer;
+    sizer.measure = true;
+    Work w;
+    layout(sizer, w, n, p, q, (int64_t)th_sched.rects.size(), (int64_t)la_sched.rects.size(),
+           max_tiles);
+    if (opt.workspace_budget && sizer.used > opt.workspace_budget)
+        fail(CGGM_ENOMEM, "workspace of " + std::to_string(sizer.used) +
+                              " bytes exceeds the budget of " +
+                              std::to_string(opt.workspace_budget));
+    DeviceBuffer buf;
+    if (hipMalloc(&buf.p, sizer.used) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(CGGM_ENOMEM, "hipMalloc of " + std::to_string(sizer.used) + " bytes failed");
+    }
+    Arena arena;
+    arena.base = (char *)buf.p;
+    layout(arena, w, n, p, q, (int64_t)th_sched.rects.size(), (int64_t)la_sched.rects.size(),
+           max_tiles);
+    CGGM_HIP(hipMemcpyAsync(w.rects_theta, th_sched.rects.data(),
+                            sizeof(TileRect) * th_sched.rects.size(), hipMemcpyHostToDevice, s));
+    CGGM_HIP(hipMemcpyAsync(w.rects_lambda, la_sched.rects.data(),
+                            sizeof(TileRect) * la_sched.rects.size(), hipMemcpyHostToDevice, s));
+    Ctx c{s, w, lamL, lamT};
+    const int64_t qq = q * q, pq = p * q;
+    check_finite(c, X, Y);
+
+    auto t0 = std::chrono::steady_clock::now();
+    auto ms_since = [&](std::chrono::steady_clock::time_point a) {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - a)
+            .count();
+    };
+
+    statistics(c, X, Y);
+    // Algorithm 1: Theta = 0, Lambda = I (or the warm start).
+    if (opt.warm_Lambda) {
+        CGGM_HIP(hipMemcpyAsync(w.Lam, opt.warm_Lambda, sizeof(double) * qq,
+                                hipMemcpyDeviceToDevice, s));
+    } else {
+        set_identity(s, q, w.Lam);
+    }
+    if (opt.warm_Theta) {
+        CGGM_HIP(hipMemcpyAsync(w.Th, opt.warm_Theta, sizeof(double) * pq,
+                                hipMemcpyDeviceToDevice, s));
+    } else {
+        fill(s, pq, 0.0, w.Th);
+    }
+    CGGM_HIP(hipMemcpyAsync(w.L, w.Lam, sizeof(double) * qq, hipMemcpyDeviceToDevice, s));
+    set_int(s, w.flag, 0);
+    cholesky_inplace(s, q, w.L, w.flag);
+    reduce_logdet(s, q, w.L, w.partials, w.scal + S_LOGDET);
+    int hflag = 0;
+    CGGM_HIP(hipMemcpyAsync(&hflag, w.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    CGGM_HIP(hipStreamSynchronize(s));
+    if (hflag) fail(CGGM_ENOTPD, "the warm-start Lambda is not positive definite");
+    spd_inverse_from_cholesky(s, q, w.L, w.U, w.Sig);
+    theta_products(c, X);
+
+    hipEvent_t ev[5];
+    for (auto &e : ev) CGGM_HIP(hipEventCreate(&e));
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard() {
+            for (int k = 0; k < 5; ++k) (void)hipEventDestroy(e[k]);
+        }
+    } evg{ev};
+
+    int status = CGGM_MAXITER, stalled = 0, t = 0, ls_fail_streak = 0;
+    double sg_best = INFINITY, f_prev = INFINITY, f_after_ls = INFINITY;
+    bool have_phase = false;
+    int trace_len = 0, last_trials = 0, last_fallbacks = 0;
+    double last_alpha = 0.0;
+    TopStats top{};
+    for (t = 0;; ++t) {
+        CGGM_HIP(hipEventRecord(ev[0], s));
+        // ---- top of the iteration: objective (A, R already current) --------
+        reduce_dot(s, w.n * q, w.A, w.R, w.partials, w.scal + S_AR);
+        reduce_top_stats(s, p, q, w.Sxy, w.Sxy, w.Th, lamT, 0, w.partials, w.scal + S_THETA);
+        reduce_top_stats(s, q, q, w.Syy, w.Syy, w.Lam, lamL, 1, w.partials, w.scal + S_LAM);
+        reduce_logdet(s, q, w.L, w.partials, w.scal + S_LOGDET);
+        TopStats pre = read_top(c, false);
+        if (t > 0 && pre.f > f_after_ls + F_ROUNDING * std::max(1.0, fabs(f_after_ls))) {
+            // Descent guard: the concurrent tiles of the Theta sweep raised f.
+            // Redo the sweep one tile per wave (exact block Gauss-Seidel).
+            CGGM_HIP(hipMemcpyAsync(w.Th, w.ThOld, sizeof(double) * pq, hipMemcpyDeviceToDevice,
+                                    s));
+            gemm(s, false, false, p, q, q, 1.0, w.Th, q, w.Sig, q, 0.0, w.V, q);
+            run_theta_sweep(c, th_safe);
+            ++last_fallbacks;
+            theta_products(c, X);
+            reduce_dot(s, w.n * q, w.A, w.R, w.partials, w.scal + S_AR);
+            reduce_top_stats(s, p, q, w.Sxy, w.Sxy, w.Th, lamT, 0, w.partials,
+                             w.scal + S_THETA);
+        }
+        gradients(c, X);
+        reduce_top_stats(s, p, q, w.Sxy, w.GT, w.Th, lamT, 0, w.partials, w.scal + S_THETA);
+        reduce_top_stats(s, q, q, w.Syy, w.GL, w.Lam, lamL, 1, w.partials, w.scal + S_LAM);
+        CGGM_HIP(hipEventRecord(ev[1], s));
+        top = read_top(c, true);
+        if (opt.trace && trace_len < opt.trace_cap) {
+            cggm_trace_entry &te = opt.trace[trace_len++];
+            memset(&te, 0, sizeof(te));
+            te.iter = t;
+            te.f = top.f;
+            te.subgrad_l1 = top.subgrad;
+            te.l1 = top.l1;
+            te.m_Lambda = top.mL;
+            te.m_Theta = top.mT;
+            te.nnz_Lambda = top.nnzL;
+            te.nnz_Theta = top.nnzT;
+            te.t_end_ms = ms_since(t0);
+            float ms = 0.f;
+            CGGM_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+            te.ms_gradient = ms;
+            if (t > 0 && trace_len >= 2) {
+                cggm_trace_entry &pv = opt.trace[trace_len - 2];
+                pv.alpha = last_alpha;
+                pv.ls_trials = last_trials;
+                pv.sweep_fallbacks = last_fallbacks;
+                if (have_phase) {
+                    CGGM_HIP(hipEventElapsedTime(&ms, ev[2], ev[3]));
+                    pv.ms_lambda_cd = ms;
+                    CGGM_HIP(hipEventElapsedTime(&ms, ev[3], ev[4]));
+                    pv.ms_line_search = ms;
+                    CGGM_HIP(hipEventElapsedTime(&ms, ev[4], ev[0]));
+                    pv.ms_theta_cd = ms;
+                }
+            }
+        }
+        last_fallbacks = 0;
+        if (top.subgrad < tol * top.l1) {
+            status = CGGM_OK;
+            break;
+        }
+        if (opt.stall_iters > 0) {
+            const bool no_progress = (top.subgrad >= sg_best) &&
+                                     (top.f >= f_prev - 1e-15 * fabs(f_prev));
+            stalled = no_progress ? stalled + 1 : 0;
+            if (stalled >= opt.stall_iters) {
+                status = CGGM_OK;
+                break;
+            }
+        }
+        sg_best = std::min(sg_best, top.subgrad);
+        f_prev = top.f;
+        if (t >= opt.max_iter) {
+            status = CGGM_MAXITER;
+            break;
+        }
+
+        // ---- Lambda: Newton direction by one CD pass, Armijo line search ----
+        CGGM_HIP(hipEventRecord(ev[2], s));
+        run_lambda_sweep(c, la_sched);
+        reduce_direction(s, q, w.GL, w.Lam, w.D, w.partials, w.scal + S_DIR);
+        double hd[2];
+        CGGM_HIP(hipMemcpyAsync(hd, w.scal + S_DIR, sizeof(hd), hipMemcpyDeviceToHost, s));
+        CGGM_HIP(hipStreamSynchronize(s));
+        double delta = hd[0] + lamL * hd[1];
+        if (!(delta < 0.0) && !seq) {
+            // Descent guard: redo the direction one tile per wave.
+            run_lambda_sweep(c, la_safe);
+            ++last_fallbacks;
+            reduce_direction(s, q, w.GL, w.Lam, w.D, w.partials, w.scal + S_DIR);
+            CGGM_HIP(hipMemcpyAsync(hd, w.scal + S_DIR, sizeof(hd), hipMemcpyDeviceToHost, s));
+            CGGM_HIP(hipStreamSynchronize(s));
+            delta = hd[0] + lamL * hd[1];
+        }
+        CGGM_HIP(hipEventRecord(ev[3], s));
+        double alpha = 0.0, f_acc = top.f;
+        int trials = 0;
+        bool accepted = false;
+        if (delta < 0.0) {
+            transpose(s, w.n, q, w.A, w.At);            // A^T, q x n
+            double a = 1.0;
+            for (int k = 0; k < opt.max_ls; ++k, a *= opt.ls_beta) {
+                ++trials;
+                build_trial(s, q, w.Lam, w.D, a, w.Syy, w.LamT, w.partials, w.scal + S_TRIAL);
+                CGGM_HIP(hipMemcpyAsync(w.Lt, w.LamT, sizeof(double) * qq,
+                                        hipMemcpyDeviceToDevice, s));
+                set_int(s, w.flag, 0);
+                cholesky_inplace(s, q, w.Lt, w.flag);
+                reduce_logdet(s, q, w.Lt, w.partials, w.scal + S_TLOGDET);
+                CGGM_HIP(hipMemcpyAsync(w.Zt, w.At, sizeof(double) * w.n * q,
+                                        hipMemcpyDeviceToDevice, s));
+                trsm_lower_left(s, q, w.Lt, w.Zt, w.n, w.n, false);
+                reduce_dot(s, q * w.n, w.Zt, w.Zt, w.partials, w.scal + S_ZZ);
+                double h[6];
+                int hf = 0;
+                CGGM_HIP(hipMemcpyAsync(h, w.scal + S_TRIAL, sizeof(h), hipMemcpyDeviceToHost, s));
+                CGGM_HIP(hipMemcpyAsync(&hf, w.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+                CGGM_HIP(hipStreamSynchronize(s));
+                const double trS = h[0], l1T = h[1], ld = h[2], bad = h[3], zz = h[4];
+                if (hf || bad != 0.0 || !isfinite(zz)) continue;      // not positive definite
+                const double fa = -ld + trS + 2.0 * top.sxyT + zz / (double)w.n + lamL * l1T +
+                                  lamT * top.l1T;
+                if (fa <= top.f + opt.ls_sigma * a * delta +
+                              F_ROUNDING * std::max(1.0, fabs(top.f))) {
+                    alpha = a;
+                    f_acc = fa;
+                    accepted = true;
+                    break;
+                }
+            }
+        }
+        if (accepted) {
+            std::swap(w.Lam, w.LamT);
+            std::swap(w.L, w.Lt);
+            ls_fail_streak = 0;
+        } else if (delta < 0.0) {
+            if (++ls_fail_streak >= 2) {
+                status = CGGM_ELINESEARCH;
+                break;
+            }
+        }
+        f_after_ls = f_acc;
+        last_alpha = alpha;
+        last_trials = trials;
+        spd_inverse_from_cholesky(s, q, w.L, w.U, w.Sig);
+        CGGM_HIP(hipEventRecord(ev[4], s));
+        have_phase = true;
+
+        // ---- Theta: one CD pass on Eq. (7) with Sigma of the new Lambda ----
+        CGGM_HIP(hipMemcpyAsync(w.ThOld, w.Th, sizeof(double) * pq, hipMemcpyDeviceToDevice, s));
+        gemm(s, false, false, p, q, q, 1.0, w.Th, q, w.Sig, q, 0.0, w.V, q);   // V = Theta Sigma
+        run_theta_sweep(c, th_sched);
+        theta_products(c, X);
+    }
+    opt.trace_len = trace_len;
+    if (opt_in) opt_in->trace_len = trace_len;
+
+    auto *res = new ResultImpl();
+    std::unique_ptr<ResultImpl> guard(res);
+    res->p = p;
+    res->q = q;
+    res->iters = t;
+    res->f = top.f;
+    res->status = status;
+    CGGM_HIP(hipMalloc(&res->Lam, sizeof(double) * qq));
+    CGGM_HIP(hipMalloc(&res->Th, sizeof(double) * pq));
+    CGGM_HIP(hipMemcpyAsync(res->Lam, w.Lam, sizeof(double) * qq, hipMemcpyDeviceToDevice, s));
+    CGGM_HIP(hipMemcpyAsync(res->Th, w.Th, sizeof(double) * pq, hipMemcpyDeviceToDevice, s));
+    to_csr(s, q, q, res->Lam, &res->L_rowptr, &res->L_col, &res->L_val, &res->nnzL);
+    to_csr(s, p, q, res->Th, &res->T_rowptr, &res->T_col, &res->T_val, &res->nnzT);
+    *out = reinterpret_cast<cggm_result *>(guard.release());
+    return status;
+}
+
+// ------------------------------------------------------- objective/gradient --
+// Workspace for the standalone evaluations.
+struct EvalWork {
+    double *A, *R, *At, *L, *Sig, *Psi, *Work, *YL, *partials, *scal;
+    int *flag;
+};
+
+void eval_layout(Arena &a, EvalWork &e, int64_t n, int64_t p, int64_t q, bool gradient) {
+    e.A = a.take<double>(n * q);
+    e.R = a.take<double>(n * q);
+    e.At = a.take<double>(n * q);
+    e.L = a.take<double>(q * q);
+    e.Sig = gradient ? a.take<double>(q * q) : nullptr;
+    e.Psi = gradient ? a.take<double>(q * q) : nullptr;
+    e.Work = a.take<double>(q * q);
+    e.YL = a.take<double>(n * q);
+    e.partials = a.take<double>(REDUCE_BLOCKS * 8);
+    e.scal = a.take<double>(NSCAL);
+    e.flag = a.take<int>(4);
+}
+
+int objective_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q,
+                   const double *Lam, const double *Th, double lamL, double lamT, double *f_out,
+                   hipStream_t s) {
+    if (!X || !Y || !Lam || !Th || !f_out) fail(CGGM_EINVAL, "NULL pointer argument");
+    check_sizes(n, p, q);
+    check_lambda(lamL, lamT);
+    Arena sizer;
+    sizer.measure = true;
+    EvalWork e;
+    eval_layout(sizer, e, n, p, q, false);
+    DeviceBuffer buf;
+    if (hipMalloc(&buf.p, sizer.used) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(CGGM_ENOMEM, "hipMalloc failed");
+    }
+    Arena arena;
+    arena.base = (char *)buf.p;
+    eval_layout(arena, e, n, p, q, false);
+    // f = -log det L + tr(Syy Lam) + 2 <Sxy, Theta> + |L^{-1} (X Theta)^T|_F^2 / n + penalties
+    // with tr(Syy Lam) = <Y, Y Lam> / n and <Sxy, Theta> = <Y, X Theta> / n.
+    gemm(s, false, false, n, q, p, 1.0, X, p, Th, q, 0.0, e.A, q);
+    CGGM_HIP(hipMemcpyAsync(e.L, Lam, sizeof(double) * q * q, hipMemcpyDeviceToDevice, s));
+    set_int(s, e.flag, 0);
+    cholesky_inplace(s, q, e.L, e.flag);
+    reduce_logdet(s, q, e.L, e.partials, e.scal + 0);
+    transpose(s, n, q, e.A, e.At);
+    trsm_lower_left(s, q, e.L, e.At, n, n, false);
+    reduce_dot(s, q * n, e.At, e.At, e.partials, e.scal + 2);
+    gemm(s, false, false, n, q, q, 1.0, Y, q, Lam, q, 0.0, e.YL, q);
+    reduce_dot(s, n * q, Y, e.YL, e.partials, e.scal + 3);
+    reduce_dot(s, n * q, Y, e.A, e.partials, e.scal + 4);
+    // l1 norms through the top-stats reduction (W = P, G unused)
+    reduce_top_stats(s, q, q, Lam, Lam, Lam, 0.0, 0, e.partials, e.scal + 5);
+    reduce_top_stats(s, p, q, Th, Th, Th, 0.0, 0, e.partials, e.scal + 10);
+    double h[16];
+    int hf = 0;
+    CGGM_HIP(hipMemcpyAsync(h, e.scal, sizeof(h), hipMemcpyDeviceToHost, s));
+    CGGM_HIP(hipMemcpyAsync(&hf, e.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    CGGM_HIP(hipStreamSynchronize(s));
+    if (hf || h[1] != 0.0) fail(CGGM_ENOTPD, "Lambda is not positive definite");
+    const double inv_n = 1.0 / (double)n;
+    *f_out = -h[0] + h[3] * inv_n + 2.0 * h[4] * inv_n + h[2] * inv_n + lamL * h[6] +
+             lamT * h[11];
+    return CGGM_OK;
+}
+
+int gradient_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q,
+                  const double *Lam, const double *Th, double *GL, double *GT, hipStream_t s) {
+    if (!X || !Y || !Lam || !Th || !GL || !GT) fail(CGGM_EINVAL, "NULL pointer argument");
+    check_sizes(n, p, q);
+    Arena sizer;
+    sizer.measure = true;
+    EvalWork e;
+    eval_layout(sizer, e, n, p, q, true);
+    DeviceBuffer buf;
+    if (hipMalloc(&buf.p, sizer.used) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(CGGM_ENOMEM, "hipMalloc failed");
+    }
+    Arena arena;
+    arena.base = (char *)buf.p;
+    eval_layout(arena, e, n, p, q, true);
+    const double inv_n = 1.0 / (double)n;
+    CGGM_HIP(hipMemcpyAsync(e.L, Lam, sizeof(double) * q * q, hipMemcpyDeviceToDevice, s));
+    set_int(s, e.flag, 0);
+    cholesky_inplace(s, q, e.L, e.flag);
+    reduce_logdet(s, q, e.L, e.partials, e.scal);
+    int hf = 0;
+    double h[2];
+    CGGM_HIP(hipMemcpyAsync(&hf, e.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    CGGM_HIP(hipMemcpyAsync(h, e.scal, sizeof(h), hipMemcpyDeviceToHost, s));
+    CGGM_HIP(hipStreamSynchronize(s));
+    if (hf || h[1] != 0.0) fail(CGGM_ENOTPD, "Lambda is not positive definite");
+    spd_inverse_from_cholesky(s, q, e.L, e.Work, e.Sig);
+    gemm(s, false, false, n, q, p, 1.0, X, p, Th, q, 0.0, e.A, q);        // A = X Theta
+    gemm(s, false, false, n, q, q, 1.0, e.A, q, e.Sig, q, 0.0, e.R, q);   // R = A Sigma
+    gemm(s, true, false, q, q, n, inv_n, e.R, q, e.R, q, 0.0, e.Psi, q, UPLO_LOWER);
+    symmetrize_from_lower(s, q, e.Psi);
+    gemm(s, true, false, q, q, n, inv_n, Y, q, Y, q, 0.0, e.Work, q, UPLO_LOWER);   // Syy
+    symmetrize_from_lower(s, q, e.Work);
+    assemble_lambda_gradient(s, q, e.Work, e.Sig, e.Psi, GL, e.Work);   // SP unused
+    // G_Theta = (2/n) X^T (Y + R)
+    add_kernel<<<nblk(n * q), BLOCK, 0, s>>>(n * q, Y, e.R);
+    CGGM_LAUNCH_CHECK();
+    gemm(s, true, false, p, q, n, 2.0 * inv_n, X, p, e.R, q, 0.0, GT, q);
+    CGGM_HIP(hipStreamSynchronize(s));
+    return CGGM_OK;
+}
+
+template <class F>
+int guarded(F f) {
+    try {
+        g_last_error.clear();
+        return f();
+    } catch (const Failure &e) {
+        g_last_error = e.what();
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return CGGM_ENOMEM;
+    } catch (const std::exception &e) {
+        g_last_error = e.what();
+        return CGGM_EHIP;
+    }
+}
+
+}  // namespace
+}  // namespace cggm
+
+// ================================================================= C ABI =====
+using namespace cggm;
+
+extern "C" {
+
+void cggm_default_options(cggm_options *opt) {
+    if (!opt) return;
+    memset(opt, 0, sizeof(*opt));
+    opt->max_iter = 500;
+    opt->max_ls = 30;
+    opt->ls_beta = 0.5;
+    opt->ls_sigma = 1e-3;
+    opt->stall_iters = 3;
+    opt->sweep = CGGM_SWEEP_TILED;
+    opt->tile = 0;
+}
+
+size_t cggm_solve_workspace_bytes(int64_t n, int64_t p, int64_t q) {
+    if (n < 1 || p < 1 || q < 1) return 0;
+    const Schedule th = theta_schedule(p, q, CD_TILE, false);
+    const Schedule la = lambda_schedule(q, CD_TILE, false);
+    Arena sizer;
+    sizer.measure = true;
+    Work w;
+    layout(sizer, w, n, p, q, (int64_t)th.rects.size(), (int64_t)la.rects.size(),
+           std::max(1, std::max(th.max_wave, la.max_wave)));
+    return sizer.used;
+}
+
+int cggm_solve(const double *X, const double *Y, int64_t n, int64_t p, int64_t q, double lamL,
+               double lamT, double tol, cggm_options *opt, cggm_result **out, void *stream) {
+    return guarded([&] {
+        return solve_impl(X, Y, n, p, q, lamL, lamT, tol, opt, out, (hipStream_t)stream);
+    });
+}
+
+int cggm_result_info(const cggm_result *res, int64_t *nnz_Lambda, int64_t *nnz_Theta,
+                     int *iters, double *f, int *status) {
+    return guarded([&] {
+        if (!res) fail(CGGM_EINVAL, "NULL result");
+        const auto *r = reinterpret_cast<const ResultImpl *>(res);
+        if (nnz_Lambda) *nnz_Lambda = r->nnzL;
+        if (nnz_Theta) *nnz_Theta = r->nnzT;
+        if (iters) *iters = r->iters;
+        if (f) *f = r->f;
+        if (status) *status = r->status;
+        return CGGM_OK;
+    });
+}
+
+int cggm_result_copy(const cggm_result *res, int64_t *L_rowptr, int32_t *L_col, double *L_val,
+                     int64_t *T_rowptr, int32_t *T_col, double *T_val, int to_host) {
+    return guarded([&] {
+        if (!res) fail(CGGM_EINVAL, "NULL result");
+        const auto *r = reinterpret_cast<const ResultImpl *>(res);
+        const hipMemcpyKind k = to_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+        auto cp = [&](void *dst, const void *src, size_t bytes) {
+            if (dst && bytes) CGGM_HIP(hipMemcpy(dst, src, bytes, k));
+        };
+        cp(L_rowptr, r->L_rowptr, sizeof(int64_t) * (r->q + 1));
+        cp(L_col, r->L_col, sizeof(int32_t) * r->nnzL);
+        cp(L_val, r->L_val, sizeof(double) * r->nnzL);
+        cp(T_rowptr, r->T_rowptr, sizeof(int64_t) * (r->p + 1));
+        cp(T_col, r->T_col, sizeof(int32_t) * r->nnzT);
+        cp(T_val, r->T_val, sizeof(double) * r->nnzT);
+        return CGGM_OK;
+    });
+}
+
+int cggm_result_dense(const cggm_result *res, double *Lambda, double *Theta, int to_host) {
+    return guarded([&] {
+        if (!res) fail(CGGM_EINVAL, "NULL result");
+        const auto *r = reinterpret_cast<const ResultImpl *>(res);
+        const hipMemcpyKind k = to_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+        if (Lambda) CGGM_HIP(hipMemcpy(Lambda, r->Lam, sizeof(double) * r->q * r->q, k));
+        if (Theta) CGGM_HIP(hipMemcpy(Theta, r->Th, sizeof(double) * r->p * r->q, k));
+        return CGGM_OK;
+    });
+}
+
+void cggm_result_free(cggm_result *res) { delete reinterpret_cast<ResultImpl *>(res); }
+
+int cggm_objective(const double *X, const double *Y, int64_t n, int64_t p, int64_t q,
+                   const double *Lambda, const double *Theta, double lamL, double lamT,
+                   double *f_out, void *stream) {
+    return guarded([&] {
+        return objective_impl(X, Y, n, p, q, Lambda, Theta, lamL, lamT, f_out,
+                              (hipStream_t)stream);
+    });
+}
+
+int cggm_gradient(const double *X, const double *Y, int64_t n, int64_t p, int64_t q,
+                  const double *Lambda, const double *Theta, double *G_Lambda, double *G_Theta,
+                  void *stream) {
+    return guarded([&] {
+        return gradient_impl(X, Y, n, p, q, Lambda, Theta, G_Lambda, G_Theta,
+                             (hipStream_t)stream);
+    });
+}
+
+const char *cggm_status_string(int status) {
+    switch (status) {
+        case CGGM_OK: return "ok";
+        case CGGM_MAXITER: return "iteration cap reached";
+        case CGGM_EINVAL: return "invalid argument";
+        case CGGM_ENOTPD: return "Lambda is not positive definite";
+        case CGGM_ELINESEARCH: return "line search found no Armijo step";
+        case CGGM_ENOMEM: return "out of device memory or over the workspace budget";
+        case CGGM_EHIP: return "HIP runtime error";
+        default: return "unknown status";
+    }
+}
+
+const char *cggm_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

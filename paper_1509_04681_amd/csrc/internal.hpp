@@ -1,0 +1,142 @@
+// internal.hpp -- host-side interfaces between the translation units of the
+// gfx950 CGGM solver library.  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <stdexcept>
+#include <string>
+
+#include "cggm.h"
+
+namespace cggm {
+
+// Internal error carried to the C ABI boundary, where it becomes a status code.
+struct Failure : std::runtime_error {
+    int code;
+    Failure(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] inline void fail(int code, const std::string &msg) { throw Failure(code, msg); }
+
+#define CGGM_HIP(call)                                                                   \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            ::cggm::fail(CGGM_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define CGGM_LAUNCH_CHECK() CGGM_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------- la.hip ---
+enum { UPLO_FULL = 0, UPLO_LOWER = 1 };
+enum { KRANGE_FULL = 0, KRANGE_FROM_ROW = 1 };
+
+// C = alpha op(A) op(B) + beta C, all row-major FP64, op(X) = X or X^T.
+// uplo = UPLO_LOWER computes only the 64x64 output tiles on or below the
+// diagonal (entries above the diagonal inside those tiles are written too).
+// krange = KRANGE_FROM_ROW starts the inner sum of output tile row-block I at
+// k = I * 64 (for products whose A operand is zero above that row, as in
+// L^{-T} L^{-1}).
+void gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
+          const double *A, int64_t lda, const double *B, int64_t ldb, double beta, double *C,
+          int64_t ldc, int uplo = UPLO_FULL, int krange = KRANGE_FULL);
+
+// Mirror the strict lower triangle of the q x q matrix A into its upper triangle.
+void symmetrize_from_lower(hipStream_t s, int64_t q, double *A);
+
+// A = I (q x q).
+void set_identity(hipStream_t s, int64_t q, double *A);
+
+// dst (cols x rows) = src^T (src rows x cols).
+void transpose(hipStream_t s, int64_t rows, int64_t cols, const double *src, double *dst);
+
+// In-place blocked right-looking Cholesky of the lower triangle of A (q x q,
+// ld = q): on return the lower triangle holds L with A = L L^T.  *notpd_dev
+// (device int) is set to 1 when a pivot is not strictly positive.
+void cholesky_inplace(hipStream_t s, int64_t q, double *A, int *notpd_dev);
+
+// Solve L Z = B in place (B is q x m, leading dimension ldb, L lower q x q).
+// lower_rhs = true declares B lower triangular (B = I) so only the columns a
+// lower-triangular solution can populate are touched.
+void trsm_lower_left(hipStream_t s, int64_t q, const double *L, double *B, int64_t m,
+                     int64_t ldb, bool lower_rhs);
+
+// Sigma = (L L^T)^{-1} from the Cholesky factor: W = L^{-1} (into `work`,
+// q x q), then Sigma = W^T W (lower tiles, k from the row block) mirrored.
+void spd_inverse_from_cholesky(hipStream_t s, int64_t q, const double *L, double *work,
+                               double *Sigma);
+
+// Deterministic sums: each call reduces into `out[0..nv)` (device) through a
+// fixed-size partials buffer (device, >= REDUCE_BLOCKS * 8 doubles).
+constexpr int REDUCE_BLOCKS = 512;
+
+// out[0] = 2 sum_i log L_ii; out[1] = 1 if some L_ii <= 0 or non-finite.
+void reduce_logdet(hipStream_t s, int64_t q, const double *L, double *partials, double *out);
+
+// out[0] = sum A_ij B_ij over `count` entries.
+void reduce_dot(hipStream_t s, int64_t count, const double *A, const double *B,
+                double *partials, double *out);
+
+// Statistics of the top of an iteration over a matrix pair (G, P) with
+// penalty lam (P = Lambda with G = G_Lambda and upper = 1, or P = Theta with
+// G = G_Theta):
+//   out[0] = sum_ij W_ij P_ij           (W = Syy or Sxy; tr(W^T P))
+//   out[1] = ||P||_1
+//   out[2] = l1 norm of the minimum-norm subgradient
+//   out[3] = active count (|G| > lam or P != 0; upper triangle only if upper)
+//   out[4] = nonzeros of P
+void reduce_top_stats(hipStream_t s, int64_t rows, int64_t cols, const double *W,
+                      const double *G, const double *P, double lam, int upper,
+                      double *partials, double *out);
+
+// Line-search quantities of a direction D:
+//   out[0] = sum G_ij D_ij,   out[1] = sum (|Lambda + D| - |Lambda|)  (entrywise)
+void reduce_direction(hipStream_t s, int64_t q, const double *G, const double *Lam,
+                      const double *D, double *partials, double *out);
+
+// Trial point: T = Lambda + alpha D written to `trial`; out[0] = tr(Syy T),
+// out[1] = ||T||_1.
+void build_trial(hipStream_t s, int64_t q, const double *Lam, const double *D, double alpha,
+                 const double *Syy, double *trial, double *partials, double *out);
+
+// Gradient assembly: GL = Syy - Sigma - Psi, SP = Sigma + Psi.
+void assemble_lambda_gradient(hipStream_t s, int64_t q, const double *Syy,
+                              const double *Sigma, const double *Psi, double *GL, double *SP);
+
+// y = a x (count entries).
+void scale_copy(hipStream_t s, int64_t count, double a, const double *x, double *y);
+
+// Set a device int to a value (a kernel, so the stream may be graph-captured).
+void set_int(hipStream_t s, int *dst, int v);
+
+// Count non-finite entries of x into out[0] (as a double).
+void reduce_nonfinite(hipStream_t s, int64_t count, const double *x, double *partials,
+                      double *out);
+
+// ---------------------------------------------------------------- cd.hip ---
+struct TileRect {
+    int32_t r0, r1, c0, c1;   // rows [r0, r1), columns [c0, c1)
+};
+
+constexpr int CD_TILE = 32;   // maximum tile edge of a CD tile
+
+// One wave of the Theta sweep: every rect in `rects` (row- and column-disjoint)
+// runs exact Gauss-Seidel over its active coordinates from a snapshot of
+// b = 2 Sxy + 2 Sxx V, writes the updated Theta and its delta (dT, nrect
+// tiles of CD_TILE^2), then V[rows, :] += dTheta Sigma[cols, :].
+void theta_wave(hipStream_t s, const TileRect *rects_dev, int nrect, int64_t p, int64_t q,
+                const double *Sxx, const double *Sxy, const double *Sigma, double *V,
+                const double *GT, double *Theta, double lamT, double *dT, int *changed);
+
+// One wave of the Lambda direction sweep over upper-triangle rects with
+// pairwise-disjoint index sets: exact Gauss-Seidel inside each rect from a
+// snapshot of b = G + SP U + (Psi U)^T, D written (both triangles), then
+// U rows of both index sets updated with the rect's delta.
+void lambda_wave(hipStream_t s, const TileRect *rects_dev, int nrect, int64_t q,
+                 const double *Sigma, const double *Psi, const double *SP, const double *GL,
+                 const double *Lam, double lamL, double *D, double *U, double *dD,
+                 int *changed);
+
+}  // namespace cggm

@@ -1,0 +1,446 @@
+// la.hip -- dense FP64 linear algebra on gfx950 for the CGGM solver:
+// MFMA GEMM, blocked Cholesky, blocked triangular solve / SPD inverse,
+// elementwise assembly and deterministic two-stage reductions.
+#include <math.h>
+
+#include <algorithm>
+
+#include "device_common.hpp"
+#include "internal.hpp"
+
+namespace cggm {
+
+namespace {
+
+constexpr int GEMM_TS = 64;
+
+// --------------------------------------------------------------- GEMM -------
+template <bool TA, bool TB>
+__global__ __launch_bounds__(BLOCK) void gemm_kernel(int64_t M, int64_t N, int64_t K,
+                                                     double alpha, const double *A, int64_t lda,
+                                                     const double *B, int64_t ldb, double beta,
+                                                     double *C, int64_t ldc, int uplo,
+                                                     int krange) {
+    const int64_t bm = blockIdx.y, bn = blockIdx.x;
+    if (uplo == UPLO_LOWER && bn > bm) return;
+    __shared__ TileSmem<GEMM_TS> sm;
+    WaveAcc<GEMM_TS> acc;
+    acc.zero();
+    const int64_t m0 = bm * GEMM_TS, n0 = bn * GEMM_TS;
+    const int64_t k0 = (krange == KRANGE_FROM_ROW) ? std::min<int64_t>(m0, K) : 0;
+    tile_mma<TA, TB, GEMM_TS>(A, lda, B, ldb, m0, n0, M, N, k0, K, sm, acc);
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+#pragma unroll
+    for (int i = 0; i < WaveAcc<GEMM_TS>::NB; ++i)
+#pragma unroll
+        for (int j = 0; j < WaveAcc<GEMM_TS>::NB; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = m0 + acc_row<GEMM_TS>(wid, lane, i, r);
+                const int64_t col = n0 + acc_col<GEMM_TS>(wid, lane, j);
+                if (row < M && col < N) {
+                    double *c = C + row * ldc + col;
+                    const double v = alpha * acc.c[i][j][r];
+                    *c = (beta == 0.0) ? v : v + beta * (*c);
+                }
+            }
+}
+
+// ------------------------------------------------------------ Cholesky ------
+constexpr int PB = 64;   // panel width of the blocked Cholesky / TRSM
+
+// Factor the diagonal block A[kb:kb+nb, kb:kb+nb] = L_kk L_kk^T in LDS (one
+// workgroup) and store L_kk in place; *notpd = 1 if a pivot is not positive.
+__global__ __launch_bounds__(BLOCK) void potrf_diag_kernel(double *A, int64_t q, int64_t kb,
+                                                           int nb, int *notpd) {
+    __shared__ double d[PB][PB + 1];
+    __shared__ int bad;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < nb * nb; e += BLOCK) {
+        const int i = e / nb, j = e % nb;
+        if (j <= i) d[i][j] = A[(kb + i) * q + kb + j];
+    }
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    for (int j = 0; j < nb; ++j) {
+        if (tid == 0) {
+            const double v = d[j][j];
+            if (!(v > 0.0) || !isfinite(v)) bad = 1;
+            d[j][j] = (v > 0.0 && isfinite(v)) ? sqrt(v) : 1.0;
+        }
+        __syncthreads();
+        const double djj = d[j][j];
+        for (int i = j + 1 + tid; i < nb; i += BLOCK) d[i][j] /= djj;
+        __syncthreads();
+        const int w = nb - j - 1;
+        for (int e = tid; e < w * w; e += BLOCK) {
+            const int i = j + 1 + e / w, c = j + 1 + e % w;
+            if (c <= i) d[i][c] -= d[i][j] * d[c][j];
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < nb * nb; e += BLOCK) {
+        const int i = e / nb, j = e % nb;
+        if (j <= i) A[(kb + i) * q + kb + j] = d[i][j];
+    }
+    if (tid == 0 && bad) *notpd = 1;
+}
+
+// Panel below a factored diagonal block: each thread solves one row r,
+// L[r, kb:kb+PB] = A[r, kb:kb+PB] L_kk^{-T} (full-width panels only).
+__global__ __launch_bounds__(BLOCK) void potrf_panel_kernel(double *A, int64_t q, int64_t kb) {
+    __shared__ double d[PB][PB + 1];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < PB * PB; e += BLOCK) {
+        const int i = e / PB, j = e % PB;
+        d[i][j] = (j <= i) ? A[(kb + i) * q + kb + j] : 0.0;
+    }
+    __syncthreads();
+    const int64_t r = kb + PB + (int64_t)blockIdx.x * BLOCK + tid;
+    if (r >= q) return;
+    double x[PB];
+    double *row = A + r * q + kb;
+#pragma unroll
+    for (int c = 0; c < PB; ++c) x[c] = row[c];
+#pragma unroll
+    for (int c = 0; c < PB; ++c) {
+        double s = x[c];
+#pragma unroll
+        for (int m = 0; m < c; ++m) s -= x[m] * d[c][m];
+        x[c] = s / d[c][c];
+    }
+#pragma unroll
+    for (int c = 0; c < PB; ++c) row[c] = x[c];
+}
+
+// Forward substitution of one diagonal block for the columns [0, ncols) of
+// B[kb:kb+nb, :]: B_k <- L_kk^{-1} B_k, one column per thread.
+__global__ __launch_bounds__(BLOCK) void trsm_diag_kernel(const double *L, int64_t q,
+                                                          int64_t kb, int nb, double *B,
+                                                          int64_t ldb, int64_t ncols) {
+    __shared__ double d[PB][PB + 1];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < PB * PB; e += BLOCK) {
+        const int i = e / PB, j = e % PB;
+        double v;
+        if (i < nb && j < nb) v = (j <= i) ? L[(kb + i) * q + kb + j] : 0.0;
+        else v = (i == j) ? 1.0 : 0.0;
+        d[i][j] = v;
+    }
+    __syncthreads();
+    const int64_t c = (int64_t)blockIdx.x * BLOCK + tid;
+    if (c >= ncols) return;
+    double x[PB];
+#pragma unroll
+    for (int i = 0; i < PB; ++i) x[i] = (i < nb) ? B[(kb + i) * ldb + c] : 0.0;
+#pragma unroll
+    for (int i = 0; i < PB; ++i) {
+        double s = x[i];
+#pragma unroll
+        for (int m = 0; m < i; ++m) s -= d[i][m] * x[m];
+        x[i] = s / d[i][i];
+    }
+#pragma unroll
+    for (int i = 0; i < PB; ++i)
+        if (i < nb) B[(kb + i) * ldb + c] = x[i];
+}
+
+// ---------------------------------------------------------- elementwise -----
+__global__ void symmetrize_kernel(int64_t q, double *A) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= q * q) return;
+    const int64_t i = e / q, j = e % q;
+    if (j > i) A[e] = A[j * q + i];
+}
+
+__global__ void identity_kernel(int64_t q, double *A) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= q * q) return;
+    A[e] = (e / q == e % q) ? 1.0 : 0.0;
+}
+
+__global__ void transpose_kernel(int64_t rows, int64_t cols, const double *src, double *dst) {
+    __shared__ double t[32][33];
+    const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8 threads
+    for (int k = ty; k < 32; k += 8) {
+        const int64_t r = r0 + k, c = c0 + tx;
+        if (r < rows && c < cols) t[k][tx] = src[r * cols + c];
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+        const int64_t c = c0 + k, r = r0 + tx;   // dst row c, column r
+        if (r < rows && c < cols) dst[c * rows + r] = t[tx][k];
+    }
+}
+
+__global__ void assemble_lambda_kernel(int64_t count, const double *Syy, const double *Sigma,
+                                       const double *Psi, double *GL, double *SP) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    const double s = Sigma[e], p = Psi[e];
+    GL[e] = Syy[e] - s - p;
+    SP[e] = s + p;
+}
+
+__global__ void scale_copy_kernel(int64_t count, double a, const double *x, double *y) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < count) y[e] = a * x[e];
+}
+
+__global__ void set_int_kernel(int *dst, int v) { *dst = v; }
+
+// ---------------------------------------------------------- reductions ------
+// Block-level sum of NV values; thread 0 of the block gets the totals.
+template <int NV>
+__device__ void block_sum(double (&v)[NV], double (&out)[NV]) {
+    __shared__ double red[BLOCK / WAVE][NV];
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        const double w = wave_sum(v[k]);
+        if (lane == 0) red[wid][k] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double t = 0.0;
+            for (int w = 0; w < BLOCK / WAVE; ++w) t += red[w][k];
+            out[k] = t;
+        }
+    }
+}
+
+template <int NV, class F>
+__global__ __launch_bounds__(BLOCK) void reduce_partials_kernel(int64_t count, F f,
+                                                                double *partials) {
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < count; e += stride)
+        f(e, acc);
+    double tot[NV];
+    block_sum<NV>(acc, tot);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) partials[blockIdx.x * NV + k] = tot[k];
+}
+
+template <int NV>
+__global__ __launch_bounds__(BLOCK) void reduce_final_kernel(int nblocks,
+                                                             const double *partials,
+                                                             double *out) {
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += BLOCK)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) acc[k] += partials[b * NV + k];
+    double tot[NV];
+    block_sum<NV>(acc, tot);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) out[k] = tot[k];
+}
+
+template <int NV, class F>
+void run_reduce(hipStream_t s, int64_t count, F f, double *partials, double *out) {
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(REDUCE_BLOCKS,
+                                                               (count + BLOCK - 1) / BLOCK));
+    reduce_partials_kernel<NV, F><<<nb, BLOCK, 0, s>>>(count, f, partials);
+    CGGM_LAUNCH_CHECK();
+    reduce_final_kernel<NV><<<1, BLOCK, 0, s>>>(nb, partials, out);
+    CGGM_LAUNCH_CHECK();
+}
+
+struct LogdetF {
+    const double *L;
+    int64_t q;
+    __device__ void operator()(int64_t i, double (&acc)[2]) const {
+        const double d = L[i * q + i];
+        if (d > 0.0 && isfinite(d)) acc[0] += 2.0 * log(d);
+        else acc[1] += 1.0;
+    }
+};
+
+struct DotF {
+    const double *A, *B;
+    __device__ void operator()(int64_t e, double (&acc)[1]) const { acc[0] += A[e] * B[e]; }
+};
+
+struct TopStatsF {
+    const double *W, *G, *P;
+    double lam;
+    int64_t cols;
+    int upper;
+    __device__ void operator()(int64_t e, double (&acc)[5]) const {
+        const double w = W[e], g = G[e], x = P[e];
+        acc[0] += w * x;
+        acc[1] += fabs(x);
+        if (x != 0.0) acc[2] += fabs(g + copysign(lam, x));
+        else acc[2] += fmax(fabs(g) - lam, 0.0);
+        const bool in_tri = !upper || (e % cols) >= (e / cols);
+        acc[3] += (in_tri && (fabs(g) > lam || x != 0.0)) ? 1.0 : 0.0;
+        acc[4] += (x != 0.0) ? 1.0 : 0.0;
+    }
+};
+
+struct DirectionF {
+    const double *G, *Lam, *D;
+    __device__ void operator()(int64_t e, double (&acc)[2]) const {
+        const double d = D[e], l = Lam[e];
+        acc[0] += G[e] * d;
+        acc[1] += fabs(l + d) - fabs(l);
+    }
+};
+
+struct TrialF {
+    const double *Lam, *D, *Syy;
+    double alpha;
+    double *T;
+    __device__ void operator()(int64_t e, double (&acc)[2]) const {
+        const double t = Lam[e] + alpha * D[e];
+        T[e] = t;
+        acc[0] += Syy[e] * t;
+        acc[1] += fabs(t);
+    }
+};
+
+struct NonFiniteF {
+    const double *x;
+    __device__ void operator()(int64_t e, double (&acc)[1]) const {
+        acc[0] += isfinite(x[e]) ? 0.0 : 1.0;
+    }
+};
+
+inline int blocks_for(int64_t count, int bs = BLOCK) {
+    return (int)std::max<int64_t>(1, (count + bs - 1) / bs);
+}
+
+}  // namespace
+
+// ======================================================== host wrappers =====
+void gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
+          const double *A, int64_t lda, const double *B, int64_t ldb, double beta, double *C,
+          int64_t ldc, int uplo, int krange) {
+    if (M <= 0 || N <= 0) return;
+    dim3 grid((unsigned)((N + GEMM_TS - 1) / GEMM_TS), (unsigned)((M + GEMM_TS - 1) / GEMM_TS));
+    if (ta && tb)
+        gemm_kernel<true, true><<<grid, BLOCK, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C,
+                                                       ldc, uplo, krange);
+    else if (ta)
+        gemm_kernel<true, false><<<grid, BLOCK, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C,
+                                                        ldc, uplo, krange);
+    else if (tb)
+        gemm_kernel<false, true><<<grid, BLOCK, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C,
+                                                        ldc, uplo, krange);
+    else
+        gemm_kernel<false, false><<<grid, BLOCK, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta,
+                                                         C, ldc, uplo, krange);
+    CGGM_LAUNCH_CHECK();
+}
+
+void symmetrize_from_lower(hipStream_t s, int64_t q, double *A) {
+    symmetrize_kernel<<<blocks_for(q * q), BLOCK, 0, s>>>(q, A);
+    CGGM_LAUNCH_CHECK();
+}
+
+void set_identity(hipStream_t s, int64_t q, double *A) {
+    identity_kernel<<<blocks_for(q * q), BLOCK, 0, s>>>(q, A);
+    CGGM_LAUNCH_CHECK();
+}
+
+void transpose(hipStream_t s, int64_t rows, int64_t cols, const double *src, double *dst) {
+    dim3 grid((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32));
+    transpose_kernel<<<grid, BLOCK, 0, s>>>(rows, cols, src, dst);
+    CGGM_LAUNCH_CHECK();
+}
+
+void cholesky_inplace(hipStream_t s, int64_t q, double *A, int *notpd_dev) {
+    for (int64_t kb = 0; kb < q; kb += PB) {
+        const int nb = (int)std::min<int64_t>(PB, q - kb);
+        const int64_t below = q - kb - nb;
+        potrf_diag_kernel<<<1, BLOCK, 0, s>>>(A, q, kb, nb, notpd_dev);
+        CGGM_LAUNCH_CHECK();
+        if (below > 0) {                 // below > 0 implies nb == PB
+            potrf_panel_kernel<<<blocks_for(below), BLOCK, 0, s>>>(A, q, kb);
+            CGGM_LAUNCH_CHECK();
+            const double *P = A + (kb + nb) * q + kb;
+            gemm(s, false, true, below, below, nb, -1.0, P, q, P, q, 1.0,
+                 A + (kb + nb) * q + kb + nb, q, UPLO_LOWER, KRANGE_FULL);
+        }
+    }
+}
+
+void trsm_lower_left(hipStream_t s, int64_t q, const double *L, double *B, int64_t m,
+                     int64_t ldb, bool lower_rhs) {
+    for (int64_t kb = 0; kb < q; kb += PB) {
+        const int nb = (int)std::min<int64_t>(PB, q - kb);
+        const int64_t ncols = lower_rhs ? std::min<int64_t>(m, kb + nb) : m;
+        trsm_diag_kernel<<<blocks_for(ncols), BLOCK, 0, s>>>(L, q, kb, nb, B, ldb, ncols);
+        CGGM_LAUNCH_CHECK();
+        const int64_t below = q - kb - nb;
+        if (below > 0)
+            gemm(s, false, false, below, ncols, nb, -1.0, L + (kb + nb) * q + kb, q,
+                 B + kb * ldb, ldb, 1.0, B + (kb + nb) * ldb, ldb);
+    }
+}
+
+void spd_inverse_from_cholesky(hipStream_t s, int64_t q, const double *L, double *work,
+                               double *Sigma) {
+    set_identity(s, q, work);
+    trsm_lower_left(s, q, L, work, q, q, true);          // work = L^{-1} (lower)
+    gemm(s, true, false, q, q, q, 1.0, work, q, work, q, 0.0, Sigma, q, UPLO_LOWER,
+         KRANGE_FROM_ROW);                               // Sigma = L^{-T} L^{-1}
+    symmetrize_from_lower(s, q, Sigma);
+}
+
+void reduce_logdet(hipStream_t s, int64_t q, const double *L, double *partials, double *out) {
+    run_reduce<2>(s, q, LogdetF{L, q}, partials, out);
+}
+
+void reduce_dot(hipStream_t s, int64_t count, const double *A, const double *B,
+                double *partials, double *out) {
+    run_reduce<1>(s, count, DotF{A, B}, partials, out);
+}
+
+void reduce_top_stats(hipStream_t s, int64_t rows, int64_t cols, const double *W,
+                      const double *G, const double *P, double lam, int upper,
+                      double *partials, double *out) {
+    run_reduce<5>(s, rows * cols, TopStatsF{W, G, P, lam, cols, upper}, partials, out);
+}
+
+void reduce_direction(hipStream_t s, int64_t q, const double *G, const double *Lam,
+                      const double *D, double *partials, double *out) {
+    run_reduce<2>(s, q * q, DirectionF{G, Lam, D}, partials, out);
+}
+
+void build_trial(hipStream_t s, int64_t q, const double *Lam, const double *D, double alpha,
+                 const double *Syy, double *trial, double *partials, double *out) {
+    run_reduce<2>(s, q * q, TrialF{Lam, D, Syy, alpha, trial}, partials, out);
+}
+
+void reduce_nonfinite(hipStream_t s, int64_t count, const double *x, double *partials,
+                      double *out) {
+    run_reduce<1>(s, count, NonFiniteF{x}, partials, out);
+}
+
+void assemble_lambda_gradient(hipStream_t s, int64_t q, const double *Syy,
+                              const double *Sigma, const double *Psi, double *GL, double *SP) {
+    assemble_lambda_kernel<<<blocks_for(q * q), BLOCK, 0, s>>>(q * q, Syy, Sigma, Psi, GL, SP);
+    CGGM_LAUNCH_CHECK();
+}
+
+void scale_copy(hipStream_t s, int64_t count, double a, const double *x, double *y) {
+    scale_copy_kernel<<<blocks_for(count), BLOCK, 0, s>>>(count, a, x, y);
+    CGGM_LAUNCH_CHECK();
+}
+
+void set_int(hipStream_t s, int *dst, int v) {
+    set_int_kernel<<<1, 1, 0, s>>>(dst, v);
+    CGGM_LAUNCH_CHECK();
+}
+
+}  // namespace cggm

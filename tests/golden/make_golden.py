@@ -1,0 +1,112 @@
+"""Write the stored expected values of the parity tests.
+
+Every number written here comes from the CPU oracle (``oracle/``) run on the
+seeded synthetic workloads of ``synth``; nothing comes from the GPU library.
+The solve is run to the rounding floor (the oracle's stall rule) in chunks of
+warm-started iterations so a long run can resume from its last state.
+
+    python tests/golden/make_golden.py chain40
+    python tests/golden/make_golden.py chain2k --state-dir /tmp/golden_state
+
+Output: tests/golden/<workload>.json with the converged objective f*, the
+iteration count, the nonzero counts, and the supports {|x| > 1e-6} of Lambda*
+and Theta* as zlib-compressed bitmasks (numpy.packbits, row-major).
+"""
+import argparse
+import base64
+import json
+import os
+import sys
+import time
+import zlib
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+
+SUPPORT_EPS = 1e-6
+
+
+def pack_mask(mask: np.ndarray) -> str:
+    return base64.b64encode(zlib.compress(np.packbits(mask.reshape(-1)).tobytes(), 9)).decode()
+
+
+def unpack_mask(s: str, shape) -> np.ndarray:
+    bits = np.frombuffer(zlib.decompress(base64.b64decode(s)), np.uint8)
+    return np.unpackbits(bits)[: int(np.prod(shape))].reshape(shape).astype(bool)
+
+
+def load(name: str) -> dict:
+    with open(os.path.join(HERE, f"{name}.json")) as fh:
+        g = json.load(fh)
+    q, p = g["q"], g["p"]
+    g["support_Lambda"] = unpack_mask(g["support_Lambda"], (q, q))
+    g["support_Theta"] = unpack_mask(g["support_Theta"], (p, q))
+    g["borderline_Lambda"] = unpack_mask(g["borderline_Lambda"], (q, q))
+    g["borderline_Theta"] = unpack_mask(g["borderline_Theta"], (p, q))
+    return g
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("workload", choices=sorted(synth.WORKLOADS))
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--chunk", type=int, default=25)
+    ap.add_argument("--max-iter", type=int, default=20000)
+    ap.add_argument("--state-dir", default=None)
+    args = ap.parse_args()
+    pr = synth.workload(args.workload, seed=args.seed)
+    state = args.state_dir
+    Lam = Th = None
+    done = 0
+    fs = []
+    if state and os.path.exists(os.path.join(state, "Lambda.npy")):
+        Lam = np.load(os.path.join(state, "Lambda.npy"))
+        Th = np.load(os.path.join(state, "Theta.npy"))
+        meta = json.load(open(os.path.join(state, "meta.json")))
+        done, fs = meta["done"], meta["f"]
+    t0 = time.time()
+    while True:
+        r = oracle.solve(pr.X, pr.Y, pr.lam_Lambda, pr.lam_Theta, tol=0.0,
+                         max_iter=args.chunk, stall_iters=3, Lambda0=Lam, Theta0=Th)
+        Lam, Th = r.Lambda, r.Theta
+        done += r.iters
+        fs.extend(float(v) for v in r.trace["f"][: r.iters])
+        print(f"[{time.time() - t0:9.1f}s] iters={done} f={r.f!r} "
+              f"subgrad/l1={r.trace['subgrad'][-1] / r.trace['l1'][-1]:.3e} status={r.status}",
+              flush=True)
+        if state:
+            os.makedirs(state, exist_ok=True)
+            np.save(os.path.join(state, "Lambda.npy"), Lam)
+            np.save(os.path.join(state, "Theta.npy"), Th)
+            json.dump({"done": done, "f": fs}, open(os.path.join(state, "meta.json"), "w"))
+        if r.status == oracle.ORC_STALLED or done >= args.max_iter:
+            break
+    out = {
+        "workload": args.workload, "seed": args.seed, "n": pr.n, "p": pr.p, "q": pr.q,
+        "lam_Lambda": pr.lam_Lambda, "lam_Theta": pr.lam_Theta,
+        "f_star": r.f, "iterations": done, "status": int(r.status),
+        "subgrad_l1": float(r.trace["subgrad"][-1]), "l1": float(r.trace["l1"][-1]),
+        "nnz_Lambda": int(np.count_nonzero(np.abs(Lam) > SUPPORT_EPS)),
+        "nnz_Theta": int(np.count_nonzero(np.abs(Th) > SUPPORT_EPS)),
+        "support_eps": SUPPORT_EPS,
+        "support_Lambda": pack_mask(np.abs(Lam) > SUPPORT_EPS),
+        "support_Theta": pack_mask(np.abs(Th) > SUPPORT_EPS),
+        # entries whose magnitude lies in [1e-7, 1e-5]: support comparisons skip them
+        "borderline_Lambda": pack_mask((np.abs(Lam) >= 1e-7) & (np.abs(Lam) <= 1e-5)),
+        "borderline_Theta": pack_mask((np.abs(Th) >= 1e-7) & (np.abs(Th) <= 1e-5)),
+        "f_trace_head": fs[:50],
+        "generator": "synth.workload(%r, seed=%d) -> oracle.solve(tol=0, stall_iters=3)"
+                     % (args.workload, args.seed),
+    }
+    with open(os.path.join(HERE, f"{args.workload}.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+    print("wrote", args.workload, "f*", r.f)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,95 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every entry point include/cggm.h declares, and rejects bad arguments before
+touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "cggm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cggm_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1509_04681_amd as m
+    if not os.path.exists(m.LIB_PATH):
+        from paper_1509_04681_amd import build
+        build.build()
+    return m.load()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("cggm_solve", "cggm_objective", "cggm_gradient", "cggm_result_info",
+                     "cggm_result_copy", "cggm_result_free", "cggm_status_string",
+                     "cggm_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_status_strings(lib):
+    import paper_1509_04681_amd as m
+    for code in (0, 1, -1, -2, -3, -4, -5):
+        assert m.cggm_status_string(code) != "unknown status"
+    assert m.cggm_status_string(42) == "unknown status"
+
+
+def test_argument_errors_without_device(lib):
+    import paper_1509_04681_amd as m
+    r = ctypes.c_void_p()
+    fake = ctypes.c_void_p(64)          # never dereferenced: validation fails first
+    assert lib.cggm_solve(None, fake, 4, 3, 2, 0.1, 0.1, 0.01, None, ctypes.byref(r), None) \
+        == m.CGGM_EINVAL
+    assert lib.cggm_solve(fake, fake, 0, 3, 2, 0.1, 0.1, 0.01, None, ctypes.byref(r), None) \
+        == m.CGGM_EINVAL
+    assert lib.cggm_solve(fake, fake, 4, 3, 2, -0.1, 0.1, 0.01, None, ctypes.byref(r), None) \
+        == m.CGGM_EINVAL
+    assert lib.cggm_solve(fake, fake, 4, 3, 2, 0.1, float("nan"), 0.01, None, ctypes.byref(r),
+                          None) == m.CGGM_EINVAL
+    assert lib.cggm_solve(fake, fake, 4, 3, 2, 0.1, 0.1, -1.0, None, ctypes.byref(r), None) \
+        == m.CGGM_EINVAL
+    assert b"tol" in lib.cggm_last_error()
+    opt = m.Options()
+    lib.cggm_default_options(ctypes.byref(opt))
+    opt.ls_beta = 1.5
+    assert lib.cggm_solve(fake, fake, 4, 3, 2, 0.1, 0.1, 0.01, ctypes.byref(opt),
+                          ctypes.byref(r), None) == m.CGGM_EINVAL
+    lib.cggm_default_options(ctypes.byref(opt))
+    opt.tile = 64
+    assert lib.cggm_solve(fake, fake, 4, 3, 2, 0.1, 0.1, 0.01, ctypes.byref(opt),
+                          ctypes.byref(r), None) == m.CGGM_EINVAL
+
+
+def test_workspace_budget_is_checked_before_allocation(lib):
+    import paper_1509_04681_amd as m
+    need = m.cggm_solve_workspace_bytes(50, 40, 30)
+    assert need > 8 * (30 * 30 * 11 + 40 * 30 * 5 + 40 * 40)
+    opt = m.Options()
+    lib.cggm_default_options(ctypes.byref(opt))
+    opt.workspace_budget = need - 1
+    r = ctypes.c_void_p()
+    fake = ctypes.c_void_p(64)
+    assert lib.cggm_solve(fake, fake, 50, 40, 30, 0.1, 0.1, 0.01, ctypes.byref(opt),
+                          ctypes.byref(r), None) == m.CGGM_ENOMEM
+    # footprint at the 20000 x 20000 workload fits one 288 GB device
+    assert m.cggm_solve_workspace_bytes(1000, 20000, 20000) < 100e9
+
+
+def test_default_options(lib):
+    import paper_1509_04681_amd as m
+    opt = m.Options()
+    lib.cggm_default_options(ctypes.byref(opt))
+    assert (opt.max_iter, opt.max_ls, opt.ls_beta, opt.ls_sigma, opt.stall_iters) == \
+        (500, 30, 0.5, 1e-3, 3)
+    assert opt.sweep == m.CGGM_SWEEP_TILED

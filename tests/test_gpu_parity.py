@@ -1,0 +1,281 @@
+"""Parity of the gfx950 library (through its C ABI) with the CPU oracle.
+
+Bars (FP64 mode): per-evaluation quantities (gradient, objective) agree to
+1e-12 relative; a solve run in the oracle's coordinate order reproduces its
+iterates to rounding; a converged tiled solve matches the oracle's converged
+objective within 1e-8 relative with identical supports {|x| > 1e-6}
+(entries with magnitude in [1e-7, 1e-5] on either side are reported as
+borderline and excluded from the support comparison).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+F_RTOL = 1e-8
+SUPPORT_EPS = 1e-6
+
+
+@pytest.fixture(scope="module")
+def cg():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1509_04681_amd as m
+    m.load()
+    return m
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.build()
+    return oracle
+
+
+def load_golden(name):
+    import importlib.util
+    path = os.path.join(os.path.dirname(__file__), "golden", "make_golden.py")
+    spec = importlib.util.spec_from_file_location("make_golden", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod.load(name)
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda:0")
+
+
+def rel_err(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def random_problem(p, q, n, seed, theta_density=0.2):
+    rng = np.random.default_rng(seed)
+    Lam = synth.random_spd(q, rng, degree=3.0)
+    Theta = synth.dense_theta(p, q, theta_density, rng)
+    X = rng.standard_normal((n, p))
+    Sig = np.linalg.inv(Lam)
+    E = rng.standard_normal((n, q)) @ np.linalg.cholesky(Sig).T
+    Y = -X @ Theta @ Sig + E
+    return np.ascontiguousarray(X), np.ascontiguousarray(Y)
+
+
+def eval_point(p, q, rng):
+    Lam = synth.random_spd(q, rng, degree=3.0) + 0.2 * np.eye(q)
+    Theta = synth.dense_theta(p, q, 0.3, rng)
+    return Lam, Theta
+
+
+SHAPES = [(70, 90, 50), (130, 65, 200), (64, 64, 64), (1, 1, 3), (5, 129, 7)]
+
+
+@pytest.mark.parametrize("p,q,n", SHAPES)
+def test_gradient_matches_oracle(cg, orc, p, q, n):
+    rng = np.random.default_rng(p * 1000 + q)
+    X, Y = random_problem(p, q, n, seed=p + q)
+    Lam, Theta = eval_point(p, q, rng)
+    GL, GT = cg.cggm_gradient(dev(X), dev(Y), dev(Lam), dev(Theta))
+    GLo, GTo, _, _ = orc.gradient(orc.stats(X, Y), Lam, Theta)
+    print(f"gradient p={p} q={q} n={n}: rel err GL {rel_err(GL.cpu(), GLo):.2e} "
+          f"GT {rel_err(GT.cpu(), GTo):.2e}", flush=True)
+    assert rel_err(GL.cpu().numpy(), GLo) < 1e-12
+    assert rel_err(GT.cpu().numpy(), GTo) < 1e-12
+
+
+@pytest.mark.parametrize("p,q,n", SHAPES)
+def test_objective_matches_oracle(cg, orc, p, q, n):
+    rng = np.random.default_rng(7 * p + q)
+    X, Y = random_problem(p, q, n, seed=3 * p + q)
+    Lam, Theta = eval_point(p, q, rng)
+    f = cg.cggm_objective(dev(X), dev(Y), dev(Lam), dev(Theta), 0.07, 0.03)
+    fo = orc.objective(orc.stats(X, Y), Lam, Theta, 0.07, 0.03)
+    assert f == pytest.approx(fo, rel=1e-12)
+
+
+def test_objective_rejects_non_pd(cg):
+    X, Y = random_problem(4, 3, 10, seed=1)
+    Lam = np.eye(3)
+    Lam[1, 1] = -1.0
+    with pytest.raises(cg.CggmError) as ei:
+        cg.cggm_objective(dev(X), dev(Y), dev(Lam), dev(np.zeros((4, 3))), 0.1, 0.1)
+    assert ei.value.code == cg.CGGM_ENOTPD
+
+
+@pytest.mark.parametrize("p,q,n,seed", [(24, 20, 60, 0), (9, 33, 40, 1)])
+def test_sequential_order_reproduces_oracle_iterates(cg, orc, p, q, n, seed):
+    """With one coordinate per wave in lexicographic order the GPU runs the
+    oracle's exact Gauss-Seidel sequence: every iterate agrees to rounding."""
+    pr = synth.chain_problem(p=p, q=q, n=n, density=0.1, lam=0.08, seed=seed)
+    k = 6
+    g = cg.cggm_solve(dev(pr.X), dev(pr.Y), pr.lam_Lambda, pr.lam_Theta, tol=0.0, max_iter=k,
+                      stall_iters=0, sweep=cg.CGGM_SWEEP_SEQUENTIAL)
+    o = orc.solve(pr.X, pr.Y, pr.lam_Lambda, pr.lam_Theta, tol=0.0, max_iter=k)
+    fg = np.array([t["f"] for t in g.trace])
+    np.testing.assert_allclose(fg, o.trace["f"], rtol=1e-11)
+    np.testing.assert_array_equal([t["m_Lambda"] for t in g.trace], o.trace["mL"])
+    np.testing.assert_array_equal([t["m_Theta"] for t in g.trace], o.trace["mT"])
+    np.testing.assert_allclose([t["alpha"] for t in g.trace[:-1]], o.trace["alpha"][:-1])
+    np.testing.assert_allclose(g.Lambda.cpu().numpy(), o.Lambda, rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(g.Theta.cpu().numpy(), o.Theta, rtol=1e-10, atol=1e-12)
+
+
+def support_compare(G, O):
+    """Supports {|x| > 1e-6} must agree outside the borderline band [1e-7, 1e-5]."""
+    G, O = np.abs(np.asarray(G)), np.abs(np.asarray(O))
+    border = ((G >= 1e-7) & (G <= 1e-5)) | ((O >= 1e-7) & (O <= 1e-5))
+    mism = ((G > SUPPORT_EPS) != (O > SUPPORT_EPS)) & ~border
+    return int(mism.sum()), int(border.sum())
+
+
+def kkt_violation(X, Y, Lam, Theta, lamL, lamT):
+    n = X.shape[0]
+    Sxx, Sxy, Syy = X.T @ X / n, X.T @ Y / n, Y.T @ Y / n
+    Sig = np.linalg.inv(Lam)
+    Gam = Sxx @ Theta @ Sig
+    GL, GT = Syy - Sig - Sig @ Theta.T @ Gam, 2 * Sxy + 2 * Gam
+
+    def viol(G, P, lam):
+        nz = P != 0
+        a = np.abs(G[nz] + lam * np.sign(P[nz])).max(initial=0.0)
+        b = np.maximum(np.abs(G[~nz]) - lam, 0).max(initial=0.0)
+        return max(a, b)
+
+    return max(viol(GL, Lam, lamL), viol(GT, Theta, lamT))
+
+
+def solve_both(cg, orc, X, Y, lamL, lamT, **kw):
+    g = cg.cggm_solve(dev(X), dev(Y), lamL, lamT, tol=0.0, max_iter=5000, **kw)
+    o = orc.solve(X, Y, lamL, lamT, tol=0.0, max_iter=5000, stall_iters=3)
+    return g, o
+
+
+@pytest.mark.parametrize("case", ["chain40", "ragged75x50", "ragged33x97", "wide20x140"])
+def test_tiled_solve_converges_to_oracle_optimum(cg, orc, case):
+    if case == "chain40":
+        pr = synth.workload("chain40")
+        X, Y, lamL, lamT = pr.X, pr.Y, pr.lam_Lambda, pr.lam_Theta
+    else:
+        shapes = {"ragged75x50": (75, 50, 90), "ragged33x97": (33, 97, 120),
+                  "wide20x140": (20, 140, 60)}
+        p, q, n = shapes[case]
+        pr = synth.chain_problem(p=p, q=q, n=n, density=0.05, lam=0.1, seed=11)
+        X, Y, lamL, lamT = pr.X, pr.Y, pr.lam_Lambda, pr.lam_Theta
+    g, o = solve_both(cg, orc, X, Y, lamL, lamT)
+    Lg, Tg = g.Lambda.cpu().numpy(), g.Theta.cpu().numpy()
+    mL, bL = support_compare(Lg, o.Lambda)
+    mT, bT = support_compare(Tg, o.Theta)
+    print(f"{case}: f_gpu={g.f!r} f_oracle={o.f!r} rel={abs(g.f - o.f) / abs(o.f):.2e} "
+          f"iters gpu={g.iters} oracle={o.iters} support mismatches L={mL} T={mT} "
+          f"borderline L={bL} T={bT} kkt={kkt_violation(X, Y, Lg, Tg, lamL, lamT):.2e}",
+          flush=True)
+    assert abs(g.f - o.f) <= F_RTOL * abs(o.f)
+    assert mL == 0 and mT == 0
+    assert np.array_equal(Lg, Lg.T)
+    assert kkt_violation(X, Y, Lg, Tg, lamL, lamT) < 1e-6
+
+
+def test_golden_chain40(cg):
+    """Stored oracle optimum of the 40 x 40 chain workload (tests/golden)."""
+    gold = load_golden("chain40")
+    pr = synth.workload("chain40")
+    g = cg.cggm_solve(dev(pr.X), dev(pr.Y), pr.lam_Lambda, pr.lam_Theta, tol=0.0,
+                      max_iter=5000)
+    assert abs(g.f - gold["f_star"]) <= F_RTOL * abs(gold["f_star"])
+    sL = np.abs(g.Lambda.cpu().numpy()) > SUPPORT_EPS
+    sT = np.abs(g.Theta.cpu().numpy()) > SUPPORT_EPS
+    assert ((sL == gold["support_Lambda"]) | gold["borderline_Lambda"]).all()
+    assert ((sT == gold["support_Theta"]) | gold["borderline_Theta"]).all()
+
+
+def test_monotone_and_pd_trace(cg):
+    pr = synth.chain_problem(p=60, q=70, n=80, density=0.05, lam=0.08, seed=5)
+    g = cg.cggm_solve(dev(pr.X), dev(pr.Y), pr.lam_Lambda, pr.lam_Theta, tol=0.0, max_iter=400)
+    f = np.array([t["f"] for t in g.trace])
+    assert np.all(np.diff(f) <= 1e-12 * np.abs(f[1:]))
+    assert np.linalg.eigvalsh(g.Lambda.cpu().numpy()).min() > 0
+
+
+def test_repeat_is_bitwise_identical(cg):
+    """Fixed-order reductions, no floating-point atomics: two runs give the same bits."""
+    pr = synth.chain_problem(p=90, q=80, n=70, density=0.05, lam=0.08, seed=6)
+    a = cg.cggm_solve(dev(pr.X), dev(pr.Y), pr.lam_Lambda, pr.lam_Theta, tol=0.0, max_iter=30)
+    b = cg.cggm_solve(dev(pr.X), dev(pr.Y), pr.lam_Lambda, pr.lam_Theta, tol=0.0, max_iter=30)
+    assert a.f == b.f
+    assert np.array_equal(a.Lambda.cpu().numpy(), b.Lambda.cpu().numpy())
+    assert np.array_equal(a.Theta.cpu().numpy(), b.Theta.cpu().numpy())
+
+
+def test_warm_start_resume_matches_uninterrupted(cg):
+    pr = synth.chain_problem(p=40, q=50, n=60, density=0.05, lam=0.1, seed=8)
+    X, Y = dev(pr.X), dev(pr.Y)
+    full = cg.cggm_solve(X, Y, pr.lam_Lambda, pr.lam_Theta, tol=0.0, max_iter=3000)
+    part = cg.cggm_solve(X, Y, pr.lam_Lambda, pr.lam_Theta, tol=0.0, max_iter=10, stall_iters=0)
+    rest = cg.cggm_solve(X, Y, pr.lam_Lambda, pr.lam_Theta, tol=0.0, max_iter=3000,
+                         warm_Lambda=part.Lambda, warm_Theta=part.Theta)
+    assert rest.f == pytest.approx(full.f, rel=1e-12)
+
+
+def test_single_output_is_lasso(cg):
+    """q = 1: Theta* = -b*/K(b*), Lambda* = 1/K(b*) with b* the lasso solution."""
+    from sklearn.linear_model import Lasso
+    rng = np.random.default_rng(12)
+    n, p = 80, 30
+    X = rng.standard_normal((n, p))
+    y = X @ synth.dense_theta(p, 1, 0.3, rng)[:, 0] + 0.5 * rng.standard_normal(n)
+    lamL, lamT = 0.05, 0.1
+    g = cg.cggm_solve(dev(X), dev(y[:, None]), lamL, lamT, tol=0.0, max_iter=5000)
+    b = Lasso(alpha=lamT / 2, fit_intercept=False, tol=1e-15, max_iter=1000000).fit(X, y).coef_
+    K = np.sum((y - X @ b) ** 2) / n + lamT * np.abs(b).sum() + lamL
+    assert g.f == pytest.approx(1 + np.log(K), rel=1e-10)
+    assert g.Lambda.item() == pytest.approx(1 / K, rel=1e-7)
+    np.testing.assert_allclose(g.Theta.cpu().numpy()[:, 0], -b / K, atol=1e-7)
+
+
+def test_unpenalised_closed_form(cg):
+    """lambda = 0, n > p + q: Lambda^{-1} is the OLS residual covariance."""
+    X, Y = random_problem(12, 9, 200, seed=13)
+    g = cg.cggm_solve(dev(X), dev(Y), 0.0, 0.0, tol=0.0, max_iter=5000)
+    n = X.shape[0]
+    Sxx, Sxy, Syy = X.T @ X / n, X.T @ Y / n, Y.T @ Y / n
+    B = np.linalg.solve(Sxx, Sxy)
+    Sig = Syy - Sxy.T @ B
+    np.testing.assert_allclose(np.linalg.inv(g.Lambda.cpu().numpy()), Sig, rtol=1e-8,
+                               atol=1e-10)
+    assert g.f == pytest.approx(9 + np.linalg.slogdet(Sig)[1], rel=1e-12)
+
+
+def test_csr_output_matches_dense(cg):
+    pr = synth.chain_problem(p=45, q=38, n=70, density=0.05, lam=0.1, seed=14)
+    g = cg.cggm_solve(dev(pr.X), dev(pr.Y), pr.lam_Lambda, pr.lam_Theta, tol=1e-3,
+                      max_iter=500, keep_csr=True)
+    import scipy.sparse as sp
+    (Lr, Lc, Lv), (Tr, Tc, Tv) = g.csr
+    L = sp.csr_matrix((Lv, Lc, Lr), shape=(38, 38)).toarray()
+    T = sp.csr_matrix((Tv, Tc, Tr), shape=(45, 38)).toarray()
+    assert np.array_equal(L, g.Lambda.cpu().numpy())
+    assert np.array_equal(T, g.Theta.cpu().numpy())
+    assert g.nnz_Lambda == np.count_nonzero(L) and g.nnz_Theta == np.count_nonzero(T)
+
+
+def test_error_paths_on_device(cg):
+    X, Y = random_problem(6, 5, 20, seed=15)
+    Xbad = X.copy()
+    Xbad[3, 2] = np.nan
+    with pytest.raises(cg.CggmError) as ei:
+        cg.cggm_solve(dev(Xbad), dev(Y), 0.1, 0.1)
+    assert ei.value.code == cg.CGGM_EINVAL
+    warm = -np.eye(5)
+    with pytest.raises(cg.CggmError) as ei:
+        cg.cggm_solve(dev(X), dev(Y), 0.1, 0.1, warm_Lambda=dev(warm))
+    assert ei.value.code == cg.CGGM_ENOTPD
+    with pytest.raises(cg.CggmError) as ei:
+        cg.cggm_solve(dev(X), dev(Y), 0.1, 0.1, workspace_budget=1024)
+    assert ei.value.code == cg.CGGM_ENOMEM
+    r = cg.cggm_solve(dev(X), dev(Y), 0.1, 0.1, tol=0.0, max_iter=2, stall_iters=0)
+    assert r.status == cg.CGGM_MAXITER and r.iters == 2
