@@ -1,5 +1,5 @@
 // device_common.hpp -- device-side building blocks shared by the kernels of the
-// gfx950 CGGM solver: the FP64 MFMA 64x64 tile product, wave-level helpers and
+// gfx950 CGGM solver: the FP64 MFMA tile product, wave-level helpers and
 // the soft-threshold operator.
 #pragma once
 
@@ -17,7 +17,7 @@ constexpr int LDS_PAD = 2;      // row padding (doubles) of the staged chunks
 
 // One v_mfma_f64_16x16x4_f64: D(16x16) += A(16x4) B(4x16).
 // Operand layout per lane l: A[l % 16][l / 16], B[l / 16][l % 16];
-// result element r of lane l is D[4 * (l / 16) + r][l % 16].
+// result element r of lane l is D[l / 16 + 4 * r][l % 16].
 __device__ __forceinline__ v4d mfma_f64_16x16x4(double a, double b, v4d c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
@@ -48,7 +48,7 @@ struct WaveAcc {
 // `lane` in wave `wid`.
 template <int TS>
 __device__ __forceinline__ int acc_row(int wid, int lane, int i, int r) {
-    return (wid >> 1) * (TS / 2) + i * 16 + 4 * (lane >> 4) + r;
+    return (wid >> 1) * (TS / 2) + i * 16 + (lane >> 4) + 4 * r;
 }
 template <int TS>
 __device__ __forceinline__ int acc_col(int wid, int lane, int j) {
