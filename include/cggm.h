@@ -73,6 +73,20 @@ typedef struct {
     double ms_theta_cd;   /* V = Theta Sigma and the Theta sweep                 */
 } cggm_trace_entry;
 
+/* Launch statistics of the two coordinate-descent tile kernels, filled when
+ * options.kstats is non-NULL.  Durations come from HIP events recorded on the
+ * solve's stream around every launch; bytes and flops are the algorithmic
+ * traffic and arithmetic of the tiles that had active coordinates (operand
+ * slabs of the gradient snapshot, the tile's Sigma / Psi / Sxx blocks, the
+ * tile's gradient and parameter reads and its writes), counted on the device. */
+typedef struct {
+    int64_t launches[2];        /* [0] Lambda tile kernel, [1] Theta tile kernel   */
+    int64_t tiles[2];           /* tiles processed (with active coordinates)       */
+    double ms[2];               /* summed launch durations                         */
+    double bytes[2];            /* summed algorithmic bytes                        */
+    double flops[2];            /* summed algorithmic flops                        */
+} cggm_kernel_stats;
+
 typedef struct {
     int max_iter;          /* outer iterations (default 500)                   */
     int max_ls;            /* line-search trials (default 30)                  */
@@ -89,6 +103,7 @@ typedef struct {
     cggm_trace_entry *trace;   /* host array of trace_cap records, or NULL     */
     int trace_cap;
     int trace_len;             /* out: records written                          */
+    cggm_kernel_stats *kstats; /* out: CD tile-kernel statistics, or NULL        */
 } cggm_options;
 
 /* Fill `opt` with the defaults above. */

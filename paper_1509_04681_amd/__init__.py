@@ -40,6 +40,12 @@ class TraceEntry(ctypes.Structure):
                 ("ms_theta_cd", ctypes.c_double)]
 
 
+class KernelStats(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64 * 2), ("tiles", ctypes.c_int64 * 2),
+                ("ms", ctypes.c_double * 2), ("bytes", ctypes.c_double * 2),
+                ("flops", ctypes.c_double * 2)]
+
+
 class Options(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int), ("max_ls", ctypes.c_int),
                 ("ls_beta", ctypes.c_double), ("ls_sigma", ctypes.c_double),
@@ -48,7 +54,7 @@ class Options(ctypes.Structure):
                 ("workspace_budget", ctypes.c_size_t),
                 ("warm_Lambda", _vp), ("warm_Theta", _vp),
                 ("trace", ctypes.POINTER(TraceEntry)), ("trace_cap", ctypes.c_int),
-                ("trace_len", ctypes.c_int)]
+                ("trace_len", ctypes.c_int), ("kstats", ctypes.POINTER(KernelStats))]
 
 
 class CggmError(RuntimeError):
@@ -142,6 +148,9 @@ class SolveResult:
     nnz_Lambda: int
     nnz_Theta: int
     trace: list
+    # CD tile-kernel launch statistics when cggm_solve(..., kernel_stats=True):
+    # {"lambda_tile"|"theta_tile": {launches, tiles, ms, bytes, flops}}
+    kernel_stats: dict | None = None
     # host CSR ((rowptr, col, val) of Lambda (full symmetric), same of Theta)
     # when cggm_solve(..., keep_csr=True)
     csr: tuple | None = None
@@ -151,7 +160,8 @@ def cggm_solve(X, Y, lam_Lambda: float, lam_Theta: float, tol: float = 1e-2, *,
                max_iter: int = 500, max_ls: int = 30, ls_beta: float = 0.5,
                ls_sigma: float = 1e-3, stall_iters: int = 3, sweep: int = CGGM_SWEEP_TILED,
                tile: int = 0, workspace_budget: int = 0, warm_Lambda=None, warm_Theta=None,
-               trace_cap: int | None = None, keep_csr: bool = False, stream=None) -> SolveResult:
+               trace_cap: int | None = None, keep_csr: bool = False, kernel_stats: bool = False,
+               stream=None) -> SolveResult:
     """Alternating Newton CD (Algorithm 1) on device X (n x p) and Y (n x q), float64."""
     import torch
     lib = load()
@@ -170,6 +180,9 @@ def cggm_solve(X, Y, lam_Lambda: float, lam_Theta: float, tol: float = 1e-2, *,
     trace_buf = (TraceEntry * max(cap, 1))()
     opt.trace = ctypes.cast(trace_buf, ctypes.POINTER(TraceEntry)) if cap > 0 else None
     opt.trace_cap = cap
+    ks = KernelStats() if kernel_stats else None
+    if ks is not None:
+        opt.kstats = ctypes.pointer(ks)
     res = ctypes.c_void_p()
     code = lib.cggm_solve(_dev(X, "X"), _dev(Y, "Y"), n, p, q, float(lam_Lambda),
                           float(lam_Theta), float(tol), ctypes.byref(opt), ctypes.byref(res),
@@ -197,8 +210,14 @@ def cggm_solve(X, Y, lam_Lambda: float, lam_Theta: float, tol: float = 1e-2, *,
         lib.cggm_result_free(res)
     trace = [{k: getattr(trace_buf[i], k) for k, _ in TraceEntry._fields_ if k != "_pad"}
              for i in range(opt.trace_len)]
+    kst = None
+    if ks is not None:
+        kst = {name: {"launches": ks.launches[k], "tiles": ks.tiles[k], "ms": ks.ms[k],
+                      "bytes": ks.bytes[k], "flops": ks.flops[k]}
+               for k, name in enumerate(("lambda_tile", "theta_tile"))}
     return SolveResult(Lambda=Lam, Theta=Th, f=f.value, iters=it.value, status=st.value,
-                       nnz_Lambda=nL.value, nnz_Theta=nT.value, trace=trace, csr=csr)
+                       nnz_Lambda=nL.value, nnz_Theta=nT.value, trace=trace, csr=csr,
+                       kernel_stats=kst)
 
 
 def cggm_objective(X, Y, Lambda, Theta, lam_Lambda: float, lam_Theta: float,

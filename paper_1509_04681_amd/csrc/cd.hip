@@ -38,7 +38,8 @@ __global__ __launch_bounds__(BLOCK) void theta_tile_kernel(
     const TileRect *__restrict__ rects, int64_t p, int64_t q, const double *__restrict__ Sxx,
     const double *__restrict__ Sxy, const double *__restrict__ Sigma,
     const double *__restrict__ V, const double *__restrict__ GT, double *__restrict__ Theta,
-    double lamT, double *__restrict__ dT, int *__restrict__ changed) {
+    double lamT, double *__restrict__ dT, int *__restrict__ changed,
+    unsigned long long *__restrict__ counters) {
     const int e = blockIdx.x;
     const TileRect rc = rects[e];
     const int R = rc.r1 - rc.r0, C = rc.c1 - rc.c0;
@@ -58,6 +59,13 @@ __global__ __launch_bounds__(BLOCK) void theta_tile_kernel(
         return;
     }
 
+    if (counters && tid == 0) {
+        // slabs Sxx[:, I], V[:, J]; blocks Sxx[I, I], Sigma[J, J]; Sxy, G, Theta
+        // tile reads; Theta and delta writes
+        atomicAdd(counters + 0, 1ull);
+        atomicAdd(counters + 1, (unsigned long long)(8 * (p * (R + C) + R * R + C * C + 5 * R * C)));
+        atomicAdd(counters + 2, (unsigned long long)(2 * (int64_t)R * C * p + 4 * (int64_t)R * C * C));
+    }
     __shared__ TileSmem<T> sm;
     __shared__ double Bs[T][LD];    // gradient snapshot, then corrected in place
     __shared__ double sxx[T][LD];   // Sxx[I, I]
@@ -179,7 +187,7 @@ __global__ __launch_bounds__(BLOCK) void lambda_tile_kernel(
     const double *__restrict__ Psi, const double *__restrict__ SP,
     const double *__restrict__ GL, const double *__restrict__ Lam, double lamL,
     double *__restrict__ D, const double *__restrict__ U, double *__restrict__ dD,
-    int *__restrict__ changed) {
+    int *__restrict__ changed, unsigned long long *__restrict__ counters) {
     const int e = blockIdx.x;
     const TileRect rc = rects[e];
     const int R = rc.r1 - rc.r0, C = rc.c1 - rc.c0;
@@ -199,6 +207,14 @@ __global__ __launch_bounds__(BLOCK) void lambda_tile_kernel(
         return;
     }
 
+    if (counters && tid == 0) {
+        // slabs SP[:, I], U[:, J], U[:, I], Psi[:, J]; six Sigma / Psi blocks;
+        // G and Lambda tile reads; D (both triangles) and delta writes
+        atomicAdd(counters + 0, 1ull);
+        atomicAdd(counters + 1, (unsigned long long)(8 * (2 * q * (R + C) + 2 * R * R + 2 * C * C +
+                                                         7 * R * C)));
+        atomicAdd(counters + 2, (unsigned long long)(4 * (int64_t)R * C * q + 16 * (int64_t)R * C * C));
+    }
     __shared__ TileSmem<T> sm;
     __shared__ double Bs[T][LD];
     __shared__ double sII[T][LD], pII[T][LD], sJJ[T][LD], pJJ[T][LD], sIJ[T][LD], pIJ[T][LD];
@@ -361,11 +377,15 @@ __global__ __launch_bounds__(BLOCK) void lambda_u_update_kernel(
 
 void theta_wave(hipStream_t s, const TileRect *rects_dev, int nrect, int64_t p, int64_t q,
                 const double *Sxx, const double *Sxy, const double *Sigma, double *V,
-                const double *GT, double *Theta, double lamT, double *dT, int *changed) {
+                const double *GT, double *Theta, double lamT, double *dT, int *changed,
+                const WaveProbe *probe) {
     if (nrect <= 0) return;
+    if (probe) CGGM_HIP(hipEventRecord(probe->start, s));
     theta_tile_kernel<<<nrect, BLOCK, 0, s>>>(rects_dev, p, q, Sxx, Sxy, Sigma, V, GT, Theta,
-                                              lamT, dT, changed);
+                                              lamT, dT, changed,
+                                              probe ? probe->counters : nullptr);
     CGGM_LAUNCH_CHECK();
+    if (probe) CGGM_HIP(hipEventRecord(probe->stop, s));
     dim3 grid((unsigned)((q + T - 1) / T), (unsigned)nrect);
     theta_v_update_kernel<<<grid, BLOCK, 0, s>>>(rects_dev, q, Sigma, dT, changed, V);
     CGGM_LAUNCH_CHECK();
@@ -374,11 +394,13 @@ void theta_wave(hipStream_t s, const TileRect *rects_dev, int nrect, int64_t p, 
 void lambda_wave(hipStream_t s, const TileRect *rects_dev, int nrect, int64_t q,
                  const double *Sigma, const double *Psi, const double *SP, const double *GL,
                  const double *Lam, double lamL, double *D, double *U, double *dD,
-                 int *changed) {
+                 int *changed, const WaveProbe *probe) {
     if (nrect <= 0) return;
+    if (probe) CGGM_HIP(hipEventRecord(probe->start, s));
     lambda_tile_kernel<<<nrect, BLOCK, 0, s>>>(rects_dev, q, Sigma, Psi, SP, GL, Lam, lamL, D, U,
-                                               dD, changed);
+                                               dD, changed, probe ? probe->counters : nullptr);
     CGGM_LAUNCH_CHECK();
+    if (probe) CGGM_HIP(hipEventRecord(probe->stop, s));
     dim3 grid((unsigned)((q + T - 1) / T), (unsigned)nrect, 2);
     lambda_u_update_kernel<<<grid, BLOCK, 0, s>>>(rects_dev, q, Sigma, dD, changed, U);
     CGGM_LAUNCH_CHECK();

@@ -198,6 +198,7 @@ struct Work {
     double *dT, *dD;                               // per-wave tile deltas
     double *partials, *scal;                       // reduction scratch, device scalars
     int *flag, *changed;
+    unsigned long long *kctr;                      // tile-kernel counters [2][3]
     TileRect *rects_theta, *rects_lambda;
     int max_tiles = 0;
 };
@@ -237,6 +238,7 @@ void layout(Arena &a, Work &w, int64_t n, int64_t p, int64_t q, int64_t ntheta_r
     w.scal = a.take<double>(NSCAL);
     w.flag = a.take<int>(4);
     w.changed = a.take<int>(max_tiles);
+    w.kctr = a.take<unsigned long long>(6);
     w.rects_theta = a.take<TileRect>(ntheta_rects);
     w.rects_lambda = a.take<TileRect>(nlambda_rects);
 }
@@ -327,23 +329,64 @@ TopStats read_top(Ctx &c, bool with_gradient_stats) {
     return t;
 }
 
-void run_theta_sweep(Ctx &c, const Schedule &sch) {
+// HIP-event timing of one tile kernel kind (one event pair per wave launch).
+struct KernelTimer {
+    std::vector<hipEvent_t> ev;
+    unsigned long long *counters = nullptr;
+    int pending = 0;
+    int64_t launches = 0;
+    double ms = 0.0;
+    void init(int waves, unsigned long long *ctr) {
+        counters = ctr;
+        ev.resize(2 * (size_t)waves, nullptr);
+        for (auto &e : ev) CGGM_HIP(hipEventCreate(&e));
+    }
+    ~KernelTimer() {
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+    bool on() const { return !ev.empty(); }
+    WaveProbe probe(int k) {
+        WaveProbe p;
+        p.start = ev[2 * k];
+        p.stop = ev[2 * k + 1];
+        p.counters = counters;
+        pending = k + 1;
+        return p;
+    }
+    // Sum the durations of the recorded launches (their events must be done).
+    void collect() {
+        for (int k = 0; k < pending; ++k) {
+            float m = 0.f;
+            CGGM_HIP(hipEventElapsedTime(&m, ev[2 * k], ev[2 * k + 1]));
+            ms += m;
+            ++launches;
+        }
+        pending = 0;
+    }
+};
+
+void run_theta_sweep(Ctx &c, const Schedule &sch, KernelTimer *kt = nullptr) {
     Work &w = c.w;
     for (int k = 0; k < sch.waves(); ++k) {
         const int b = sch.wave_start[k], e = sch.wave_start[k + 1];
+        WaveProbe pr;
+        if (kt && kt->on()) pr = kt->probe(k);
         theta_wave(c.s, w.rects_theta + b, e - b, w.p, w.q, w.Sxx, w.Sxy, w.Sig, w.V, w.GT,
-                   w.Th, c.lamT, w.dT, w.changed);
+                   w.Th, c.lamT, w.dT, w.changed, (kt && kt->on()) ? &pr : nullptr);
     }
 }
 
-void run_lambda_sweep(Ctx &c, const Schedule &sch) {
+void run_lambda_sweep(Ctx &c, const Schedule &sch, KernelTimer *kt = nullptr) {
     Work &w = c.w;
     fill(c.s, w.q * w.q, 0.0, w.D);
     fill(c.s, w.q * w.q, 0.0, w.U);
     for (int k = 0; k < sch.waves(); ++k) {
         const int b = sch.wave_start[k], e = sch.wave_start[k + 1];
+        WaveProbe pr;
+        if (kt && kt->on()) pr = kt->probe(k);
         lambda_wave(c.s, w.rects_lambda + b, e - b, w.q, w.Sig, w.Psi, w.SP, w.GL, w.Lam,
-                    c.lamL, w.D, w.U, w.dD, w.changed);
+                    c.lamL, w.D, w.U, w.dD, w.changed, (kt && kt->on()) ? &pr : nullptr);
     }
 }
 
@@ -467,6 +510,12 @@ int solve_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q
     Ctx c{s, w, lamL, lamT};
     const int64_t qq = q * q, pq = p * q;
     check_finite(c, X, Y);
+    KernelTimer kt_lambda, kt_theta;
+    if (opt.kstats) {
+        fill(s, 6, 0.0, reinterpret_cast<double *>(w.kctr));   // all-zero bits
+        kt_lambda.init(la_sched.waves(), w.kctr);
+        kt_theta.init(th_sched.waves(), w.kctr + 3);
+    }
 
     auto t0 = std::chrono::steady_clock::now();
     auto ms_since = [&](std::chrono::steady_clock::time_point a) {
@@ -522,6 +571,7 @@ int solve_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q
         reduce_top_stats(s, q, q, w.Syy, w.Syy, w.Lam, lamL, 1, w.partials, w.scal + S_LAM);
         reduce_logdet(s, q, w.L, w.partials, w.scal + S_LOGDET);
         TopStats pre = read_top(c, false);
+        kt_theta.collect();                       // the last Theta sweep is done
         if (t > 0 && pre.f > f_after_ls + F_ROUNDING * std::max(1.0, fabs(f_after_ls))) {
             // Descent guard: the concurrent tiles of the Theta sweep raised f.
             // Redo the sweep one tile per wave (exact block Gauss-Seidel).
@@ -593,11 +643,12 @@ int solve_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q
 
         // ---- Lambda: Newton direction by one CD pass, Armijo line search ----
         CGGM_HIP(hipEventRecord(ev[2], s));
-        run_lambda_sweep(c, la_sched);
+        run_lambda_sweep(c, la_sched, &kt_lambda);
         reduce_direction(s, q, w.GL, w.Lam, w.D, w.partials, w.scal + S_DIR);
         double hd[2];
         CGGM_HIP(hipMemcpyAsync(hd, w.scal + S_DIR, sizeof(hd), hipMemcpyDeviceToHost, s));
         CGGM_HIP(hipStreamSynchronize(s));
+        kt_lambda.collect();
         double delta = hd[0] + lamL * hd[1];
         if (!(delta < 0.0) && !seq) {
             // Descent guard: redo the direction one tile per wave.
@@ -665,10 +716,26 @@ int solve_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q
         // ---- Theta: one CD pass on Eq. (7) with Sigma of the new Lambda ----
         CGGM_HIP(hipMemcpyAsync(w.ThOld, w.Th, sizeof(double) * pq, hipMemcpyDeviceToDevice, s));
         gemm(s, false, false, p, q, q, 1.0, w.Th, q, w.Sig, q, 0.0, w.V, q);   // V = Theta Sigma
-        run_theta_sweep(c, th_sched);
+        run_theta_sweep(c, th_sched, &kt_theta);
         theta_products(c, X);
     }
     opt.trace_len = trace_len;
+    if (opt.kstats) {
+        CGGM_HIP(hipStreamSynchronize(s));
+        kt_theta.collect();
+        unsigned long long h[6];
+        CGGM_HIP(hipMemcpy(h, w.kctr, sizeof(h), hipMemcpyDeviceToHost));
+        cggm_kernel_stats &ks = *opt.kstats;
+        ks.launches[0] = kt_lambda.launches;
+        ks.launches[1] = kt_theta.launches;
+        ks.ms[0] = kt_lambda.ms;
+        ks.ms[1] = kt_theta.ms;
+        for (int k = 0; k < 2; ++k) {
+            ks.tiles[k] = (int64_t)h[3 * k];
+            ks.bytes[k] = (double)h[3 * k + 1];
+            ks.flops[k] = (double)h[3 * k + 2];
+        }
+    }
     if (opt_in) opt_in->trace_len = trace_len;
 
     auto *res = new ResultImpl();

@@ -122,13 +122,21 @@ struct TileRect {
 
 constexpr int CD_TILE = 32;   // maximum tile edge of a CD tile
 
+// Optional instrumentation of a wave: events recorded around the tile kernel
+// and device counters (processed tiles, algorithmic bytes, flops) it adds to.
+struct WaveProbe {
+    hipEvent_t start = nullptr, stop = nullptr;
+    unsigned long long *counters = nullptr;   // [3]
+};
+
 // One wave of the Theta sweep: every rect in `rects` (row- and column-disjoint)
 // runs exact Gauss-Seidel over its active coordinates from a snapshot of
 // b = 2 Sxy + 2 Sxx V, writes the updated Theta and its delta (dT, nrect
 // tiles of CD_TILE^2), then V[rows, :] += dTheta Sigma[cols, :].
 void theta_wave(hipStream_t s, const TileRect *rects_dev, int nrect, int64_t p, int64_t q,
                 const double *Sxx, const double *Sxy, const double *Sigma, double *V,
-                const double *GT, double *Theta, double lamT, double *dT, int *changed);
+                const double *GT, double *Theta, double lamT, double *dT, int *changed,
+                const WaveProbe *probe = nullptr);
 
 // One wave of the Lambda direction sweep over upper-triangle rects with
 // pairwise-disjoint index sets: exact Gauss-Seidel inside each rect from a
@@ -137,6 +145,6 @@ void theta_wave(hipStream_t s, const TileRect *rects_dev, int nrect, int64_t p, 
 void lambda_wave(hipStream_t s, const TileRect *rects_dev, int nrect, int64_t q,
                  const double *Sigma, const double *Psi, const double *SP, const double *GL,
                  const double *Lam, double lamL, double *D, double *U, double *dD,
-                 int *changed);
+                 int *changed, const WaveProbe *probe = nullptr);
 
 }  // namespace cggm
