@@ -66,28 +66,24 @@ __global__ __launch_bounds__(BLOCK) void theta_tile_kernel(
         atomicAdd(counters + 1, (unsigned long long)(8 * (p * (R + C) + R * R + C * C + 5 * R * C)));
         atomicAdd(counters + 2, (unsigned long long)(2 * (int64_t)R * C * p + 4 * (int64_t)R * C * C));
     }
-    __shared__ TileSmem<T> sm;
     __shared__ double Bs[T][LD];    // gradient snapshot, then corrected in place
-    __shared__ double sxx[T][LD];   // Sxx[I, I]
-    __shared__ double sig[T][LD];   // Sigma[J, J]
+    __shared__ union {
+        SlabRed red;
+        struct {
+            double sxx[T][LD];      // Sxx[I, I]
+            double sig[T][LD];      // Sigma[J, J]
+        } b;
+    } sh;
+    auto &sxx = sh.b.sxx;
+    auto &sig = sh.b.sig;
 
-    WaveAcc<T> acc;
-    acc.zero();
     // (Sxx V)[I, J] = Sxx[:, I]^T V[:, J]  (Sxx symmetric)
-    tile_mma<true, false, T>(Sxx + rc.r0, p, V + rc.c0, q, 0, 0, R, C, 0, p, sm, acc);
-#pragma unroll
-    for (int i = 0; i < WaveAcc<T>::NB; ++i)
-#pragma unroll
-        for (int j = 0; j < WaveAcc<T>::NB; ++j)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = acc_row<T>(wid, lane, i, r), col = acc_col<T>(wid, lane, j);
-                if (row < R && col < C)
-                    Bs[row][col] = 2.0 * Sxy[(int64_t)(rc.r0 + row) * q + rc.c0 + col] +
-                                   2.0 * acc.c[i][j][r];
-            }
+    const SlabPair pr[1] = {{Sxx + rc.r0, p, V + rc.c0, q}};
+    slab_product_32<1>(pr, p, R, C, sh.red, Bs);
     for (int k = tid; k < T * T; k += BLOCK) {
         const int r = k / T, c = k % T;
+        if (r < R && c < C) Bs[r][c] = 2.0 * Sxy[(int64_t)(rc.r0 + r) * q + rc.c0 + c] +
+                                       2.0 * Bs[r][c];
         sxx[r][c] = (r < R && c < R) ? Sxx[(int64_t)(rc.r0 + r) * p + rc.r0 + c] : 0.0;
         sig[r][c] = (r < C && c < C) ? Sigma[(int64_t)(rc.c0 + r) * q + rc.c0 + c] : 0.0;
     }
@@ -215,28 +211,28 @@ __global__ __launch_bounds__(BLOCK) void lambda_tile_kernel(
                                                          7 * R * C)));
         atomicAdd(counters + 2, (unsigned long long)(4 * (int64_t)R * C * q + 16 * (int64_t)R * C * C));
     }
-    __shared__ TileSmem<T> sm;
     __shared__ double Bs[T][LD];
-    __shared__ double sII[T][LD], pII[T][LD], sJJ[T][LD], pJJ[T][LD], sIJ[T][LD], pIJ[T][LD];
+    __shared__ union {
+        SlabRed red;
+        struct {
+            double sII[T][LD], pII[T][LD], sJJ[T][LD], pJJ[T][LD], sIJ[T][LD], pIJ[T][LD];
+        } b;
+    } sh;
+    auto &sII = sh.b.sII;
+    auto &pII = sh.b.pII;
+    auto &sJJ = sh.b.sJJ;
+    auto &pJJ = sh.b.pJJ;
+    auto &sIJ = sh.b.sIJ;
+    auto &pIJ = sh.b.pIJ;
 
-    WaveAcc<T> acc;
-    acc.zero();
     // b snapshot: G + (SP U)[I, J] + ((Psi U)[J, I])^T
-    tile_mma<true, false, T>(SP + rc.r0, q, U + rc.c0, q, 0, 0, R, C, 0, q, sm, acc);
-    tile_mma<true, false, T>(U + rc.r0, q, Psi + rc.c0, q, 0, 0, R, C, 0, q, sm, acc);
-#pragma unroll
-    for (int i = 0; i < WaveAcc<T>::NB; ++i)
-#pragma unroll
-        for (int j = 0; j < WaveAcc<T>::NB; ++j)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = acc_row<T>(wid, lane, i, r), col = acc_col<T>(wid, lane, j);
-                if (row < R && col < C)
-                    Bs[row][col] = GL[(int64_t)(rc.r0 + row) * q + rc.c0 + col] + acc.c[i][j][r];
-            }
+    //   = G + SP[:, I]^T U[:, J] + U[:, I]^T Psi[:, J]   (SP, Psi symmetric)
+    const SlabPair pr[2] = {{SP + rc.r0, q, U + rc.c0, q}, {U + rc.r0, q, Psi + rc.c0, q}};
+    slab_product_32<2>(pr, q, R, C, sh.red, Bs);
     for (int k = tid; k < T * T; k += BLOCK) {
         const int r = k / T, c = k % T;
         const bool ii = r < R && c < R, jj = r < C && c < C, ij = r < R && c < C;
+        if (ij) Bs[r][c] += GL[(int64_t)(rc.r0 + r) * q + rc.c0 + c];
         sII[r][c] = ii ? Sigma[(int64_t)(rc.r0 + r) * q + rc.r0 + c] : 0.0;
         pII[r][c] = ii ? Psi[(int64_t)(rc.r0 + r) * q + rc.r0 + c] : 0.0;
         sJJ[r][c] = jj ? Sigma[(int64_t)(rc.c0 + r) * q + rc.c0 + c] : 0.0;

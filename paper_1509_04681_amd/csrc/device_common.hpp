@@ -107,6 +107,82 @@ __device__ void tile_mma(const double *__restrict__ A, int64_t lda,
     }
 }
 
+// One operand pair of a column-slab product: A[k][a0 + m] (m < ma) and
+// B[k][b0 + n] (n < nb), k in [0, K), row-major with leading dims lda, ldb.
+struct SlabPair {
+    const double *A;
+    int64_t lda;
+    const double *B;
+    int64_t ldb;
+};
+
+// Partial sums of the four waves of a 32 x 32 slab product (LDS).
+struct SlabRed {
+    double part[4][32][33];
+};
+
+// out[m][n] = sum over the pairs P of sum_k P.A[k][m] P.B[k][n], for a 32 x 32
+// output (entries m >= ma or n >= nb are zero).  The K range is split into
+// four contiguous quarters, one per wave; each wave loads its MFMA operands
+// directly from global memory (16 consecutive doubles per operand row,
+// UNROLL k-steps in flight) and accumulates the whole 32 x 32 tile as 2 x 2
+// MFMA blocks; the four partial tiles are summed through LDS.  All 256
+// threads must call it; on return `out` is complete (a barrier is included).
+template <int NPAIR>
+__device__ void slab_product_32(const SlabPair (&pairs)[NPAIR], int64_t K, int ma, int nb,
+                                SlabRed &red, double (*out)[33]) {
+    constexpr int UNROLL = 8;
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
+    const int64_t ksteps = (K + 3) / 4;
+    const int64_t s0 = (ksteps * wid) / 4, s1 = (ksteps * (wid + 1)) / 4;
+    const int col = lane & 15, krow = lane >> 4;
+    v4d acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    const bool am0 = col < ma, am1 = col + 16 < ma, bn0 = col < nb, bn1 = col + 16 < nb;
+#pragma unroll
+    for (int pp = 0; pp < NPAIR; ++pp) {
+        const SlabPair P = pairs[pp];
+        for (int64_t st = s0; st < s1; st += UNROLL) {
+            double a[UNROLL][2], b[UNROLL][2];
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) {
+                const int64_t k = (st + u) * 4 + krow;
+                const bool kv = (st + u) < s1 && k < K;
+                const double *ar = P.A + k * P.lda;
+                const double *br = P.B + k * P.ldb;
+                a[u][0] = (kv && am0) ? ar[col] : 0.0;
+                a[u][1] = (kv && am1) ? ar[col + 16] : 0.0;
+                b[u][0] = (kv && bn0) ? br[col] : 0.0;
+                b[u][1] = (kv && bn1) ? br[col + 16] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u)
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        acc[i][j] = mfma_f64_16x16x4(a[u][i], b[u][j], acc[i][j]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                red.part[wid][i * 16 + krow + 4 * r][j * 16 + col] = acc[i][j][r];
+    __syncthreads();
+    for (int e = tid; e < 32 * 32; e += BLOCK) {
+        const int m = e >> 5, n = e & 31;
+        out[m][n] = red.part[0][m][n] + red.part[1][m][n] + red.part[2][m][n] +
+                    red.part[3][m][n];
+    }
+    __syncthreads();
+}
+
 // Broadcast a double from `lane` (wave-uniform index) to the whole wave.
 __device__ __forceinline__ double readlane_f64(double v, int lane) {
     int64_t bits = __double_as_longlong(v);

@@ -193,6 +193,7 @@ struct Work {
     int64_t n = 0, p = 0, q = 0;
     double *Sxx, *Sxy, *Syy;                       // statistics
     double *Lam, *LamT, *L, *Lt, *Sig, *Psi, *SP, *GL, *D, *U;   // q x q
+    double *Wd, *Wdt;                              // diagonal-block inverses of L, Lt
     double *Th, *ThOld, *GT, *V;                   // p x q
     double *A, *R, *At, *Zt;                       // n x q, q x n
     double *dT, *dD;                               // per-wave tile deltas
@@ -223,6 +224,8 @@ void layout(Arena &a, Work &w, int64_t n, int64_t p, int64_t q, int64_t ntheta_r
     w.GL = a.take<double>(qq);
     w.D = a.take<double>(qq);
     w.U = a.take<double>(qq);
+    w.Wd = a.take<double>(diag_inv_count(q));
+    w.Wdt = a.take<double>(diag_inv_count(q));
     w.Th = a.take<double>(pq);
     w.ThOld = a.take<double>(pq);
     w.GT = a.take<double>(pq);
@@ -539,13 +542,13 @@ int solve_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q
     }
     CGGM_HIP(hipMemcpyAsync(w.L, w.Lam, sizeof(double) * qq, hipMemcpyDeviceToDevice, s));
     set_int(s, w.flag, 0);
-    cholesky_inplace(s, q, w.L, w.flag);
+    cholesky_inplace(s, q, w.L, w.flag, w.Wd);
     reduce_logdet(s, q, w.L, w.partials, w.scal + S_LOGDET);
     int hflag = 0;
     CGGM_HIP(hipMemcpyAsync(&hflag, w.flag, sizeof(int), hipMemcpyDeviceToHost, s));
     CGGM_HIP(hipStreamSynchronize(s));
     if (hflag) fail(CGGM_ENOTPD, "the warm-start Lambda is not positive definite");
-    spd_inverse_from_cholesky(s, q, w.L, w.U, w.Sig);
+    spd_inverse_from_cholesky(s, q, w.L, w.Wd, w.U, w.Sig);
     theta_products(c, X);
 
     hipEvent_t ev[5];
@@ -672,11 +675,11 @@ int solve_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q
                 CGGM_HIP(hipMemcpyAsync(w.Lt, w.LamT, sizeof(double) * qq,
                                         hipMemcpyDeviceToDevice, s));
                 set_int(s, w.flag, 0);
-                cholesky_inplace(s, q, w.Lt, w.flag);
+                cholesky_inplace(s, q, w.Lt, w.flag, w.Wdt);
                 reduce_logdet(s, q, w.Lt, w.partials, w.scal + S_TLOGDET);
                 CGGM_HIP(hipMemcpyAsync(w.Zt, w.At, sizeof(double) * w.n * q,
                                         hipMemcpyDeviceToDevice, s));
-                trsm_lower_left(s, q, w.Lt, w.Zt, w.n, w.n, false);
+                trsm_lower_left(s, q, w.Lt, w.Wdt, w.Zt, w.n, w.n, false);
                 reduce_dot(s, q * w.n, w.Zt, w.Zt, w.partials, w.scal + S_ZZ);
                 double h[6];
                 int hf = 0;
@@ -699,6 +702,7 @@ int solve_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q
         if (accepted) {
             std::swap(w.Lam, w.LamT);
             std::swap(w.L, w.Lt);
+            std::swap(w.Wd, w.Wdt);
             ls_fail_streak = 0;
         } else if (delta < 0.0) {
             if (++ls_fail_streak >= 2) {
@@ -709,7 +713,7 @@ int solve_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q
         f_after_ls = f_acc;
         last_alpha = alpha;
         last_trials = trials;
-        spd_inverse_from_cholesky(s, q, w.L, w.U, w.Sig);
+        spd_inverse_from_cholesky(s, q, w.L, w.Wd, w.U, w.Sig);
         CGGM_HIP(hipEventRecord(ev[4], s));
         have_phase = true;
 
@@ -758,7 +762,7 @@ int solve_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q
 // ------------------------------------------------------- objective/gradient --
 // Workspace for the standalone evaluations.
 struct EvalWork {
-    double *A, *R, *At, *L, *Sig, *Psi, *Work, *YL, *partials, *scal;
+    double *A, *R, *At, *L, *Wd, *Sig, *Psi, *Work, *YL, *partials, *scal;
     int *flag;
 };
 
@@ -767,6 +771,7 @@ void eval_layout(Arena &a, EvalWork &e, int64_t n, int64_t p, int64_t q, bool gr
     e.R = a.take<double>(n * q);
     e.At = a.take<double>(n * q);
     e.L = a.take<double>(q * q);
+    e.Wd = a.take<double>(diag_inv_count(q));
     e.Sig = gradient ? a.take<double>(q * q) : nullptr;
     e.Psi = gradient ? a.take<double>(q * q) : nullptr;
     e.Work = a.take<double>(q * q);
@@ -799,10 +804,10 @@ int objective_impl(const double *X, const double *Y, int64_t n, int64_t p, int64
     gemm(s, false, false, n, q, p, 1.0, X, p, Th, q, 0.0, e.A, q);
     CGGM_HIP(hipMemcpyAsync(e.L, Lam, sizeof(double) * q * q, hipMemcpyDeviceToDevice, s));
     set_int(s, e.flag, 0);
-    cholesky_inplace(s, q, e.L, e.flag);
+    cholesky_inplace(s, q, e.L, e.flag, e.Wd);
     reduce_logdet(s, q, e.L, e.partials, e.scal + 0);
     transpose(s, n, q, e.A, e.At);
-    trsm_lower_left(s, q, e.L, e.At, n, n, false);
+    trsm_lower_left(s, q, e.L, e.Wd, e.At, n, n, false);
     reduce_dot(s, q * n, e.At, e.At, e.partials, e.scal + 2);
     gemm(s, false, false, n, q, q, 1.0, Y, q, Lam, q, 0.0, e.YL, q);
     reduce_dot(s, n * q, Y, e.YL, e.partials, e.scal + 3);
@@ -841,7 +846,7 @@ int gradient_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_
     const double inv_n = 1.0 / (double)n;
     CGGM_HIP(hipMemcpyAsync(e.L, Lam, sizeof(double) * q * q, hipMemcpyDeviceToDevice, s));
     set_int(s, e.flag, 0);
-    cholesky_inplace(s, q, e.L, e.flag);
+    cholesky_inplace(s, q, e.L, e.flag, e.Wd);
     reduce_logdet(s, q, e.L, e.partials, e.scal);
     int hf = 0;
     double h[2];
@@ -849,7 +854,7 @@ int gradient_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_
     CGGM_HIP(hipMemcpyAsync(h, e.scal, sizeof(h), hipMemcpyDeviceToHost, s));
     CGGM_HIP(hipStreamSynchronize(s));
     if (hf || h[1] != 0.0) fail(CGGM_ENOTPD, "Lambda is not positive definite");
-    spd_inverse_from_cholesky(s, q, e.L, e.Work, e.Sig);
+    spd_inverse_from_cholesky(s, q, e.L, e.Wd, e.Work, e.Sig);
     gemm(s, false, false, n, q, p, 1.0, X, p, Th, q, 0.0, e.A, q);        // A = X Theta
     gemm(s, false, false, n, q, q, 1.0, e.A, q, e.Sig, q, 0.0, e.R, q);   // R = A Sigma
     gemm(s, true, false, q, q, n, inv_n, e.R, q, e.R, q, 0.0, e.Psi, q, UPLO_LOWER);

@@ -52,21 +52,29 @@ void set_identity(hipStream_t s, int64_t q, double *A);
 // dst (cols x rows) = src^T (src rows x cols).
 void transpose(hipStream_t s, int64_t rows, int64_t cols, const double *src, double *dst);
 
-// In-place blocked right-looking Cholesky of the lower triangle of A (q x q,
-// ld = q): on return the lower triangle holds L with A = L L^T.  *notpd_dev
-// (device int) is set to 1 when a pivot is not strictly positive.
-void cholesky_inplace(hipStream_t s, int64_t q, double *A, int *notpd_dev);
+// Panel width of the blocked factorizations; `Wd` arrays hold the inverses
+// of the diagonal PB x PB blocks of a Cholesky factor (diag_inv_count(q)
+// doubles).
+constexpr int PB = 64;
+inline int64_t diag_inv_count(int64_t q) { return ((q + PB - 1) / PB) * PB * PB; }
 
-// Solve L Z = B in place (B is q x m, leading dimension ldb, L lower q x q).
-// lower_rhs = true declares B lower triangular (B = I) so only the columns a
-// lower-triangular solution can populate are touched.
-void trsm_lower_left(hipStream_t s, int64_t q, const double *L, double *B, int64_t m,
-                     int64_t ldb, bool lower_rhs);
+// In-place blocked right-looking Cholesky of the lower triangle of A (q x q,
+// ld = q): on return the lower triangle holds L with A = L L^T and Wd the
+// inverses of its diagonal blocks.  *notpd_dev (device int) is set to 1 when a
+// pivot is not strictly positive.
+void cholesky_inplace(hipStream_t s, int64_t q, double *A, int *notpd_dev, double *Wd);
+
+// Solve L Z = B in place (B is q x m, leading dimension ldb, L lower q x q
+// with diagonal-block inverses Wd).  lower_rhs = true declares B lower
+// triangular (B = I) so only the columns a lower-triangular solution can
+// populate are touched.
+void trsm_lower_left(hipStream_t s, int64_t q, const double *L, const double *Wd, double *B,
+                     int64_t m, int64_t ldb, bool lower_rhs);
 
 // Sigma = (L L^T)^{-1} from the Cholesky factor: W = L^{-1} (into `work`,
 // q x q), then Sigma = W^T W (lower tiles, k from the row block) mirrored.
-void spd_inverse_from_cholesky(hipStream_t s, int64_t q, const double *L, double *work,
-                               double *Sigma);
+void spd_inverse_from_cholesky(hipStream_t s, int64_t q, const double *L, const double *Wd,
+                               double *work, double *Sigma);
 
 // Deterministic sums: each call reduces into `out[0..nv)` (device) through a
 // fixed-size partials buffer (device, >= REDUCE_BLOCKS * 8 doubles).

@@ -47,13 +47,34 @@ __global__ __launch_bounds__(BLOCK) void gemm_kernel(int64_t M, int64_t N, int64
 }
 
 // ------------------------------------------------------------ Cholesky ------
-constexpr int PB = 64;   // panel width of the blocked Cholesky / TRSM
+
+// W = L^{-1} of the nb x nb lower-triangular block in d (LDS), column c by
+// thread c (forward substitution on e_c), written to Wk (PB x PB, zero above
+// the diagonal and outside nb).
+__device__ void invert_lower_block(const double (*d)[PB + 1], double (*w)[PB + 1], int nb,
+                                   double *Wk) {
+    const int c = threadIdx.x;
+    if (c < nb) {
+        for (int i = c; i < nb; ++i) {
+            double s = (i == c) ? 1.0 : 0.0;
+            for (int m = c; m < i; ++m) s -= d[i][m] * w[m][c];
+            w[i][c] = s / d[i][i];
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < PB * PB; e += BLOCK) {
+        const int i = e / PB, j = e % PB;
+        Wk[e] = (i < nb && j <= i) ? w[i][j] : 0.0;
+    }
+}
 
 // Factor the diagonal block A[kb:kb+nb, kb:kb+nb] = L_kk L_kk^T in LDS (one
-// workgroup) and store L_kk in place; *notpd = 1 if a pivot is not positive.
+// workgroup), store L_kk in place and L_kk^{-1} in Wk (PB x PB); *notpd = 1 if
+// a pivot is not positive.
 __global__ __launch_bounds__(BLOCK) void potrf_diag_kernel(double *A, int64_t q, int64_t kb,
-                                                           int nb, int *notpd) {
+                                                           int nb, int *notpd, double *Wk) {
     __shared__ double d[PB][PB + 1];
+    __shared__ double w[PB][PB + 1];
     __shared__ int bad;
     const int tid = threadIdx.x;
     for (int e = tid; e < nb * nb; e += BLOCK) {
@@ -84,65 +105,7 @@ __global__ __launch_bounds__(BLOCK) void potrf_diag_kernel(double *A, int64_t q,
         if (j <= i) A[(kb + i) * q + kb + j] = d[i][j];
     }
     if (tid == 0 && bad) *notpd = 1;
-}
-
-// Panel below a factored diagonal block: each thread solves one row r,
-// L[r, kb:kb+PB] = A[r, kb:kb+PB] L_kk^{-T} (full-width panels only).
-__global__ __launch_bounds__(BLOCK) void potrf_panel_kernel(double *A, int64_t q, int64_t kb) {
-    __shared__ double d[PB][PB + 1];
-    const int tid = threadIdx.x;
-    for (int e = tid; e < PB * PB; e += BLOCK) {
-        const int i = e / PB, j = e % PB;
-        d[i][j] = (j <= i) ? A[(kb + i) * q + kb + j] : 0.0;
-    }
-    __syncthreads();
-    const int64_t r = kb + PB + (int64_t)blockIdx.x * BLOCK + tid;
-    if (r >= q) return;
-    double x[PB];
-    double *row = A + r * q + kb;
-#pragma unroll
-    for (int c = 0; c < PB; ++c) x[c] = row[c];
-#pragma unroll
-    for (int c = 0; c < PB; ++c) {
-        double s = x[c];
-#pragma unroll
-        for (int m = 0; m < c; ++m) s -= x[m] * d[c][m];
-        x[c] = s / d[c][c];
-    }
-#pragma unroll
-    for (int c = 0; c < PB; ++c) row[c] = x[c];
-}
-
-// Forward substitution of one diagonal block for the columns [0, ncols) of
-// B[kb:kb+nb, :]: B_k <- L_kk^{-1} B_k, one column per thread.
-__global__ __launch_bounds__(BLOCK) void trsm_diag_kernel(const double *L, int64_t q,
-                                                          int64_t kb, int nb, double *B,
-                                                          int64_t ldb, int64_t ncols) {
-    __shared__ double d[PB][PB + 1];
-    const int tid = threadIdx.x;
-    for (int e = tid; e < PB * PB; e += BLOCK) {
-        const int i = e / PB, j = e % PB;
-        double v;
-        if (i < nb && j < nb) v = (j <= i) ? L[(kb + i) * q + kb + j] : 0.0;
-        else v = (i == j) ? 1.0 : 0.0;
-        d[i][j] = v;
-    }
-    __syncthreads();
-    const int64_t c = (int64_t)blockIdx.x * BLOCK + tid;
-    if (c >= ncols) return;
-    double x[PB];
-#pragma unroll
-    for (int i = 0; i < PB; ++i) x[i] = (i < nb) ? B[(kb + i) * ldb + c] : 0.0;
-#pragma unroll
-    for (int i = 0; i < PB; ++i) {
-        double s = x[i];
-#pragma unroll
-        for (int m = 0; m < i; ++m) s -= d[i][m] * x[m];
-        x[i] = s / d[i][i];
-    }
-#pragma unroll
-    for (int i = 0; i < PB; ++i)
-        if (i < nb) B[(kb + i) * ldb + c] = x[i];
+    invert_lower_block(d, w, nb, Wk);
 }
 
 // ---------------------------------------------------------- elementwise -----
@@ -358,15 +321,17 @@ void transpose(hipStream_t s, int64_t rows, int64_t cols, const double *src, dou
     CGGM_LAUNCH_CHECK();
 }
 
-void cholesky_inplace(hipStream_t s, int64_t q, double *A, int *notpd_dev) {
+void cholesky_inplace(hipStream_t s, int64_t q, double *A, int *notpd_dev, double *Wd) {
     for (int64_t kb = 0; kb < q; kb += PB) {
         const int nb = (int)std::min<int64_t>(PB, q - kb);
         const int64_t below = q - kb - nb;
-        potrf_diag_kernel<<<1, BLOCK, 0, s>>>(A, q, kb, nb, notpd_dev);
+        double *Wk = Wd + (kb / PB) * PB * PB;
+        potrf_diag_kernel<<<1, BLOCK, 0, s>>>(A, q, kb, nb, notpd_dev, Wk);
         CGGM_LAUNCH_CHECK();
         if (below > 0) {                 // below > 0 implies nb == PB
-            potrf_panel_kernel<<<blocks_for(below), BLOCK, 0, s>>>(A, q, kb);
-            CGGM_LAUNCH_CHECK();
+            // panel: L[below, k] = A[below, k] L_kk^{-T}, in place (one column tile)
+            double *Pw = A + (kb + nb) * q + kb;
+            gemm(s, false, true, below, nb, nb, 1.0, Pw, q, Wk, PB, 0.0, Pw, q);
             const double *P = A + (kb + nb) * q + kb;
             gemm(s, false, true, below, below, nb, -1.0, P, q, P, q, 1.0,
                  A + (kb + nb) * q + kb + nb, q, UPLO_LOWER, KRANGE_FULL);
@@ -374,13 +339,15 @@ void cholesky_inplace(hipStream_t s, int64_t q, double *A, int *notpd_dev) {
     }
 }
 
-void trsm_lower_left(hipStream_t s, int64_t q, const double *L, double *B, int64_t m,
-                     int64_t ldb, bool lower_rhs) {
+void trsm_lower_left(hipStream_t s, int64_t q, const double *L, const double *Wd, double *B,
+                     int64_t m, int64_t ldb, bool lower_rhs) {
     for (int64_t kb = 0; kb < q; kb += PB) {
         const int nb = (int)std::min<int64_t>(PB, q - kb);
         const int64_t ncols = lower_rhs ? std::min<int64_t>(m, kb + nb) : m;
-        trsm_diag_kernel<<<blocks_for(ncols), BLOCK, 0, s>>>(L, q, kb, nb, B, ldb, ncols);
-        CGGM_LAUNCH_CHECK();
+        // B_k <- L_kk^{-1} B_k in place (one row tile: every output tile reads its
+        // whole K range before it is written)
+        gemm(s, false, false, nb, ncols, nb, 1.0, Wd + (kb / PB) * PB * PB, PB, B + kb * ldb, ldb,
+             0.0, B + kb * ldb, ldb);
         const int64_t below = q - kb - nb;
         if (below > 0)
             gemm(s, false, false, below, ncols, nb, -1.0, L + (kb + nb) * q + kb, q,
@@ -388,10 +355,10 @@ void trsm_lower_left(hipStream_t s, int64_t q, const double *L, double *B, int64
     }
 }
 
-void spd_inverse_from_cholesky(hipStream_t s, int64_t q, const double *L, double *work,
-                               double *Sigma) {
+void spd_inverse_from_cholesky(hipStream_t s, int64_t q, const double *L, const double *Wd,
+                               double *work, double *Sigma) {
     set_identity(s, q, work);
-    trsm_lower_left(s, q, L, work, q, q, true);          // work = L^{-1} (lower)
+    trsm_lower_left(s, q, L, Wd, work, q, q, true);      // work = L^{-1} (lower)
     gemm(s, true, false, q, q, q, 1.0, work, q, work, q, 0.0, Sigma, q, UPLO_LOWER,
          KRANGE_FROM_ROW);                               // Sigma = L^{-T} L^{-1}
     symmetrize_from_lower(s, q, Sigma);
