@@ -25,8 +25,43 @@ namespace cggm {
 
 namespace {
 
-constexpr int T = CD_TILE;   // 32
+constexpr int T = LAMBDA_TILE;    // 32
 constexpr int LD = T + 1;
+constexpr int TT = THETA_TILE;    // 64
+constexpr int LDT = TT + 1;
+
+// Largest number of workgroups one tile's gradient snapshot is split over.
+constexpr int MAX_SPLIT = CD_MAX_SPLIT;
+
+// Cross-workgroup sum of a tile's snapshot split over S workgroups: each
+// workgroup stores its partial (out, TS x TS) in `slots` (S partials), then
+// counts itself in `*cnt`; the workgroup that arrives last sums the S partials
+// in slot order (so the result does not depend on arrival order) into `out`,
+// resets the counter for the next wave and returns true.  The others return
+// false.  All CD_BLOCK threads call it.
+template <int TS, int LDO>
+__device__ bool combine_partials(double (*out)[LDO], double *slots, int part, int S, int *cnt) {
+    if (S == 1) return true;
+    const int tid = threadIdx.x;
+    double *mine = slots + (int64_t)part * TS * TS;
+    for (int e = tid; e < TS * TS; e += CD_BLOCK) mine[e] = out[e / TS][e % TS];
+    __threadfence();
+    __syncthreads();
+    __shared__ int last;
+    if (tid == 0) last = (atomicAdd(cnt, 1) == S - 1);
+    __syncthreads();
+    if (!last) return false;
+    __threadfence();
+    if (tid == 0) *cnt = 0;
+    for (int e = tid; e < TS * TS; e += CD_BLOCK) {
+        double v = 0.0;
+        for (int k = 0; k < S; ++k)
+            v += __builtin_nontemporal_load(slots + (int64_t)k * TS * TS + e);
+        out[e / TS][e % TS] = v;
+    }
+    __syncthreads();
+    return true;
+}
 
 // ------------------------------------------------------------------ Theta ---
 // Coordinate (i, j): along Theta_ij the Theta objective changes by
@@ -34,31 +69,50 @@ constexpr int LD = T + 1;
 // with b = 2 Sxy_ij + 2 (Sxx V)_ij and a = 2 Sxx_ii Sigma_jj; the minimiser is
 // Theta_ij <- S_{lamT/a}(Theta_ij - b/a).  Moving Theta_ij by mu changes the b
 // of coordinate (i', j') by 2 Sxx_i'i Sigma_jj' mu.
-__global__ __launch_bounds__(BLOCK) void theta_tile_kernel(
+__global__ __launch_bounds__(CD_BLOCK) void theta_tile_kernel(
     const TileRect *__restrict__ rects, int64_t p, int64_t q, const double *__restrict__ Sxx,
     const double *__restrict__ Sxy, const double *__restrict__ Sigma,
     const double *__restrict__ V, const double *__restrict__ GT, double *__restrict__ Theta,
     double lamT, double *__restrict__ dT, int *__restrict__ changed,
-    unsigned long long *__restrict__ counters) {
-    const int e = blockIdx.x;
+    unsigned long long *__restrict__ counters, int S, double *__restrict__ partial,
+    int *__restrict__ tile_cnt) {
+    const int e = blockIdx.x / S, part = blockIdx.x % S;
     const TileRect rc = rects[e];
     const int R = rc.r1 - rc.r0, C = rc.c1 - rc.c0;
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
 
     // Skip tiles without active coordinates (|G| > lambda or Theta != 0).
     int act_any = 0;
-    for (int k = tid; k < T * T; k += BLOCK) {
-        const int r = k / T, c = k % T;
+    for (int k = tid; k < TT * TT; k += CD_BLOCK) {
+        const int r = k / TT, c = k % TT;
         if (r < R && c < C) {
             const int64_t idx = (int64_t)(rc.r0 + r) * q + rc.c0 + c;
             act_any |= (fabs(GT[idx]) > lamT || Theta[idx] != 0.0);
         }
     }
     if (!__syncthreads_or(act_any)) {
-        if (tid == 0) changed[e] = 0;
+        if (tid == 0 && part == 0) changed[e] = 0;
         return;
     }
+    __shared__ double Bs[TT][LDT];    // gradient snapshot, then corrected in place
+    __shared__ union {
+        double red[slab_red_doubles<TT>()];
+        struct {
+            double sxx[TT][LDT];      // Sxx[I, I]
+            double sig[TT][LDT];      // Sigma[J, J]
+        } b;
+    } sh;
+    auto &sxx = sh.b.sxx;
+    auto &sig = sh.b.sig;
 
+    // This workgroup's share of (Sxx V)[I, J] = Sxx[:, I]^T V[:, J] (Sxx
+    // symmetric): rows [k0, k1) of the K range.
+    const int64_t k0 = (p * part) / S, k1 = (p * (part + 1)) / S;
+    const SlabPair pr[1] = {{Sxx + k0 * p + rc.r0, p, V + k0 * q + rc.c0, q}};
+    slab_product<TT, 1, LDT>(pr, k1 - k0, R, C, sh.red, Bs);
+    if (!combine_partials<TT, LDT>(Bs, partial + (int64_t)e * MAX_SPLIT * TT * TT, part, S,
+                                   tile_cnt + e))
+        return;                       // another workgroup finishes this tile
     if (counters && tid == 0) {
         // slabs Sxx[:, I], V[:, J]; blocks Sxx[I, I], Sigma[J, J]; Sxy, G, Theta
         // tile reads; Theta and delta writes
@@ -66,22 +120,8 @@ __global__ __launch_bounds__(BLOCK) void theta_tile_kernel(
         atomicAdd(counters + 1, (unsigned long long)(8 * (p * (R + C) + R * R + C * C + 5 * R * C)));
         atomicAdd(counters + 2, (unsigned long long)(2 * (int64_t)R * C * p + 4 * (int64_t)R * C * C));
     }
-    __shared__ double Bs[T][LD];    // gradient snapshot, then corrected in place
-    __shared__ union {
-        SlabRed red;
-        struct {
-            double sxx[T][LD];      // Sxx[I, I]
-            double sig[T][LD];      // Sigma[J, J]
-        } b;
-    } sh;
-    auto &sxx = sh.b.sxx;
-    auto &sig = sh.b.sig;
-
-    // (Sxx V)[I, J] = Sxx[:, I]^T V[:, J]  (Sxx symmetric)
-    const SlabPair pr[1] = {{Sxx + rc.r0, p, V + rc.c0, q}};
-    slab_product_32<1>(pr, p, R, C, sh.red, Bs);
-    for (int k = tid; k < T * T; k += BLOCK) {
-        const int r = k / T, c = k % T;
+    for (int k = tid; k < TT * TT; k += CD_BLOCK) {
+        const int r = k / TT, c = k % TT;
         if (r < R && c < C) Bs[r][c] = 2.0 * Sxy[(int64_t)(rc.r0 + r) * q + rc.c0 + c] +
                                        2.0 * Bs[r][c];
         sxx[r][c] = (r < R && c < R) ? Sxx[(int64_t)(rc.r0 + r) * p + rc.r0 + c] : 0.0;
@@ -94,7 +134,7 @@ __global__ __launch_bounds__(BLOCK) void theta_tile_kernel(
     const int c = lane;
     const bool colok = c < C;
     int any_change = 0;
-    double *dTe = dT + (int64_t)e * T * T;
+    double *dTe = dT + (int64_t)e * TT * TT;
     for (int r = 0; r < R; ++r) {
         const int64_t i = rc.r0 + r;
         double th = 0.0, g = 0.0, b = 0.0, sjj = 1.0;
@@ -129,13 +169,90 @@ __global__ __launch_bounds__(BLOCK) void theta_tile_kernel(
         }
         if (colok) {
             Theta[i * q + rc.c0 + c] = th;
-            dTe[r * T + c] = mu_mine;
+            dTe[r * TT + c] = mu_mine;
             // later rows: b[r2][c] += 2 Sxx[r2][r] sum_l mu_l Sigma[l][c]
             for (int r2 = r + 1; r2 < R; ++r2) Bs[r2][c] += 2.0 * sxx[r2][r] * w;
         }
     }
     if (lane == 0) changed[e] = any_change;
 }
+
+// Out[m][n] += sum_k op(Delta)[m][k] S[k][n] for m < R, k < Kd and the
+// columns [c_begin, c_end) of a row block (the maintained-product update of a
+// tile).  op(Delta)[m][k] = Delta[m * TK + k], or Delta[k * TK + m] when
+// `trans`.  Delta is staged in LDS once; each of the 4 waves owns 16 columns of
+// every 64-column chunk, loads its S operands straight from global memory (one
+// 128-byte row segment per k-step) and read-modify-writes Out from the MFMA
+// accumulators.  All BLOCK threads call it.
+template <int TR, int TK>
+__device__ void rowblock_update(const double *__restrict__ Delta, bool trans, int R, int Kd,
+                                const double *__restrict__ S, int64_t lds,
+                                double *__restrict__ Out, int64_t ldo, int64_t c_begin,
+                                int64_t c_end, double (*dl)[TR + 2]) {
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
+    for (int e = tid; e < TK * TR; e += BLOCK) {
+        const int k = e / TR, m = e % TR;
+        dl[k][m] = (m < R && k < Kd) ? (trans ? Delta[k * TK + m] : Delta[m * TK + k]) : 0.0;
+    }
+    __syncthreads();
+    constexpr int KST = TK / 4, NI = TR / 16;
+    const int col = lane & 15, krow = lane >> 4;
+    // Operands of one 64-column chunk: S values for the MFMA B operand and the
+    // current Out values this lane updates.  The next chunk's loads are issued
+    // before the current chunk's MFMAs so their latency overlaps.
+    struct Chunk {
+        double bv[KST];
+        double ov[NI][4];
+    };
+    auto load = [&](int64_t c0, Chunk &ch) {
+        const int64_t n = c0 + wid * 16 + col;
+        const bool nv = c0 < c_end && n < c_end;
+#pragma unroll
+        for (int ks = 0; ks < KST; ++ks) {
+            const int k = ks * 4 + krow;
+            ch.bv[ks] = (nv && k < Kd) ? S[(int64_t)k * lds + n] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < NI; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = i * 16 + krow + 4 * r;
+                ch.ov[i][r] = (nv && m < R) ? Out[(int64_t)m * ldo + n] : 0.0;
+            }
+    };
+    auto apply = [&](int64_t c0, const Chunk &ch) {
+        const int64_t n = c0 + wid * 16 + col;
+        const bool nv = n < c_end;
+        v4d acc[NI];
+#pragma unroll
+        for (int i = 0; i < NI; ++i)
+            acc[i] = v4d{ch.ov[i][0], ch.ov[i][1], ch.ov[i][2], ch.ov[i][3]};
+#pragma unroll
+        for (int ks = 0; ks < KST; ++ks)
+#pragma unroll
+            for (int i = 0; i < NI; ++i)
+                acc[i] = mfma_f64_16x16x4(dl[ks * 4 + krow][i * 16 + col], ch.bv[ks], acc[i]);
+        if (nv) {
+#pragma unroll
+            for (int i = 0; i < NI; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int m = i * 16 + krow + 4 * r;
+                    if (m < R) Out[(int64_t)m * ldo + n] = acc[i][r];
+                }
+        }
+    };
+    Chunk a, b;
+    load(c_begin, a);
+    for (int64_t c0 = c_begin; c0 < c_end; c0 += 128) {
+        load(c0 + 64, b);
+        apply(c0, a);
+        load(c0 + 128, a);
+        if (c0 + 64 < c_end) apply(c0 + 64, b);
+    }
+}
+
+constexpr int UPD_CHUNKS = 4;   // 64-column chunks per update workgroup
 
 // V[I, :] += dTheta[I, J] Sigma[J, :] for every changed tile of the wave.
 __global__ __launch_bounds__(BLOCK) void theta_v_update_kernel(
@@ -145,23 +262,11 @@ __global__ __launch_bounds__(BLOCK) void theta_v_update_kernel(
     if (!changed[e]) return;
     const TileRect rc = rects[e];
     const int R = rc.r1 - rc.r0, C = rc.c1 - rc.c0;
-    const int64_t n0 = (int64_t)blockIdx.x * T;
-    __shared__ TileSmem<T> sm;
-    WaveAcc<T> acc;
-    acc.zero();
-    tile_mma<false, false, T>(dT + (int64_t)e * T * T, T, Sigma + (int64_t)rc.c0 * q, q, 0, n0,
-                              R, q, 0, C, sm, acc);
-    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
-#pragma unroll
-    for (int i = 0; i < WaveAcc<T>::NB; ++i)
-#pragma unroll
-        for (int j = 0; j < WaveAcc<T>::NB; ++j)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = acc_row<T>(wid, lane, i, r);
-                const int64_t col = n0 + acc_col<T>(wid, lane, j);
-                if (row < R && col < q) V[(int64_t)(rc.r0 + row) * q + col] += acc.c[i][j][r];
-            }
+    const int64_t c_begin = (int64_t)blockIdx.x * 64 * UPD_CHUNKS;
+    const int64_t c_end = std::min<int64_t>(q, c_begin + 64 * UPD_CHUNKS);
+    __shared__ double dl[TT][TT + 2];
+    rowblock_update<TT, TT>(dT + (int64_t)e * TT * TT, false, R, C, Sigma + (int64_t)rc.c0 * q,
+                            q, V + (int64_t)rc.r0 * q, q, c_begin, c_end, dl);
 }
 
 // ----------------------------------------------------------------- Lambda ---
@@ -178,20 +283,21 @@ __global__ __launch_bounds__(BLOCK) void theta_v_update_kernel(
 // coordinate (i', j') by
 //   mu_e [SP_i'i S_lj' + SP_i'l S_ij' + P_ij' S_i'l + P_lj' S_ii']
 // for a move at (i, l), with mu_e = mu (l != i) or mu / 2 (l == i).
-__global__ __launch_bounds__(BLOCK) void lambda_tile_kernel(
+__global__ __launch_bounds__(CD_BLOCK) void lambda_tile_kernel(
     const TileRect *__restrict__ rects, int64_t q, const double *__restrict__ Sigma,
     const double *__restrict__ Psi, const double *__restrict__ SP,
     const double *__restrict__ GL, const double *__restrict__ Lam, double lamL,
     double *__restrict__ D, const double *__restrict__ U, double *__restrict__ dD,
-    int *__restrict__ changed, unsigned long long *__restrict__ counters) {
-    const int e = blockIdx.x;
+    int *__restrict__ changed, unsigned long long *__restrict__ counters, int S,
+    double *__restrict__ partial, int *__restrict__ tile_cnt) {
+    const int e = blockIdx.x / S, part = blockIdx.x % S;
     const TileRect rc = rects[e];
     const int R = rc.r1 - rc.r0, C = rc.c1 - rc.c0;
     const bool diag = rc.r0 == rc.c0;
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
 
     int act_any = 0;
-    for (int k = tid; k < T * T; k += BLOCK) {
+    for (int k = tid; k < T * T; k += CD_BLOCK) {
         const int r = k / T, c = k % T;
         if (r < R && c < C && (!diag || c >= r)) {
             const int64_t idx = (int64_t)(rc.r0 + r) * q + rc.c0 + c;
@@ -199,21 +305,12 @@ __global__ __launch_bounds__(BLOCK) void lambda_tile_kernel(
         }
     }
     if (!__syncthreads_or(act_any)) {
-        if (tid == 0) changed[e] = 0;
+        if (tid == 0 && part == 0) changed[e] = 0;
         return;
-    }
-
-    if (counters && tid == 0) {
-        // slabs SP[:, I], U[:, J], U[:, I], Psi[:, J]; six Sigma / Psi blocks;
-        // G and Lambda tile reads; D (both triangles) and delta writes
-        atomicAdd(counters + 0, 1ull);
-        atomicAdd(counters + 1, (unsigned long long)(8 * (2 * q * (R + C) + 2 * R * R + 2 * C * C +
-                                                         7 * R * C)));
-        atomicAdd(counters + 2, (unsigned long long)(4 * (int64_t)R * C * q + 16 * (int64_t)R * C * C));
     }
     __shared__ double Bs[T][LD];
     __shared__ union {
-        SlabRed red;
+        double red[slab_red_doubles<T>()];
         struct {
             double sII[T][LD], pII[T][LD], sJJ[T][LD], pJJ[T][LD], sIJ[T][LD], pIJ[T][LD];
         } b;
@@ -226,10 +323,24 @@ __global__ __launch_bounds__(BLOCK) void lambda_tile_kernel(
     auto &pIJ = sh.b.pIJ;
 
     // b snapshot: G + (SP U)[I, J] + ((Psi U)[J, I])^T
-    //   = G + SP[:, I]^T U[:, J] + U[:, I]^T Psi[:, J]   (SP, Psi symmetric)
-    const SlabPair pr[2] = {{SP + rc.r0, q, U + rc.c0, q}, {U + rc.r0, q, Psi + rc.c0, q}};
-    slab_product_32<2>(pr, q, R, C, sh.red, Bs);
-    for (int k = tid; k < T * T; k += BLOCK) {
+    //   = G + SP[:, I]^T U[:, J] + U[:, I]^T Psi[:, J]   (SP, Psi symmetric);
+    // this workgroup sums the rows [k0, k1) of the K range.
+    const int64_t k0 = (q * part) / S, k1 = (q * (part + 1)) / S;
+    const SlabPair pr[2] = {{SP + k0 * q + rc.r0, q, U + k0 * q + rc.c0, q},
+                            {U + k0 * q + rc.r0, q, Psi + k0 * q + rc.c0, q}};
+    slab_product<T, 2, LD>(pr, k1 - k0, R, C, sh.red, Bs);
+    if (!combine_partials<T, LD>(Bs, partial + (int64_t)e * MAX_SPLIT * T * T, part, S,
+                                 tile_cnt + e))
+        return;                       // another workgroup finishes this tile
+    if (counters && tid == 0) {
+        // slabs SP[:, I], U[:, J], U[:, I], Psi[:, J]; six Sigma / Psi blocks;
+        // G and Lambda tile reads; D (both triangles) and delta writes
+        atomicAdd(counters + 0, 1ull);
+        atomicAdd(counters + 1, (unsigned long long)(8 * (2 * q * (R + C) + 2 * R * R + 2 * C * C +
+                                                         7 * R * C)));
+        atomicAdd(counters + 2, (unsigned long long)(4 * (int64_t)R * C * q + 16 * (int64_t)R * C * C));
+    }
+    for (int k = tid; k < T * T; k += CD_BLOCK) {
         const int r = k / T, c = k % T;
         const bool ii = r < R && c < R, jj = r < C && c < C, ij = r < R && c < C;
         if (ij) Bs[r][c] += GL[(int64_t)(rc.r0 + r) * q + rc.c0 + c];
@@ -338,35 +449,25 @@ __global__ __launch_bounds__(BLOCK) void lambda_u_update_kernel(
     const bool diag = rc.r0 == rc.c0;
     if (diag && half == 1) return;
     const int R = rc.r1 - rc.r0, C = rc.c1 - rc.c0;
-    const int64_t n0 = (int64_t)blockIdx.x * T;
-    __shared__ TileSmem<T> sm;
-    WaveAcc<T> acc;
-    acc.zero();
+    const int64_t c_begin = (int64_t)blockIdx.x * 64 * UPD_CHUNKS;
+    const int64_t c_end = std::min<int64_t>(q, c_begin + 64 * UPD_CHUNKS);
+    __shared__ double dl[T][T + 2];
     const double *dDe = dD + (int64_t)e * T * T;
-    int rows;
-    int64_t row0;
-    if (half == 0) {
-        tile_mma<false, false, T>(dDe, T, Sigma + (int64_t)rc.c0 * q, q, 0, n0, R, q, 0, C, sm,
-                                  acc);
-        rows = R;
-        row0 = rc.r0;
-    } else {
-        tile_mma<true, false, T>(dDe, T, Sigma + (int64_t)rc.r0 * q, q, 0, n0, C, q, 0, R, sm,
-                                 acc);
-        rows = C;
-        row0 = rc.c0;
-    }
-    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
-#pragma unroll
-    for (int i = 0; i < WaveAcc<T>::NB; ++i)
-#pragma unroll
-        for (int j = 0; j < WaveAcc<T>::NB; ++j)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = acc_row<T>(wid, lane, i, r);
-                const int64_t col = n0 + acc_col<T>(wid, lane, j);
-                if (row < rows && col < q) U[(row0 + row) * q + col] += acc.c[i][j][r];
-            }
+    if (half == 0)
+        rowblock_update<T, T>(dDe, false, R, C, Sigma + (int64_t)rc.c0 * q, q,
+                              U + (int64_t)rc.r0 * q, q, c_begin, c_end, dl);
+    else
+        rowblock_update<T, T>(dDe, true, C, R, Sigma + (int64_t)rc.r0 * q, q,
+                              U + (int64_t)rc.c0 * q, q, c_begin, c_end, dl);
+}
+
+// Workgroups per tile snapshot: about 1024 workgroups per wave, at most
+// MAX_SPLIT, and at least 256 rows of K per workgroup.
+int snapshot_split(int nrect, int64_t K) {
+    int S = (1024 + nrect - 1) / nrect;
+    S = std::min(S, MAX_SPLIT);
+    S = (int)std::min<int64_t>(S, std::max<int64_t>(1, K / 256));
+    return std::max(S, 1);
 }
 
 }  // namespace
@@ -374,15 +475,18 @@ __global__ __launch_bounds__(BLOCK) void lambda_u_update_kernel(
 void theta_wave(hipStream_t s, const TileRect *rects_dev, int nrect, int64_t p, int64_t q,
                 const double *Sxx, const double *Sxy, const double *Sigma, double *V,
                 const double *GT, double *Theta, double lamT, double *dT, int *changed,
-                const WaveProbe *probe) {
+                const CdScratch &scr, const WaveProbe *probe) {
     if (nrect <= 0) return;
+    const int S = snapshot_split(nrect, p);
     if (probe) CGGM_HIP(hipEventRecord(probe->start, s));
-    theta_tile_kernel<<<nrect, BLOCK, 0, s>>>(rects_dev, p, q, Sxx, Sxy, Sigma, V, GT, Theta,
-                                              lamT, dT, changed,
-                                              probe ? probe->counters : nullptr);
+    theta_tile_kernel<<<nrect * S, CD_BLOCK, 0, s>>>(rects_dev, p, q, Sxx, Sxy, Sigma, V, GT,
+                                                     Theta, lamT, dT, changed,
+                                                     probe ? probe->counters : nullptr, S,
+                                                     scr.partial, scr.tile_cnt);
     CGGM_LAUNCH_CHECK();
     if (probe) CGGM_HIP(hipEventRecord(probe->stop, s));
-    dim3 grid((unsigned)((q + T - 1) / T), (unsigned)nrect);
+    const int64_t cols_per_wg = 64 * UPD_CHUNKS;
+    dim3 grid((unsigned)((q + cols_per_wg - 1) / cols_per_wg), (unsigned)nrect);
     theta_v_update_kernel<<<grid, BLOCK, 0, s>>>(rects_dev, q, Sigma, dT, changed, V);
     CGGM_LAUNCH_CHECK();
 }
@@ -390,14 +494,18 @@ void theta_wave(hipStream_t s, const TileRect *rects_dev, int nrect, int64_t p, 
 void lambda_wave(hipStream_t s, const TileRect *rects_dev, int nrect, int64_t q,
                  const double *Sigma, const double *Psi, const double *SP, const double *GL,
                  const double *Lam, double lamL, double *D, double *U, double *dD,
-                 int *changed, const WaveProbe *probe) {
+                 int *changed, const CdScratch &scr, const WaveProbe *probe) {
     if (nrect <= 0) return;
+    const int S = snapshot_split(nrect, q);
     if (probe) CGGM_HIP(hipEventRecord(probe->start, s));
-    lambda_tile_kernel<<<nrect, BLOCK, 0, s>>>(rects_dev, q, Sigma, Psi, SP, GL, Lam, lamL, D, U,
-                                               dD, changed, probe ? probe->counters : nullptr);
+    lambda_tile_kernel<<<nrect * S, CD_BLOCK, 0, s>>>(rects_dev, q, Sigma, Psi, SP, GL, Lam,
+                                                      lamL, D, U, dD, changed,
+                                                      probe ? probe->counters : nullptr, S,
+                                                      scr.partial, scr.tile_cnt);
     CGGM_LAUNCH_CHECK();
     if (probe) CGGM_HIP(hipEventRecord(probe->stop, s));
-    dim3 grid((unsigned)((q + T - 1) / T), (unsigned)nrect, 2);
+    const int64_t cols_per_wg = 64 * UPD_CHUNKS;
+    dim3 grid((unsigned)((q + cols_per_wg - 1) / cols_per_wg), (unsigned)nrect, 2);
     lambda_u_update_kernel<<<grid, BLOCK, 0, s>>>(rects_dev, q, Sigma, dD, changed, U);
     CGGM_LAUNCH_CHECK();
 }

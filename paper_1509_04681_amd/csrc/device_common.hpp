@@ -116,71 +116,108 @@ struct SlabPair {
     int64_t ldb;
 };
 
-// Partial sums of the four waves of a 32 x 32 slab product (LDS).
-struct SlabRed {
-    double part[4][32][33];
-};
+// Workgroup size of the coordinate-descent tile kernels (8 waves).
+constexpr int CD_BLOCK = 512;
 
-// out[m][n] = sum over the pairs P of sum_k P.A[k][m] P.B[k][n], for a 32 x 32
-// output (entries m >= ma or n >= nb are zero).  The K range is split into
-// four contiguous quarters, one per wave; each wave loads its MFMA operands
-// directly from global memory (16 consecutive doubles per operand row,
-// UNROLL k-steps in flight) and accumulates the whole 32 x 32 tile as 2 x 2
-// MFMA blocks; the four partial tiles are summed through LDS.  All 256
-// threads must call it; on return `out` is complete (a barrier is included).
-template <int NPAIR>
-__device__ void slab_product_32(const SlabPair (&pairs)[NPAIR], int64_t K, int ma, int nb,
-                                SlabRed &red, double (*out)[33]) {
-    constexpr int UNROLL = 8;
+// out[m][n] = sum over the pairs P of sum_k P.A[k][m] P.B[k][n] for a TS x TS
+// output (TS = 32 or 64; entries m >= ma or n >= nb are zero), computed by
+// the 8 waves of a CD_BLOCK workgroup: the output is split into 32 x 32
+// quadrants and the K range into KS contiguous parts, one wave per
+// (quadrant, part).  Each wave loads its MFMA operands directly from global
+// memory (16 consecutive doubles per operand row) with two register buffers of
+// U k-steps, so one buffer's loads are in flight while the other feeds the
+// MFMAs; the KS partial tiles are summed through `red` (LDS, (KS - 1) x TS x
+// (TS + 1) doubles).  All CD_BLOCK threads must call it; barriers included.
+template <int TS, int NPAIR, int LDO>
+__device__ void slab_product(const SlabPair (&pairs)[NPAIR], int64_t K, int ma, int nb,
+                             double *red, double (*out)[LDO]) {
+    constexpr int NQD = TS / 32;             // quadrants per dimension
+    constexpr int NQ = NQD * NQD;
+    constexpr int KS = (CD_BLOCK / WAVE) / NQ;
+    constexpr int U = 4;
+    static_assert(KS >= 1 && NQ * KS == CD_BLOCK / WAVE, "wave split");
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
-    const int64_t ksteps = (K + 3) / 4;
-    const int64_t s0 = (ksteps * wid) / 4, s1 = (ksteps * (wid + 1)) / 4;
+    const int quad = wid % NQ, part = wid / NQ;
+    const int mo = (quad / NQD) * 32, no = (quad % NQD) * 32;
     const int col = lane & 15, krow = lane >> 4;
+    const int64_t ksteps = (K + 3) / 4;
+    const int64_t s0 = (ksteps * part) / KS, s1 = (ksteps * (part + 1)) / KS;
+    const bool am0 = mo + col < ma, am1 = mo + col + 16 < ma;
+    const bool bn0 = no + col < nb, bn1 = no + col + 16 < nb;
     v4d acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
-    const bool am0 = col < ma, am1 = col + 16 < ma, bn0 = col < nb, bn1 = col + 16 < nb;
+    double a0[U][2], b0[U][2], a1[U][2], b1[U][2];
+    auto load = [&](const SlabPair &P, int64_t st, double (&a)[U][2], double (&b)[U][2]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t k = (st + u) * 4 + krow;
+            const bool kv = (st + u) < s1 && k < K;
+            const double *ar = P.A + k * P.lda + mo;
+            const double *br = P.B + k * P.ldb + no;
+            a[u][0] = (kv && am0) ? ar[col] : 0.0;
+            a[u][1] = (kv && am1) ? ar[col + 16] : 0.0;
+            b[u][0] = (kv && bn0) ? br[col] : 0.0;
+            b[u][1] = (kv && bn1) ? br[col + 16] : 0.0;
+        }
+    };
+    auto mma = [&](const double (&a)[U][2], const double (&b)[U][2]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = mfma_f64_16x16x4(a[u][i], b[u][j], acc[i][j]);
+    };
 #pragma unroll
     for (int pp = 0; pp < NPAIR; ++pp) {
         const SlabPair P = pairs[pp];
-        for (int64_t st = s0; st < s1; st += UNROLL) {
-            double a[UNROLL][2], b[UNROLL][2];
-#pragma unroll
-            for (int u = 0; u < UNROLL; ++u) {
-                const int64_t k = (st + u) * 4 + krow;
-                const bool kv = (st + u) < s1 && k < K;
-                const double *ar = P.A + k * P.lda;
-                const double *br = P.B + k * P.ldb;
-                a[u][0] = (kv && am0) ? ar[col] : 0.0;
-                a[u][1] = (kv && am1) ? ar[col + 16] : 0.0;
-                b[u][0] = (kv && bn0) ? br[col] : 0.0;
-                b[u][1] = (kv && bn1) ? br[col + 16] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < UNROLL; ++u)
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                    for (int j = 0; j < 2; ++j)
-                        acc[i][j] = mfma_f64_16x16x4(a[u][i], b[u][j], acc[i][j]);
+        load(P, s0, a0, b0);
+        for (int64_t st = s0; st < s1; st += 2 * U) {
+            load(P, st + U, a1, b1);
+            mma(a0, b0);
+            load(P, st + 2 * U, a0, b0);
+            mma(a1, b1);
         }
     }
+    constexpr int LDR = TS + 1;
+    if (part == 0) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+            for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                red.part[wid][i * 16 + krow + 4 * r][j * 16 + col] = acc[i][j][r];
-    __syncthreads();
-    for (int e = tid; e < 32 * 32; e += BLOCK) {
-        const int m = e >> 5, n = e & 31;
-        out[m][n] = red.part[0][m][n] + red.part[1][m][n] + red.part[2][m][n] +
-                    red.part[3][m][n];
+                for (int r = 0; r < 4; ++r)
+                    out[mo + i * 16 + krow + 4 * r][no + j * 16 + col] = acc[i][j][r];
+    } else {
+        double *rp = red + (int64_t)(part - 1) * TS * LDR;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    rp[(mo + i * 16 + krow + 4 * r) * LDR + no + j * 16 + col] = acc[i][j][r];
     }
     __syncthreads();
+    if (KS > 1) {
+        for (int e = tid; e < TS * TS; e += CD_BLOCK) {
+            const int m = e / TS, n = e % TS;
+            double v = out[m][n];
+#pragma unroll
+            for (int k = 0; k < KS - 1; ++k) v += red[k * TS * LDR + m * LDR + n];
+            out[m][n] = v;
+        }
+        __syncthreads();
+    }
+}
+
+template <int TS>
+constexpr int slab_red_doubles() {
+    return ((CD_BLOCK / WAVE) / ((TS / 32) * (TS / 32)) - 1) * TS * (TS + 1);
 }
 
 // Broadcast a double from `lane` (wave-uniform index) to the whole wave.

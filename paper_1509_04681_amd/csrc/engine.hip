@@ -200,6 +200,7 @@ struct Work {
     double *partials, *scal;                       // reduction scratch, device scalars
     int *flag, *changed;
     unsigned long long *kctr;                      // tile-kernel counters [2][3]
+    CdScratch cd;                                  // split-snapshot scratch
     TileRect *rects_theta, *rects_lambda;
     int max_tiles = 0;
 };
@@ -235,13 +236,15 @@ void layout(Arena &a, Work &w, int64_t n, int64_t p, int64_t q, int64_t ntheta_r
     w.At = a.take<double>(nq);
     w.Zt = a.take<double>(nq);
     w.max_tiles = max_tiles;
-    w.dT = a.take<double>((int64_t)max_tiles * CD_TILE * CD_TILE);
-    w.dD = a.take<double>((int64_t)max_tiles * CD_TILE * CD_TILE);
+    w.dT = a.take<double>((int64_t)max_tiles * THETA_TILE * THETA_TILE);
+    w.dD = a.take<double>((int64_t)max_tiles * LAMBDA_TILE * LAMBDA_TILE);
     w.partials = a.take<double>(REDUCE_BLOCKS * 8);
     w.scal = a.take<double>(NSCAL);
     w.flag = a.take<int>(4);
     w.changed = a.take<int>(max_tiles);
     w.kctr = a.take<unsigned long long>(6);
+    w.cd.partial = a.take<double>((int64_t)max_tiles * CD_MAX_SPLIT * THETA_TILE * THETA_TILE);
+    w.cd.tile_cnt = a.take<int>(max_tiles + 1);
     w.rects_theta = a.take<TileRect>(ntheta_rects);
     w.rects_lambda = a.take<TileRect>(nlambda_rects);
 }
@@ -376,7 +379,7 @@ void run_theta_sweep(Ctx &c, const Schedule &sch, KernelTimer *kt = nullptr) {
         WaveProbe pr;
         if (kt && kt->on()) pr = kt->probe(k);
         theta_wave(c.s, w.rects_theta + b, e - b, w.p, w.q, w.Sxx, w.Sxy, w.Sig, w.V, w.GT,
-                   w.Th, c.lamT, w.dT, w.changed, (kt && kt->on()) ? &pr : nullptr);
+                   w.Th, c.lamT, w.dT, w.changed, w.cd, (kt && kt->on()) ? &pr : nullptr);
     }
 }
 
@@ -389,7 +392,7 @@ void run_lambda_sweep(Ctx &c, const Schedule &sch, KernelTimer *kt = nullptr) {
         WaveProbe pr;
         if (kt && kt->on()) pr = kt->probe(k);
         lambda_wave(c.s, w.rects_lambda + b, e - b, w.q, w.Sig, w.Psi, w.SP, w.GL, w.Lam,
-                    c.lamL, w.D, w.U, w.dD, w.changed, (kt && kt->on()) ? &pr : nullptr);
+                    c.lamL, w.D, w.U, w.dD, w.changed, w.cd, (kt && kt->on()) ? &pr : nullptr);
     }
 }
 
@@ -449,10 +452,11 @@ void check_finite(Ctx &c, const double *X, const double *Y) {
     if (h[0] != 0.0 || h[1] != 0.0) fail(CGGM_EINVAL, "X or Y has non-finite entries");
 }
 
-int64_t default_tile(int tile) {
-    if (tile <= 0) return CD_TILE;
-    if (tile > CD_TILE) fail(CGGM_EINVAL, "tile must be <= 32");
-    return tile;
+// Tile edges of the Lambda and Theta sweeps; `tile` > 0 caps both.
+std::pair<int, int> tile_edges(int tile) {
+    if (tile <= 0) return {LAMBDA_TILE, THETA_TILE};
+    if (tile > THETA_TILE) fail(CGGM_EINVAL, "tile must be <= 64");
+    return {std::min(tile, LAMBDA_TILE), std::min(tile, THETA_TILE)};
 }
 
 // ------------------------------------------------------------------ solve ----
@@ -470,10 +474,10 @@ int solve_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q
         !(opt.ls_sigma > 0.0 && opt.ls_sigma < 1.0) || opt.stall_iters < 0 ||
         (opt.sweep != CGGM_SWEEP_TILED && opt.sweep != CGGM_SWEEP_SEQUENTIAL))
         fail(CGGM_EINVAL, "invalid options");
-    const int64_t tile = default_tile(opt.tile);
+    const auto [tileL, tileT] = tile_edges(opt.tile);
     const bool seq = opt.sweep == CGGM_SWEEP_SEQUENTIAL;
-    const Schedule th_sched = theta_schedule(p, q, (int)tile, seq);
-    const Schedule la_sched = lambda_schedule(q, (int)tile, seq);
+    const Schedule th_sched = theta_schedule(p, q, tileT, seq);
+    const Schedule la_sched = lambda_schedule(q, tileL, seq);
     // Tile-sequential fallbacks of the descent guard: one tile per wave.
     Schedule th_safe, la_safe;
     th_safe.wave_start.push_back(0);
@@ -512,6 +516,8 @@ int solve_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q
                             sizeof(TileRect) * la_sched.rects.size(), hipMemcpyHostToDevice, s));
     Ctx c{s, w, lamL, lamT};
     const int64_t qq = q * q, pq = p * q;
+    // arrival counters of the split snapshots start at zero (all-zero bits)
+    fill(s, (max_tiles + 2) / 2, 0.0, reinterpret_cast<double *>(w.cd.tile_cnt));
     check_finite(c, X, Y);
     KernelTimer kt_lambda, kt_theta;
     if (opt.kstats) {
@@ -909,8 +915,8 @@ void cggm_default_options(cggm_options *opt) {
 
 size_t cggm_solve_workspace_bytes(int64_t n, int64_t p, int64_t q) {
     if (n < 1 || p < 1 || q < 1) return 0;
-    const Schedule th = theta_schedule(p, q, CD_TILE, false);
-    const Schedule la = lambda_schedule(q, CD_TILE, false);
+    const Schedule th = theta_schedule(p, q, THETA_TILE, false);
+    const Schedule la = lambda_schedule(q, LAMBDA_TILE, false);
     Arena sizer;
     sizer.measure = true;
     Work w;

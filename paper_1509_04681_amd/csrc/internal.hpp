@@ -128,7 +128,8 @@ struct TileRect {
     int32_t r0, r1, c0, c1;   // rows [r0, r1), columns [c0, c1)
 };
 
-constexpr int CD_TILE = 32;   // maximum tile edge of a CD tile
+constexpr int LAMBDA_TILE = 32;   // tile edge of the Lambda CD tiles
+constexpr int THETA_TILE = 64;    // tile edge of the Theta CD tiles
 
 // Optional instrumentation of a wave: events recorded around the tile kernel
 // and device counters (processed tiles, algorithmic bytes, flops) it adds to.
@@ -137,14 +138,23 @@ struct WaveProbe {
     unsigned long long *counters = nullptr;   // [3]
 };
 
+// Scratch of the split gradient snapshots: per tile of a wave, CD_MAX_SPLIT
+// partial tiles (THETA_TILE^2 doubles each) and an arrival counter (zero
+// between waves; the kernels reset it).
+constexpr int CD_MAX_SPLIT = 8;
+struct CdScratch {
+    double *partial = nullptr;   // max_tiles * CD_MAX_SPLIT * THETA_TILE^2
+    int *tile_cnt = nullptr;     // max_tiles
+};
+
 // One wave of the Theta sweep: every rect in `rects` (row- and column-disjoint)
 // runs exact Gauss-Seidel over its active coordinates from a snapshot of
 // b = 2 Sxy + 2 Sxx V, writes the updated Theta and its delta (dT, nrect
-// tiles of CD_TILE^2), then V[rows, :] += dTheta Sigma[cols, :].
+// tiles of THETA_TILE^2), then V[rows, :] += dTheta Sigma[cols, :].
 void theta_wave(hipStream_t s, const TileRect *rects_dev, int nrect, int64_t p, int64_t q,
                 const double *Sxx, const double *Sxy, const double *Sigma, double *V,
                 const double *GT, double *Theta, double lamT, double *dT, int *changed,
-                const WaveProbe *probe = nullptr);
+                const CdScratch &scr, const WaveProbe *probe = nullptr);
 
 // One wave of the Lambda direction sweep over upper-triangle rects with
 // pairwise-disjoint index sets: exact Gauss-Seidel inside each rect from a
@@ -153,6 +163,6 @@ void theta_wave(hipStream_t s, const TileRect *rects_dev, int nrect, int64_t p, 
 void lambda_wave(hipStream_t s, const TileRect *rects_dev, int nrect, int64_t q,
                  const double *Sigma, const double *Psi, const double *SP, const double *GL,
                  const double *Lam, double lamL, double *D, double *U, double *dD,
-                 int *changed, const WaveProbe *probe = nullptr);
+                 int *changed, const CdScratch &scr, const WaveProbe *probe = nullptr);
 
 }  // namespace cggm

@@ -62,7 +62,7 @@ __device__ void invert_lower_block(const double (*d)[PB + 1], double (*w)[PB + 1
         }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < PB * PB; e += BLOCK) {
+    for (int e = threadIdx.x; e < PB * PB; e += blockDim.x) {
         const int i = e / PB, j = e % PB;
         Wk[e] = (i < nb && j <= i) ? w[i][j] : 0.0;
     }
@@ -71,13 +71,13 @@ __device__ void invert_lower_block(const double (*d)[PB + 1], double (*w)[PB + 1
 // Factor the diagonal block A[kb:kb+nb, kb:kb+nb] = L_kk L_kk^T in LDS (one
 // workgroup), store L_kk in place and L_kk^{-1} in Wk (PB x PB); *notpd = 1 if
 // a pivot is not positive.
-__global__ __launch_bounds__(BLOCK) void potrf_diag_kernel(double *A, int64_t q, int64_t kb,
-                                                           int nb, int *notpd, double *Wk) {
+__global__ __launch_bounds__(WAVE) void potrf_diag_kernel(double *A, int64_t q, int64_t kb,
+                                                          int nb, int *notpd, double *Wk) {
     __shared__ double d[PB][PB + 1];
     __shared__ double w[PB][PB + 1];
     __shared__ int bad;
     const int tid = threadIdx.x;
-    for (int e = tid; e < nb * nb; e += BLOCK) {
+    for (int e = tid; e < nb * nb; e += blockDim.x) {
         const int i = e / nb, j = e % nb;
         if (j <= i) d[i][j] = A[(kb + i) * q + kb + j];
     }
@@ -91,16 +91,16 @@ __global__ __launch_bounds__(BLOCK) void potrf_diag_kernel(double *A, int64_t q,
         }
         __syncthreads();
         const double djj = d[j][j];
-        for (int i = j + 1 + tid; i < nb; i += BLOCK) d[i][j] /= djj;
+        for (int i = j + 1 + tid; i < nb; i += blockDim.x) d[i][j] /= djj;
         __syncthreads();
         const int w = nb - j - 1;
-        for (int e = tid; e < w * w; e += BLOCK) {
+        for (int e = tid; e < w * w; e += blockDim.x) {
             const int i = j + 1 + e / w, c = j + 1 + e % w;
             if (c <= i) d[i][c] -= d[i][j] * d[c][j];
         }
         __syncthreads();
     }
-    for (int e = tid; e < nb * nb; e += BLOCK) {
+    for (int e = tid; e < nb * nb; e += blockDim.x) {
         const int i = e / nb, j = e % nb;
         if (j <= i) A[(kb + i) * q + kb + j] = d[i][j];
     }
@@ -326,7 +326,7 @@ void cholesky_inplace(hipStream_t s, int64_t q, double *A, int *notpd_dev, doubl
         const int nb = (int)std::min<int64_t>(PB, q - kb);
         const int64_t below = q - kb - nb;
         double *Wk = Wd + (kb / PB) * PB * PB;
-        potrf_diag_kernel<<<1, BLOCK, 0, s>>>(A, q, kb, nb, notpd_dev, Wk);
+        potrf_diag_kernel<<<1, WAVE, 0, s>>>(A, q, kb, nb, notpd_dev, Wk);
         CGGM_LAUNCH_CHECK();
         if (below > 0) {                 // below > 0 implies nb == PB
             // panel: L[below, k] = A[below, k] L_kk^{-T}, in place (one column tile)

@@ -123,11 +123,16 @@ WORKLOADS = {
     "chain2k": dict(p=2000, q=2000, n=500, density=0.01, lam=0.05),
     # p = q = 20000, n = 1000, 0.05% dense Theta, lambda = 0.02
     "chain20k": dict(p=20000, q=20000, n=1000, density=0.0005, lam=0.02),
+    # parity case large enough (K >= 512) that tile gradient snapshots are
+    # split over several workgroups
+    "chain530": dict(p=530, q=515, n=100, density=0.005, lam=0.5, seed=21),
 }
 
 
-def workload(name: str, seed: int = 0) -> Problem:
-    return chain_problem(seed=seed, **WORKLOADS[name])
+def workload(name: str, seed: int | None = None) -> Problem:
+    kw = dict(WORKLOADS[name])
+    kw["seed"] = kw.get("seed", 0) if seed is None else seed
+    return chain_problem(**kw)
 
 
 def random_spd(q: int, rng: np.random.Generator, degree: float = 4.0,

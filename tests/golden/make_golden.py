@@ -54,7 +54,7 @@ def load(name: str) -> dict:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("workload", choices=sorted(synth.WORKLOADS))
-    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--seed", type=int, default=None)
     ap.add_argument("--chunk", type=int, default=25)
     ap.add_argument("--max-iter", type=int, default=20000)
     ap.add_argument("--state-dir", default=None)
@@ -88,6 +88,7 @@ def main():
             break
     out = {
         "workload": args.workload, "seed": args.seed, "n": pr.n, "p": pr.p, "q": pr.q,
+        "name": pr.name,
         "lam_Lambda": pr.lam_Lambda, "lam_Theta": pr.lam_Theta,
         "f_star": r.f, "iterations": done, "status": int(r.status),
         "subgrad_l1": float(r.trace["subgrad"][-1]), "l1": float(r.trace["l1"][-1]),
@@ -100,7 +101,7 @@ def main():
         "borderline_Lambda": pack_mask((np.abs(Lam) >= 1e-7) & (np.abs(Lam) <= 1e-5)),
         "borderline_Theta": pack_mask((np.abs(Th) >= 1e-7) & (np.abs(Th) <= 1e-5)),
         "f_trace_head": fs[:50],
-        "generator": "synth.workload(%r, seed=%d) -> oracle.solve(tol=0, stall_iters=3)"
+        "generator": "synth.workload(%r, seed=%r) -> oracle.solve(tol=0, stall_iters=3)"
                      % (args.workload, args.seed),
     }
     with open(os.path.join(HERE, f"{args.workload}.json"), "w") as fh:

@@ -66,7 +66,7 @@ def test_argument_errors_without_device(lib):
     assert lib.cggm_solve(fake, fake, 4, 3, 2, 0.1, 0.1, 0.01, ctypes.byref(opt),
                           ctypes.byref(r), None) == m.CGGM_EINVAL
     lib.cggm_default_options(ctypes.byref(opt))
-    opt.tile = 64
+    opt.tile = 65
     assert lib.cggm_solve(fake, fake, 4, 3, 2, 0.1, 0.1, 0.01, ctypes.byref(opt),
                           ctypes.byref(r), None) == m.CGGM_EINVAL
 

@@ -180,6 +180,25 @@ def test_tiled_solve_converges_to_oracle_optimum(cg, orc, case):
     assert kkt_violation(X, Y, Lg, Tg, lamL, lamT) < 1e-6
 
 
+def test_split_snapshots_golden_chain530(cg):
+    """p, q >= 512 split every tile's gradient snapshot over several workgroups
+    (partials summed in a fixed order by the last one to arrive): the converged
+    objective and supports must match the stored oracle optimum."""
+    gold = load_golden("chain530")
+    pr = synth.workload("chain530")
+    g = cg.cggm_solve(dev(pr.X), dev(pr.Y), pr.lam_Lambda, pr.lam_Theta, tol=0.0,
+                      max_iter=3000)
+    f = np.array([t["f"] for t in g.trace])
+    print(f"chain530: f_gpu={g.f!r} f_oracle={gold['f_star']!r} iters gpu={g.iters} "
+          f"oracle={gold['iterations']}", flush=True)
+    assert np.all(np.diff(f) <= 1e-12 * np.abs(f[1:]))
+    assert abs(g.f - gold["f_star"]) <= F_RTOL * abs(gold["f_star"])
+    sL = np.abs(g.Lambda.cpu().numpy()) > SUPPORT_EPS
+    sT = np.abs(g.Theta.cpu().numpy()) > SUPPORT_EPS
+    assert ((sL == gold["support_Lambda"]) | gold["borderline_Lambda"]).all()
+    assert ((sT == gold["support_Theta"]) | gold["borderline_Theta"]).all()
+
+
 def test_golden_chain40(cg):
     """Stored oracle optimum of the 40 x 40 chain workload (tests/golden)."""
     gold = load_golden("chain40")
