@@ -73,18 +73,21 @@ typedef struct {
     double ms_theta_cd;   /* V = Theta Sigma and the Theta sweep                 */
 } cggm_trace_entry;
 
-/* Launch statistics of the two coordinate-descent tile kernels, filled when
- * options.kstats is non-NULL.  Durations come from HIP events recorded on the
+/* Launch statistics of the coordinate-descent sweeps, filled when
+ * options.kstats is non-NULL.  Each wave of a sweep runs three kernels
+ * (stage 0: gradient snapshot products, 1: in-tile Gauss-Seidel, 2: update of
+ * the maintained product).  Durations come from HIP events recorded on the
  * solve's stream around every launch; bytes and flops are the algorithmic
  * traffic and arithmetic of the tiles that had active coordinates (operand
- * slabs of the gradient snapshot, the tile's Sigma / Psi / Sxx blocks, the
- * tile's gradient and parameter reads and its writes), counted on the device. */
+ * slabs of the snapshot; the tile's Sigma / Psi / Sxx blocks, gradient and
+ * parameter reads and writes; the rows of Sigma read and of U or V updated),
+ * counted on the device.  Index [0] is the Lambda sweep, [1] the Theta sweep. */
 typedef struct {
-    int64_t launches[2];        /* [0] Lambda tile kernel, [1] Theta tile kernel   */
+    int64_t waves[2];           /* waves run (kernel triples)                      */
     int64_t tiles[2];           /* tiles processed (with active coordinates)       */
-    double ms[2];               /* summed launch durations                         */
-    double bytes[2];            /* summed algorithmic bytes                        */
-    double flops[2];            /* summed algorithmic flops                        */
+    double ms[2][3];            /* summed launch durations per stage               */
+    double bytes[2][3];         /* summed algorithmic bytes per stage              */
+    double flops[2][3];         /* summed algorithmic flops per stage              */
 } cggm_kernel_stats;
 
 typedef struct {
@@ -103,7 +106,7 @@ typedef struct {
     cggm_trace_entry *trace;   /* host array of trace_cap records, or NULL     */
     int trace_cap;
     int trace_len;             /* out: records written                          */
-    cggm_kernel_stats *kstats; /* out: CD tile-kernel statistics, or NULL        */
+    cggm_kernel_stats *kstats; /* out: CD sweep kernel statistics, or NULL       */
 } cggm_options;
 
 /* Fill `opt` with the defaults above. */

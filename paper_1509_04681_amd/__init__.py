@@ -41,9 +41,12 @@ class TraceEntry(ctypes.Structure):
 
 
 class KernelStats(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_int64 * 2), ("tiles", ctypes.c_int64 * 2),
-                ("ms", ctypes.c_double * 2), ("bytes", ctypes.c_double * 2),
-                ("flops", ctypes.c_double * 2)]
+    _fields_ = [("waves", ctypes.c_int64 * 2), ("tiles", ctypes.c_int64 * 2),
+                ("ms", (ctypes.c_double * 3) * 2), ("bytes", (ctypes.c_double * 3) * 2),
+                ("flops", (ctypes.c_double * 3) * 2)]
+
+
+STAGES = ("snapshot", "gauss_seidel", "update")
 
 
 class Options(ctypes.Structure):
@@ -148,8 +151,8 @@ class SolveResult:
     nnz_Lambda: int
     nnz_Theta: int
     trace: list
-    # CD tile-kernel launch statistics when cggm_solve(..., kernel_stats=True):
-    # {"lambda_tile"|"theta_tile": {launches, tiles, ms, bytes, flops}}
+    # CD sweep kernel statistics when cggm_solve(..., kernel_stats=True):
+    # {"<lambda|theta>_<snapshot|gauss_seidel|update>": {launches, tiles, ms, bytes, flops}}
     kernel_stats: dict | None = None
     # host CSR ((rowptr, col, val) of Lambda (full symmetric), same of Theta)
     # when cggm_solve(..., keep_csr=True)
@@ -212,9 +215,12 @@ def cggm_solve(X, Y, lam_Lambda: float, lam_Theta: float, tol: float = 1e-2, *,
              for i in range(opt.trace_len)]
     kst = None
     if ks is not None:
-        kst = {name: {"launches": ks.launches[k], "tiles": ks.tiles[k], "ms": ks.ms[k],
-                      "bytes": ks.bytes[k], "flops": ks.flops[k]}
-               for k, name in enumerate(("lambda_tile", "theta_tile"))}
+        kst = {}
+        for k, sweep in enumerate(("lambda", "theta")):
+            for j, stage in enumerate(STAGES):
+                kst[f"{sweep}_{stage}"] = {"launches": ks.waves[k], "tiles": ks.tiles[k],
+                                           "ms": ks.ms[k][j], "bytes": ks.bytes[k][j],
+                                           "flops": ks.flops[k][j]}
     return SolveResult(Lambda=Lam, Theta=Th, f=f.value, iters=it.value, status=st.value,
                        nnz_Lambda=nL.value, nnz_Theta=nT.value, trace=trace, csr=csr,
                        kernel_stats=kst)

@@ -9,11 +9,21 @@
 //     index sets are pairwise disjoint; a tile's updates touch U = D Sigma
 //     only in its row and column index sets.
 // Inside a tile the coordinates are visited in row-major order with exact
-// Gauss-Seidel semantics: the tile's gradient snapshot b is computed by an
-// MFMA tile product from the maintained product, then every coordinate update
-// is folded into the remaining b values of the tile through the exact
-// Hessian couplings.  Tiles of the same wave see each other's updates only
-// through the next wave's snapshot.
+// Gauss-Seidel semantics: the tile's gradient snapshot b is computed from the
+// maintained product, then every coordinate update is folded into the
+// remaining b values of the tile through the exact Hessian couplings.  Tiles
+// of the same wave see each other's updates only through the next wave's
+// snapshot.
+//
+// A wave runs three kernels:
+//   1. snapshot: the MFMA column-slab products of every tile, split over the
+//      K range into parts of about SNAP_ROWS rows, one wavefront per
+//      (tile, 32x32 quadrant, K part); partial tiles go to a scratch buffer;
+//   2. Gauss-Seidel: one workgroup per tile sums its partials in part order
+//      (deterministic), adds the gradient term and runs the exact in-tile CD;
+//   3. update of the maintained product's rows with the tile deltas.
+// Which tiles have active coordinates is decided once per sweep (the screen
+// uses the gradient and the parameters at the start of the sweep).
 #include <math.h>
 
 #include <algorithm>
@@ -30,37 +40,130 @@ constexpr int LD = T + 1;
 constexpr int TT = THETA_TILE;    // 64
 constexpr int LDT = TT + 1;
 
-// Largest number of workgroups one tile's gradient snapshot is split over.
-constexpr int MAX_SPLIT = CD_MAX_SPLIT;
-
-// Cross-workgroup sum of a tile's snapshot split over S workgroups: each
-// workgroup stores its partial (out, TS x TS) in `slots` (S partials), then
-// counts itself in `*cnt`; the workgroup that arrives last sums the S partials
-// in slot order (so the result does not depend on arrival order) into `out`,
-// resets the counter for the next wave and returns true.  The others return
-// false.  All CD_BLOCK threads call it.
-template <int TS, int LDO>
-__device__ bool combine_partials(double (*out)[LDO], double *slots, int part, int S, int *cnt) {
-    if (S == 1) return true;
-    const int tid = threadIdx.x;
-    double *mine = slots + (int64_t)part * TS * TS;
-    for (int e = tid; e < TS * TS; e += CD_BLOCK) mine[e] = out[e / TS][e % TS];
-    __threadfence();
-    __syncthreads();
-    __shared__ int last;
-    if (tid == 0) last = (atomicAdd(cnt, 1) == S - 1);
-    __syncthreads();
-    if (!last) return false;
-    __threadfence();
-    if (tid == 0) *cnt = 0;
-    for (int e = tid; e < TS * TS; e += CD_BLOCK) {
-        double v = 0.0;
-        for (int k = 0; k < S; ++k)
-            v += __builtin_nontemporal_load(slots + (int64_t)k * TS * TS + e);
-        out[e / TS][e % TS] = v;
+// ----------------------------------------------------------------- activity --
+// active[r] = 1 when rect r holds a coordinate with |G| > lam or P != 0
+// (upper triangle only for the diagonal rects of Lambda).
+__global__ __launch_bounds__(BLOCK) void tile_activity_kernel(const TileRect *__restrict__ rects,
+                                                              int64_t ld, const double *__restrict__ G,
+                                                              const double *__restrict__ P,
+                                                              double lam, int upper,
+                                                              int *__restrict__ active) {
+    const TileRect rc = rects[blockIdx.x];
+    const int R = rc.r1 - rc.r0, C = rc.c1 - rc.c0;
+    const bool diag = upper && rc.r0 == rc.c0;
+    int any = 0;
+    for (int k = threadIdx.x; k < R * C; k += BLOCK) {
+        const int r = k / C, c = k % C;
+        if (!diag || c >= r) {
+            const int64_t idx = (int64_t)(rc.r0 + r) * ld + rc.c0 + c;
+            any |= (fabs(G[idx]) > lam || P[idx] != 0.0);
+        }
     }
-    __syncthreads();
-    return true;
+    any = __syncthreads_or(any);
+    if (threadIdx.x == 0) active[blockIdx.x] = any;
+}
+
+// ----------------------------------------------------------------- snapshot --
+// Operand pairs of the snapshot products: out[m][n] += sum_k A[k][r0 + m] B[k][c0 + n]
+// (A, B symmetric or stored so that the tile's rows/columns are column slabs).
+template <int NPAIR>
+struct SnapArgs {
+    const double *A[NPAIR];
+    int64_t lda[NPAIR];
+    const double *B[NPAIR];
+    int64_t ldb[NPAIR];
+};
+
+// One wavefront per workgroup computes one 32 x 32 quadrant of one tile's
+// snapshot over one part of the K range, loading its MFMA operands straight
+// from HBM (16 consecutive doubles per operand row, U k-steps in flight) and
+// writing the partial from its accumulators.  No LDS, so many wavefronts stay
+// resident per CU to cover the memory latency.
+template <int TS, int NPAIR>
+__global__ __launch_bounds__(WAVE) void snapshot_kernel(const TileRect *__restrict__ rects,
+                                                        const int *__restrict__ active, int S,
+                                                        int64_t K, SnapArgs<NPAIR> args,
+                                                        double *__restrict__ partial) {
+    constexpr int NQD = TS / 32, NQ = NQD * NQD, U = 4;
+    const int64_t wg = blockIdx.x;
+    const int quad = (int)(wg % NQ);
+    const int64_t t = wg / NQ;
+    const int s = (int)(t % S);
+    const int e = (int)(t / S);
+    if (!active[e]) return;
+    const TileRect rc = rects[e];
+    const int R = rc.r1 - rc.r0, C = rc.c1 - rc.c0;
+    const int mo = (quad / NQD) * 32, no = (quad % NQD) * 32;
+    if (mo >= R || no >= C) return;                  // quadrant outside a ragged tile
+    const int lane = threadIdx.x, col = lane & 15, krow = lane >> 4;
+    const int64_t ksteps = (K + 3) / 4;
+    const int64_t s0 = (ksteps * s) / S, s1 = (ksteps * (s + 1)) / S;
+    const bool am0 = mo + col < R, am1 = mo + col + 16 < R;
+    const bool bn0 = no + col < C, bn1 = no + col + 16 < C;
+    v4d acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int pp = 0; pp < NPAIR; ++pp) {
+        const double *A = args.A[pp] + rc.r0 + mo;
+        const double *B = args.B[pp] + rc.c0 + no;
+        const int64_t lda = args.lda[pp], ldb = args.ldb[pp];
+        for (int64_t st = s0; st < s1; st += U) {
+            double a[U][2], b[U][2];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t k = (st + u) * 4 + krow;
+                const bool kv = (st + u) < s1 && k < K;
+                a[u][0] = (kv && am0) ? A[k * lda + col] : 0.0;
+                a[u][1] = (kv && am1) ? A[k * lda + col + 16] : 0.0;
+                b[u][0] = (kv && bn0) ? B[k * ldb + col] : 0.0;
+                b[u][1] = (kv && bn1) ? B[k * ldb + col + 16] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        acc[i][j] = mfma_f64_16x16x4(a[u][i], b[u][j], acc[i][j]);
+        }
+    }
+    double *out = partial + ((int64_t)e * S + s) * TS * TS;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                out[(mo + i * 16 + krow + 4 * r) * TS + no + j * 16 + col] = acc[i][j][r];
+}
+
+// Sum of the S partials of tile e in part order, for m < R, n < C.
+template <int TS, int LDO>
+__device__ void sum_partials(const double *__restrict__ partial, int e, int S, int R, int C,
+                             double (*out)[LDO]) {
+    const double *base = partial + (int64_t)e * S * TS * TS;
+    for (int k = threadIdx.x; k < TS * TS; k += BLOCK) {
+        const int m = k / TS, n = k % TS;
+        double v = 0.0;
+        if (m < R && n < C) {
+            int s = 0;
+            for (; s + 4 <= S; s += 4) {      // four independent loads in flight
+                const double v0 = base[(int64_t)(s + 0) * TS * TS + k];
+                const double v1 = base[(int64_t)(s + 1) * TS * TS + k];
+                const double v2 = base[(int64_t)(s + 2) * TS * TS + k];
+                const double v3 = base[(int64_t)(s + 3) * TS * TS + k];
+                v += v0;
+                v += v1;
+                v += v2;
+                v += v3;
+            }
+            for (; s < S; ++s) v += base[(int64_t)s * TS * TS + k];
+        }
+        out[m][n] = v;
+    }
 }
 
 // ------------------------------------------------------------------ Theta ---
@@ -69,63 +172,43 @@ __device__ bool combine_partials(double (*out)[LDO], double *slots, int part, in
 // with b = 2 Sxy_ij + 2 (Sxx V)_ij and a = 2 Sxx_ii Sigma_jj; the minimiser is
 // Theta_ij <- S_{lamT/a}(Theta_ij - b/a).  Moving Theta_ij by mu changes the b
 // of coordinate (i', j') by 2 Sxx_i'i Sigma_jj' mu.
-__global__ __launch_bounds__(CD_BLOCK) void theta_tile_kernel(
-    const TileRect *__restrict__ rects, int64_t p, int64_t q, const double *__restrict__ Sxx,
+__global__ __launch_bounds__(BLOCK) void theta_gs_kernel(
+    const TileRect *__restrict__ rects, const int *__restrict__ active, int S,
+    const double *__restrict__ partial, int64_t p, int64_t q, const double *__restrict__ Sxx,
     const double *__restrict__ Sxy, const double *__restrict__ Sigma,
-    const double *__restrict__ V, const double *__restrict__ GT, double *__restrict__ Theta,
-    double lamT, double *__restrict__ dT, int *__restrict__ changed,
-    unsigned long long *__restrict__ counters, int S, double *__restrict__ partial,
-    int *__restrict__ tile_cnt) {
-    const int e = blockIdx.x / S, part = blockIdx.x % S;
-    const TileRect rc = rects[e];
-    const int R = rc.r1 - rc.r0, C = rc.c1 - rc.c0;
+    const double *__restrict__ GT, double *__restrict__ Theta, double lamT,
+    double *__restrict__ dT, int *__restrict__ changed, unsigned long long *__restrict__ ctr) {
+    const int e = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
-
-    // Skip tiles without active coordinates (|G| > lambda or Theta != 0).
-    int act_any = 0;
-    for (int k = tid; k < TT * TT; k += CD_BLOCK) {
-        const int r = k / TT, c = k % TT;
-        if (r < R && c < C) {
-            const int64_t idx = (int64_t)(rc.r0 + r) * q + rc.c0 + c;
-            act_any |= (fabs(GT[idx]) > lamT || Theta[idx] != 0.0);
-        }
-    }
-    if (!__syncthreads_or(act_any)) {
-        if (tid == 0 && part == 0) changed[e] = 0;
+    if (!active[e]) {
+        if (tid == 0) changed[e] = 0;
         return;
     }
+    const TileRect rc = rects[e];
+    const int R = rc.r1 - rc.r0, C = rc.c1 - rc.c0;
     __shared__ double Bs[TT][LDT];    // gradient snapshot, then corrected in place
-    __shared__ union {
-        double red[slab_red_doubles<TT>()];
-        struct {
-            double sxx[TT][LDT];      // Sxx[I, I]
-            double sig[TT][LDT];      // Sigma[J, J]
-        } b;
-    } sh;
-    auto &sxx = sh.b.sxx;
-    auto &sig = sh.b.sig;
-
-    // This workgroup's share of (Sxx V)[I, J] = Sxx[:, I]^T V[:, J] (Sxx
-    // symmetric): rows [k0, k1) of the K range.
-    const int64_t k0 = (p * part) / S, k1 = (p * (part + 1)) / S;
-    const SlabPair pr[1] = {{Sxx + k0 * p + rc.r0, p, V + k0 * q + rc.c0, q}};
-    slab_product<TT, 1, LDT>(pr, k1 - k0, R, C, sh.red, Bs);
-    if (!combine_partials<TT, LDT>(Bs, partial + (int64_t)e * MAX_SPLIT * TT * TT, part, S,
-                                   tile_cnt + e))
-        return;                       // another workgroup finishes this tile
-    if (counters && tid == 0) {
-        // slabs Sxx[:, I], V[:, J]; blocks Sxx[I, I], Sigma[J, J]; Sxy, G, Theta
-        // tile reads; Theta and delta writes
-        atomicAdd(counters + 0, 1ull);
-        atomicAdd(counters + 1, (unsigned long long)(8 * (p * (R + C) + R * R + C * C + 5 * R * C)));
-        atomicAdd(counters + 2, (unsigned long long)(2 * (int64_t)R * C * p + 4 * (int64_t)R * C * C));
-    }
-    for (int k = tid; k < TT * TT; k += CD_BLOCK) {
+    __shared__ double sxx[TT][LDT];   // Sxx[I, I]
+    __shared__ double sig[TT][LDT];   // Sigma[J, J]
+    sum_partials<TT, LDT>(partial, e, S, R, C, Bs);
+    for (int k = tid; k < TT * TT; k += BLOCK) {
         const int r = k / TT, c = k % TT;
-        if (r < R && c < C) Bs[r][c] = 2.0 * Sxy[(int64_t)(rc.r0 + r) * q + rc.c0 + c] +
-                                       2.0 * Bs[r][c];
+        if (r < R && c < C)
+            Bs[r][c] = 2.0 * Sxy[(int64_t)(rc.r0 + r) * q + rc.c0 + c] + 2.0 * Bs[r][c];
         sxx[r][c] = (r < R && c < R) ? Sxx[(int64_t)(rc.r0 + r) * p + rc.r0 + c] : 0.0;
         sig[r][c] = (r < C && c < C) ? Sigma[(int64_t)(rc.c0 + r) * q + rc.c0 + c] : 0.0;
+    }
+    if (ctr && tid == 0) {
+        const int64_t RC = (int64_t)R * C;
+        atomicAdd(ctr + 0, 1ull);
+        // snapshot: slabs Sxx[:, I] and V[:, J]
+        atomicAdd(ctr + 1, (unsigned long long)(8 * p * (R + C)));
+        atomicAdd(ctr + 2, (unsigned long long)(2 * RC * p));
+        // Gauss-Seidel: Sxx[I, I], Sigma[J, J], Sxy / G / Theta reads, Theta and delta writes
+        atomicAdd(ctr + 3, (unsigned long long)(8 * (R * R + C * C + 5 * RC)));
+        atomicAdd(ctr + 4, (unsigned long long)(4 * RC * C));
+        // update: Sigma[J, :] read, V[I, :] read and written
+        atomicAdd(ctr + 5, (unsigned long long)(8 * q * (C + 2 * R)));
+        atomicAdd(ctr + 6, (unsigned long long)(2 * RC * q));
     }
     __syncthreads();
     if (wid != 0) return;
@@ -195,43 +278,37 @@ __device__ void rowblock_update(const double *__restrict__ Delta, bool trans, in
         dl[k][m] = (m < R && k < Kd) ? (trans ? Delta[k * TK + m] : Delta[m * TK + k]) : 0.0;
     }
     __syncthreads();
-    constexpr int KST = TK / 4, NI = TR / 16;
+    constexpr int KST = TK / 4, NI = TR / 16, KH = KST / 2;
     const int col = lane & 15, krow = lane >> 4;
-    // Operands of one 64-column chunk: S values for the MFMA B operand and the
-    // current Out values this lane updates.  The next chunk's loads are issued
-    // before the current chunk's MFMAs so their latency overlaps.
-    struct Chunk {
-        double bv[KST];
-        double ov[NI][4];
-    };
-    auto load = [&](int64_t c0, Chunk &ch) {
-        const int64_t n = c0 + wid * 16 + col;
-        const bool nv = c0 < c_end && n < c_end;
-#pragma unroll
-        for (int ks = 0; ks < KST; ++ks) {
-            const int k = ks * 4 + krow;
-            ch.bv[ks] = (nv && k < Kd) ? S[(int64_t)k * lds + n] : 0.0;
-        }
-#pragma unroll
-        for (int i = 0; i < NI; ++i)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int m = i * 16 + krow + 4 * r;
-                ch.ov[i][r] = (nv && m < R) ? Out[(int64_t)m * ldo + n] : 0.0;
-            }
-    };
-    auto apply = [&](int64_t c0, const Chunk &ch) {
+    // Per 64-column chunk: the current Out values go straight into the MFMA
+    // accumulators, then the S operands stream in two halves of the K range.
+#pragma unroll 1
+    for (int64_t c0 = c_begin; c0 < c_end; c0 += 64) {
         const int64_t n = c0 + wid * 16 + col;
         const bool nv = n < c_end;
         v4d acc[NI];
 #pragma unroll
         for (int i = 0; i < NI; ++i)
-            acc[i] = v4d{ch.ov[i][0], ch.ov[i][1], ch.ov[i][2], ch.ov[i][3]};
 #pragma unroll
-        for (int ks = 0; ks < KST; ++ks)
+            for (int r = 0; r < 4; ++r) {
+                const int m = i * 16 + krow + 4 * r;
+                acc[i][r] = (nv && m < R) ? Out[(int64_t)m * ldo + n] : 0.0;
+            }
+#pragma unroll 1
+        for (int h = 0; h < 2; ++h) {
+            double bv[KH];
 #pragma unroll
-            for (int i = 0; i < NI; ++i)
-                acc[i] = mfma_f64_16x16x4(dl[ks * 4 + krow][i * 16 + col], ch.bv[ks], acc[i]);
+            for (int ks = 0; ks < KH; ++ks) {
+                const int k = (h * KH + ks) * 4 + krow;
+                bv[ks] = (nv && k < Kd) ? S[(int64_t)k * lds + n] : 0.0;
+            }
+#pragma unroll
+            for (int ks = 0; ks < KH; ++ks)
+#pragma unroll
+                for (int i = 0; i < NI; ++i)
+                    acc[i] = mfma_f64_16x16x4(dl[(h * KH + ks) * 4 + krow][i * 16 + col], bv[ks],
+                                              acc[i]);
+        }
         if (nv) {
 #pragma unroll
             for (int i = 0; i < NI; ++i)
@@ -241,21 +318,13 @@ __device__ void rowblock_update(const double *__restrict__ Delta, bool trans, in
                     if (m < R) Out[(int64_t)m * ldo + n] = acc[i][r];
                 }
         }
-    };
-    Chunk a, b;
-    load(c_begin, a);
-    for (int64_t c0 = c_begin; c0 < c_end; c0 += 128) {
-        load(c0 + 64, b);
-        apply(c0, a);
-        load(c0 + 128, a);
-        if (c0 + 64 < c_end) apply(c0 + 64, b);
     }
 }
 
 constexpr int UPD_CHUNKS = 4;   // 64-column chunks per update workgroup
 
 // V[I, :] += dTheta[I, J] Sigma[J, :] for every changed tile of the wave.
-__global__ __launch_bounds__(BLOCK) void theta_v_update_kernel(
+__global__ __launch_bounds__(BLOCK, 4) void theta_v_update_kernel(
     const TileRect *__restrict__ rects, int64_t q, const double *__restrict__ Sigma,
     const double *__restrict__ dT, const int *__restrict__ changed, double *__restrict__ V) {
     const int e = blockIdx.y;
@@ -283,64 +352,25 @@ __global__ __launch_bounds__(BLOCK) void theta_v_update_kernel(
 // coordinate (i', j') by
 //   mu_e [SP_i'i S_lj' + SP_i'l S_ij' + P_ij' S_i'l + P_lj' S_ii']
 // for a move at (i, l), with mu_e = mu (l != i) or mu / 2 (l == i).
-__global__ __launch_bounds__(CD_BLOCK) void lambda_tile_kernel(
-    const TileRect *__restrict__ rects, int64_t q, const double *__restrict__ Sigma,
-    const double *__restrict__ Psi, const double *__restrict__ SP,
-    const double *__restrict__ GL, const double *__restrict__ Lam, double lamL,
-    double *__restrict__ D, const double *__restrict__ U, double *__restrict__ dD,
-    int *__restrict__ changed, unsigned long long *__restrict__ counters, int S,
-    double *__restrict__ partial, int *__restrict__ tile_cnt) {
-    const int e = blockIdx.x / S, part = blockIdx.x % S;
+__global__ __launch_bounds__(BLOCK) void lambda_gs_kernel(
+    const TileRect *__restrict__ rects, const int *__restrict__ active, int S,
+    const double *__restrict__ partial, int64_t q, const double *__restrict__ Sigma,
+    const double *__restrict__ Psi, const double *__restrict__ GL,
+    const double *__restrict__ Lam, double lamL, double *__restrict__ D,
+    double *__restrict__ dD, int *__restrict__ changed, unsigned long long *__restrict__ ctr) {
+    const int e = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
+    if (!active[e]) {
+        if (tid == 0) changed[e] = 0;
+        return;
+    }
     const TileRect rc = rects[e];
     const int R = rc.r1 - rc.r0, C = rc.c1 - rc.c0;
     const bool diag = rc.r0 == rc.c0;
-    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
-
-    int act_any = 0;
-    for (int k = tid; k < T * T; k += CD_BLOCK) {
-        const int r = k / T, c = k % T;
-        if (r < R && c < C && (!diag || c >= r)) {
-            const int64_t idx = (int64_t)(rc.r0 + r) * q + rc.c0 + c;
-            act_any |= (fabs(GL[idx]) > lamL || Lam[idx] != 0.0);
-        }
-    }
-    if (!__syncthreads_or(act_any)) {
-        if (tid == 0 && part == 0) changed[e] = 0;
-        return;
-    }
     __shared__ double Bs[T][LD];
-    __shared__ union {
-        double red[slab_red_doubles<T>()];
-        struct {
-            double sII[T][LD], pII[T][LD], sJJ[T][LD], pJJ[T][LD], sIJ[T][LD], pIJ[T][LD];
-        } b;
-    } sh;
-    auto &sII = sh.b.sII;
-    auto &pII = sh.b.pII;
-    auto &sJJ = sh.b.sJJ;
-    auto &pJJ = sh.b.pJJ;
-    auto &sIJ = sh.b.sIJ;
-    auto &pIJ = sh.b.pIJ;
-
-    // b snapshot: G + (SP U)[I, J] + ((Psi U)[J, I])^T
-    //   = G + SP[:, I]^T U[:, J] + U[:, I]^T Psi[:, J]   (SP, Psi symmetric);
-    // this workgroup sums the rows [k0, k1) of the K range.
-    const int64_t k0 = (q * part) / S, k1 = (q * (part + 1)) / S;
-    const SlabPair pr[2] = {{SP + k0 * q + rc.r0, q, U + k0 * q + rc.c0, q},
-                            {U + k0 * q + rc.r0, q, Psi + k0 * q + rc.c0, q}};
-    slab_product<T, 2, LD>(pr, k1 - k0, R, C, sh.red, Bs);
-    if (!combine_partials<T, LD>(Bs, partial + (int64_t)e * MAX_SPLIT * T * T, part, S,
-                                 tile_cnt + e))
-        return;                       // another workgroup finishes this tile
-    if (counters && tid == 0) {
-        // slabs SP[:, I], U[:, J], U[:, I], Psi[:, J]; six Sigma / Psi blocks;
-        // G and Lambda tile reads; D (both triangles) and delta writes
-        atomicAdd(counters + 0, 1ull);
-        atomicAdd(counters + 1, (unsigned long long)(8 * (2 * q * (R + C) + 2 * R * R + 2 * C * C +
-                                                         7 * R * C)));
-        atomicAdd(counters + 2, (unsigned long long)(4 * (int64_t)R * C * q + 16 * (int64_t)R * C * C));
-    }
-    for (int k = tid; k < T * T; k += CD_BLOCK) {
+    __shared__ double sII[T][LD], pII[T][LD], sJJ[T][LD], pJJ[T][LD], sIJ[T][LD], pIJ[T][LD];
+    sum_partials<T, LD>(partial, e, S, R, C, Bs);
+    for (int k = tid; k < T * T; k += BLOCK) {
         const int r = k / T, c = k % T;
         const bool ii = r < R && c < R, jj = r < C && c < C, ij = r < R && c < C;
         if (ij) Bs[r][c] += GL[(int64_t)(rc.r0 + r) * q + rc.c0 + c];
@@ -350,6 +380,22 @@ __global__ __launch_bounds__(CD_BLOCK) void lambda_tile_kernel(
         pJJ[r][c] = jj ? Psi[(int64_t)(rc.c0 + r) * q + rc.c0 + c] : 0.0;
         sIJ[r][c] = ij ? Sigma[(int64_t)(rc.r0 + r) * q + rc.c0 + c] : 0.0;
         pIJ[r][c] = ij ? Psi[(int64_t)(rc.r0 + r) * q + rc.c0 + c] : 0.0;
+    }
+    if (ctr && tid == 0) {
+        const int64_t RC = (int64_t)R * C;
+        atomicAdd(ctr + 0, 1ull);
+        // snapshot: slabs SP[:, I], U[:, J], U[:, I], Psi[:, J]
+        atomicAdd(ctr + 1, (unsigned long long)(8 * 2 * q * (R + C)));
+        atomicAdd(ctr + 2, (unsigned long long)(4 * RC * q));
+        // Gauss-Seidel: six Sigma / Psi blocks, G and Lambda reads, D (both
+        // triangles) and delta writes
+        atomicAdd(ctr + 3, (unsigned long long)(8 * (2 * R * R + 2 * C * C + 7 * RC)));
+        atomicAdd(ctr + 4, (unsigned long long)(16 * RC * C));
+        // update: Sigma rows read, U rows read and written (both index sets
+        // of an off-diagonal tile)
+        const int64_t ub = diag ? 8 * q * 3 * R : 8 * q * 3 * (R + C);
+        atomicAdd(ctr + 5, (unsigned long long)ub);
+        atomicAdd(ctr + 6, (unsigned long long)((diag ? 2 : 4) * RC * q));
     }
     __syncthreads();
     if (wid != 0) return;
@@ -440,7 +486,7 @@ __global__ __launch_bounds__(CD_BLOCK) void lambda_tile_kernel(
 
 // U[I, :] += dD Sigma[J, :] and U[J, :] += dD^T Sigma[I, :] (off-diagonal
 // tiles), or U[I, :] += dD_sym Sigma[I, :] (diagonal tiles).
-__global__ __launch_bounds__(BLOCK) void lambda_u_update_kernel(
+__global__ __launch_bounds__(BLOCK, 4) void lambda_u_update_kernel(
     const TileRect *__restrict__ rects, int64_t q, const double *__restrict__ Sigma,
     const double *__restrict__ dD, const int *__restrict__ changed, double *__restrict__ U) {
     const int e = blockIdx.y, half = blockIdx.z;
@@ -461,53 +507,84 @@ __global__ __launch_bounds__(BLOCK) void lambda_u_update_kernel(
                               U + (int64_t)rc.c0 * q, q, c_begin, c_end, dl);
 }
 
-// Workgroups per tile snapshot: about 1024 workgroups per wave, at most
-// MAX_SPLIT, and at least 256 rows of K per workgroup.
-int snapshot_split(int nrect, int64_t K) {
-    int S = (1024 + nrect - 1) / nrect;
-    S = std::min(S, MAX_SPLIT);
-    S = (int)std::min<int64_t>(S, std::max<int64_t>(1, K / 256));
-    return std::max(S, 1);
+// Parts of the K range per tile snapshot: enough wavefronts per launch
+// (about SNAP_WAVES) to fill the GPU, at least SNAP_MIN_ROWS rows per part, at
+// most CD_MAX_PARTS parts.
+constexpr int64_t SNAP_WAVES = 8192, SNAP_MIN_ROWS = 256;
+int snapshot_parts(int nrect, int quadrants, int64_t K) {
+    int64_t S = SNAP_WAVES / std::max<int64_t>(1, (int64_t)nrect * quadrants);
+    S = std::min<int64_t>(S, K / SNAP_MIN_ROWS);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(CD_MAX_PARTS, S));
+}
+
+inline void record(hipStream_t s, const WaveProbe *probe, int k) {
+    if (probe) CGGM_HIP(hipEventRecord(probe->ev[k], s));
 }
 
 }  // namespace
 
-void theta_wave(hipStream_t s, const TileRect *rects_dev, int nrect, int64_t p, int64_t q,
-                const double *Sxx, const double *Sxy, const double *Sigma, double *V,
-                const double *GT, double *Theta, double lamT, double *dT, int *changed,
-                const CdScratch &scr, const WaveProbe *probe) {
+void theta_activity(hipStream_t s, const TileRect *rects_dev, int nrect, int64_t q,
+                    const double *GT, const double *Theta, double lamT, int *active) {
     if (nrect <= 0) return;
-    const int S = snapshot_split(nrect, p);
-    if (probe) CGGM_HIP(hipEventRecord(probe->start, s));
-    theta_tile_kernel<<<nrect * S, CD_BLOCK, 0, s>>>(rects_dev, p, q, Sxx, Sxy, Sigma, V, GT,
-                                                     Theta, lamT, dT, changed,
-                                                     probe ? probe->counters : nullptr, S,
-                                                     scr.partial, scr.tile_cnt);
+    tile_activity_kernel<<<nrect, BLOCK, 0, s>>>(rects_dev, q, GT, Theta, lamT, 0, active);
     CGGM_LAUNCH_CHECK();
-    if (probe) CGGM_HIP(hipEventRecord(probe->stop, s));
+}
+
+void lambda_activity(hipStream_t s, const TileRect *rects_dev, int nrect, int64_t q,
+                     const double *GL, const double *Lam, double lamL, int *active) {
+    if (nrect <= 0) return;
+    tile_activity_kernel<<<nrect, BLOCK, 0, s>>>(rects_dev, q, GL, Lam, lamL, 1, active);
+    CGGM_LAUNCH_CHECK();
+}
+
+void theta_wave(hipStream_t s, const TileRect *rects_dev, const int *active, int nrect,
+                int64_t p, int64_t q, const double *Sxx, const double *Sxy, const double *Sigma,
+                double *V, const double *GT, double *Theta, double lamT, double *dT,
+                int *changed, const CdScratch &scr, const WaveProbe *probe) {
+    if (nrect <= 0) return;
+    const int S = snapshot_parts(nrect, 4, p);
+    SnapArgs<1> args{{Sxx}, {p}, {V}, {q}};
+    record(s, probe, 0);
+    snapshot_kernel<TT, 1><<<(unsigned)((int64_t)nrect * S * 4), WAVE, 0, s>>>(
+        rects_dev, active, S, p, args, scr.partial);
+    CGGM_LAUNCH_CHECK();
+    record(s, probe, 1);
+    theta_gs_kernel<<<nrect, BLOCK, 0, s>>>(rects_dev, active, S, scr.partial, p, q, Sxx, Sxy,
+                                            Sigma, GT, Theta, lamT, dT, changed,
+                                            probe ? probe->counters : nullptr);
+    CGGM_LAUNCH_CHECK();
+    record(s, probe, 2);
     const int64_t cols_per_wg = 64 * UPD_CHUNKS;
     dim3 grid((unsigned)((q + cols_per_wg - 1) / cols_per_wg), (unsigned)nrect);
     theta_v_update_kernel<<<grid, BLOCK, 0, s>>>(rects_dev, q, Sigma, dT, changed, V);
     CGGM_LAUNCH_CHECK();
+    record(s, probe, 3);
 }
 
-void lambda_wave(hipStream_t s, const TileRect *rects_dev, int nrect, int64_t q,
-                 const double *Sigma, const double *Psi, const double *SP, const double *GL,
-                 const double *Lam, double lamL, double *D, double *U, double *dD,
-                 int *changed, const CdScratch &scr, const WaveProbe *probe) {
+void lambda_wave(hipStream_t s, const TileRect *rects_dev, const int *active, int nrect,
+                 int64_t q, const double *Sigma, const double *Psi, const double *SP,
+                 const double *GL, const double *Lam, double lamL, double *D, double *U,
+                 double *dD, int *changed, const CdScratch &scr, const WaveProbe *probe) {
     if (nrect <= 0) return;
-    const int S = snapshot_split(nrect, q);
-    if (probe) CGGM_HIP(hipEventRecord(probe->start, s));
-    lambda_tile_kernel<<<nrect * S, CD_BLOCK, 0, s>>>(rects_dev, q, Sigma, Psi, SP, GL, Lam,
-                                                      lamL, D, U, dD, changed,
-                                                      probe ? probe->counters : nullptr, S,
-                                                      scr.partial, scr.tile_cnt);
+    const int S = snapshot_parts(nrect, 1, q);
+    // b snapshot: G + (SP U)[I, J] + ((Psi U)[J, I])^T
+    //   = G + SP[:, I]^T U[:, J] + U[:, I]^T Psi[:, J]   (SP, Psi symmetric)
+    SnapArgs<2> args{{SP, U}, {q, q}, {U, Psi}, {q, q}};
+    record(s, probe, 0);
+    snapshot_kernel<T, 2><<<(unsigned)((int64_t)nrect * S), WAVE, 0, s>>>(rects_dev, active, S, q,
+                                                                          args, scr.partial);
     CGGM_LAUNCH_CHECK();
-    if (probe) CGGM_HIP(hipEventRecord(probe->stop, s));
+    record(s, probe, 1);
+    lambda_gs_kernel<<<nrect, BLOCK, 0, s>>>(rects_dev, active, S, scr.partial, q, Sigma, Psi, GL,
+                                             Lam, lamL, D, dD, changed,
+                                             probe ? probe->counters : nullptr);
+    CGGM_LAUNCH_CHECK();
+    record(s, probe, 2);
     const int64_t cols_per_wg = 64 * UPD_CHUNKS;
     dim3 grid((unsigned)((q + cols_per_wg - 1) / cols_per_wg), (unsigned)nrect, 2);
     lambda_u_update_kernel<<<grid, BLOCK, 0, s>>>(rects_dev, q, Sigma, dD, changed, U);
     CGGM_LAUNCH_CHECK();
+    record(s, probe, 3);
 }
 
 }  // namespace cggm

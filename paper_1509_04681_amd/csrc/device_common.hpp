@@ -124,10 +124,10 @@ constexpr int CD_BLOCK = 512;
 // the 8 waves of a CD_BLOCK workgroup: the output is split into 32 x 32
 // quadrants and the K range into KS contiguous parts, one wave per
 // (quadrant, part).  Each wave loads its MFMA operands directly from global
-// memory (16 consecutive doubles per operand row) with two register buffers of
-// U k-steps, so one buffer's loads are in flight while the other feeds the
-// MFMAs; the KS partial tiles are summed through `red` (LDS, (KS - 1) x TS x
-// (TS + 1) doubles).  All CD_BLOCK threads must call it; barriers included.
+// memory (16 consecutive doubles per operand row, U k-steps in flight; the
+// other resident waves cover the latency); the KS partial tiles are summed
+// through `red` (LDS, (KS - 1) x TS x (TS + 1) doubles).  All CD_BLOCK
+// threads must call it; barriers included.
 template <int TS, int NPAIR, int LDO>
 __device__ void slab_product(const SlabPair (&pairs)[NPAIR], int64_t K, int ma, int nb,
                              double *red, double (*out)[LDO]) {
@@ -149,7 +149,7 @@ __device__ void slab_product(const SlabPair (&pairs)[NPAIR], int64_t K, int ma, 
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
-    double a0[U][2], b0[U][2], a1[U][2], b1[U][2];
+    double a0[U][2], b0[U][2];
     auto load = [&](const SlabPair &P, int64_t st, double (&a)[U][2], double (&b)[U][2]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -175,12 +175,9 @@ __device__ void slab_product(const SlabPair (&pairs)[NPAIR], int64_t K, int ma, 
 #pragma unroll
     for (int pp = 0; pp < NPAIR; ++pp) {
         const SlabPair P = pairs[pp];
-        load(P, s0, a0, b0);
-        for (int64_t st = s0; st < s1; st += 2 * U) {
-            load(P, st + U, a1, b1);
+        for (int64_t st = s0; st < s1; st += U) {
+            load(P, st, a0, b0);
             mma(a0, b0);
-            load(P, st + 2 * U, a0, b0);
-            mma(a1, b1);
         }
     }
     constexpr int LDR = TS + 1;

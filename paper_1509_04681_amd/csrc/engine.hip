@@ -199,8 +199,9 @@ struct Work {
     double *dT, *dD;                               // per-wave tile deltas
     double *partials, *scal;                       // reduction scratch, device scalars
     int *flag, *changed;
-    unsigned long long *kctr;                      // tile-kernel counters [2][3]
+    unsigned long long *kctr;                      // sweep counters [2][8]
     CdScratch cd;                                  // split-snapshot scratch
+    int *act_theta, *act_lambda;                   // per-rect activity of a sweep
     TileRect *rects_theta, *rects_lambda;
     int max_tiles = 0;
 };
@@ -242,9 +243,10 @@ void layout(Arena &a, Work &w, int64_t n, int64_t p, int64_t q, int64_t ntheta_r
     w.scal = a.take<double>(NSCAL);
     w.flag = a.take<int>(4);
     w.changed = a.take<int>(max_tiles);
-    w.kctr = a.take<unsigned long long>(6);
-    w.cd.partial = a.take<double>((int64_t)max_tiles * CD_MAX_SPLIT * THETA_TILE * THETA_TILE);
-    w.cd.tile_cnt = a.take<int>(max_tiles + 1);
+    w.kctr = a.take<unsigned long long>(16);
+    w.cd.partial = a.take<double>((int64_t)max_tiles * CD_MAX_PARTS * THETA_TILE * THETA_TILE);
+    w.act_theta = a.take<int>(ntheta_rects);
+    w.act_lambda = a.take<int>(nlambda_rects);
     w.rects_theta = a.take<TileRect>(ntheta_rects);
     w.rects_lambda = a.take<TileRect>(nlambda_rects);
 }
@@ -335,16 +337,17 @@ TopStats read_top(Ctx &c, bool with_gradient_stats) {
     return t;
 }
 
-// HIP-event timing of one tile kernel kind (one event pair per wave launch).
+// HIP-event timing of the kernels of one sweep kind: four events per wave
+// (before the snapshot, Gauss-Seidel and update kernels, and after the update).
 struct KernelTimer {
     std::vector<hipEvent_t> ev;
     unsigned long long *counters = nullptr;
     int pending = 0;
-    int64_t launches = 0;
-    double ms = 0.0;
-    void init(int waves, unsigned long long *ctr) {
+    int64_t waves = 0;
+    double ms[3] = {0.0, 0.0, 0.0};
+    void init(int nwaves, unsigned long long *ctr) {
         counters = ctr;
-        ev.resize(2 * (size_t)waves, nullptr);
+        ev.resize(4 * (size_t)nwaves, nullptr);
         for (auto &e : ev) CGGM_HIP(hipEventCreate(&e));
     }
     ~KernelTimer() {
@@ -354,19 +357,20 @@ struct KernelTimer {
     bool on() const { return !ev.empty(); }
     WaveProbe probe(int k) {
         WaveProbe p;
-        p.start = ev[2 * k];
-        p.stop = ev[2 * k + 1];
+        for (int j = 0; j < 4; ++j) p.ev[j] = ev[4 * k + j];
         p.counters = counters;
         pending = k + 1;
         return p;
     }
-    // Sum the durations of the recorded launches (their events must be done).
+    // Sum the stage durations of the recorded waves (their events must be done).
     void collect() {
         for (int k = 0; k < pending; ++k) {
-            float m = 0.f;
-            CGGM_HIP(hipEventElapsedTime(&m, ev[2 * k], ev[2 * k + 1]));
-            ms += m;
-            ++launches;
+            for (int j = 0; j < 3; ++j) {
+                float m = 0.f;
+                CGGM_HIP(hipEventElapsedTime(&m, ev[4 * k + j], ev[4 * k + j + 1]));
+                ms[j] += m;
+            }
+            ++waves;
         }
         pending = 0;
     }
@@ -374,12 +378,15 @@ struct KernelTimer {
 
 void run_theta_sweep(Ctx &c, const Schedule &sch, KernelTimer *kt = nullptr) {
     Work &w = c.w;
+    theta_activity(c.s, w.rects_theta, (int)sch.rects.size(), w.q, w.GT, w.Th, c.lamT,
+                   w.act_theta);
     for (int k = 0; k < sch.waves(); ++k) {
         const int b = sch.wave_start[k], e = sch.wave_start[k + 1];
         WaveProbe pr;
         if (kt && kt->on()) pr = kt->probe(k);
-        theta_wave(c.s, w.rects_theta + b, e - b, w.p, w.q, w.Sxx, w.Sxy, w.Sig, w.V, w.GT,
-                   w.Th, c.lamT, w.dT, w.changed, w.cd, (kt && kt->on()) ? &pr : nullptr);
+        theta_wave(c.s, w.rects_theta + b, w.act_theta + b, e - b, w.p, w.q, w.Sxx, w.Sxy, w.Sig,
+                   w.V, w.GT, w.Th, c.lamT, w.dT, w.changed, w.cd,
+                   (kt && kt->on()) ? &pr : nullptr);
     }
 }
 
@@ -387,12 +394,15 @@ void run_lambda_sweep(Ctx &c, const Schedule &sch, KernelTimer *kt = nullptr) {
     Work &w = c.w;
     fill(c.s, w.q * w.q, 0.0, w.D);
     fill(c.s, w.q * w.q, 0.0, w.U);
+    lambda_activity(c.s, w.rects_lambda, (int)sch.rects.size(), w.q, w.GL, w.Lam, c.lamL,
+                    w.act_lambda);
     for (int k = 0; k < sch.waves(); ++k) {
         const int b = sch.wave_start[k], e = sch.wave_start[k + 1];
         WaveProbe pr;
         if (kt && kt->on()) pr = kt->probe(k);
-        lambda_wave(c.s, w.rects_lambda + b, e - b, w.q, w.Sig, w.Psi, w.SP, w.GL, w.Lam,
-                    c.lamL, w.D, w.U, w.dD, w.changed, w.cd, (kt && kt->on()) ? &pr : nullptr);
+        lambda_wave(c.s, w.rects_lambda + b, w.act_lambda + b, e - b, w.q, w.Sig, w.Psi, w.SP,
+                    w.GL, w.Lam, c.lamL, w.D, w.U, w.dD, w.changed, w.cd,
+                    (kt && kt->on()) ? &pr : nullptr);
     }
 }
 
@@ -516,14 +526,12 @@ int solve_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q
                             sizeof(TileRect) * la_sched.rects.size(), hipMemcpyHostToDevice, s));
     Ctx c{s, w, lamL, lamT};
     const int64_t qq = q * q, pq = p * q;
-    // arrival counters of the split snapshots start at zero (all-zero bits)
-    fill(s, (max_tiles + 2) / 2, 0.0, reinterpret_cast<double *>(w.cd.tile_cnt));
     check_finite(c, X, Y);
     KernelTimer kt_lambda, kt_theta;
     if (opt.kstats) {
-        fill(s, 6, 0.0, reinterpret_cast<double *>(w.kctr));   // all-zero bits
+        fill(s, 16, 0.0, reinterpret_cast<double *>(w.kctr));   // all-zero bits
         kt_lambda.init(la_sched.waves(), w.kctr);
-        kt_theta.init(th_sched.waves(), w.kctr + 3);
+        kt_theta.init(th_sched.waves(), w.kctr + 8);
     }
 
     auto t0 = std::chrono::steady_clock::now();
@@ -733,17 +741,18 @@ int solve_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q
     if (opt.kstats) {
         CGGM_HIP(hipStreamSynchronize(s));
         kt_theta.collect();
-        unsigned long long h[6];
+        unsigned long long h[16];
         CGGM_HIP(hipMemcpy(h, w.kctr, sizeof(h), hipMemcpyDeviceToHost));
         cggm_kernel_stats &ks = *opt.kstats;
-        ks.launches[0] = kt_lambda.launches;
-        ks.launches[1] = kt_theta.launches;
-        ks.ms[0] = kt_lambda.ms;
-        ks.ms[1] = kt_theta.ms;
+        const KernelTimer *kts[2] = {&kt_lambda, &kt_theta};
         for (int k = 0; k < 2; ++k) {
-            ks.tiles[k] = (int64_t)h[3 * k];
-            ks.bytes[k] = (double)h[3 * k + 1];
-            ks.flops[k] = (double)h[3 * k + 2];
+            ks.waves[k] = kts[k]->waves;
+            ks.tiles[k] = (int64_t)h[8 * k];
+            for (int j = 0; j < 3; ++j) {
+                ks.ms[k][j] = kts[k]->ms[j];
+                ks.bytes[k][j] = (double)h[8 * k + 1 + 2 * j];
+                ks.flops[k][j] = (double)h[8 * k + 2 + 2 * j];
+            }
         }
     }
     if (opt_in) opt_in->trace_len = trace_len;

@@ -131,38 +131,46 @@ struct TileRect {
 constexpr int LAMBDA_TILE = 32;   // tile edge of the Lambda CD tiles
 constexpr int THETA_TILE = 64;    // tile edge of the Theta CD tiles
 
-// Optional instrumentation of a wave: events recorded around the tile kernel
-// and device counters (processed tiles, algorithmic bytes, flops) it adds to.
+// Optional instrumentation of a wave: events recorded before the snapshot,
+// the Gauss-Seidel and the update kernels and after the update, and device
+// counters the Gauss-Seidel kernel adds each processed tile's algorithmic
+// traffic to: [0] tiles, [1, 2] snapshot bytes / flops, [3, 4] Gauss-Seidel
+// bytes / flops, [5, 6] update bytes / flops.
 struct WaveProbe {
-    hipEvent_t start = nullptr, stop = nullptr;
-    unsigned long long *counters = nullptr;   // [3]
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    unsigned long long *counters = nullptr;   // [8]
 };
 
-// Scratch of the split gradient snapshots: per tile of a wave, CD_MAX_SPLIT
-// partial tiles (THETA_TILE^2 doubles each) and an arrival counter (zero
-// between waves; the kernels reset it).
-constexpr int CD_MAX_SPLIT = 8;
+// Scratch of the split gradient snapshots: partial tiles of one wave
+// (nrect x parts x THETA_TILE^2 doubles at most).
+constexpr int CD_MAX_PARTS = 64;
 struct CdScratch {
-    double *partial = nullptr;   // max_tiles * CD_MAX_SPLIT * THETA_TILE^2
-    int *tile_cnt = nullptr;     // max_tiles
+    double *partial = nullptr;
 };
+
+// Activity of every rect of a sweep (1 when the rect holds a coordinate with
+// |G| > lambda or a nonzero parameter), decided once at the start of the sweep.
+void theta_activity(hipStream_t s, const TileRect *rects_dev, int nrect, int64_t q,
+                    const double *GT, const double *Theta, double lamT, int *active);
+void lambda_activity(hipStream_t s, const TileRect *rects_dev, int nrect, int64_t q,
+                     const double *GL, const double *Lam, double lamL, int *active);
 
 // One wave of the Theta sweep: every rect in `rects` (row- and column-disjoint)
 // runs exact Gauss-Seidel over its active coordinates from a snapshot of
 // b = 2 Sxy + 2 Sxx V, writes the updated Theta and its delta (dT, nrect
 // tiles of THETA_TILE^2), then V[rows, :] += dTheta Sigma[cols, :].
-void theta_wave(hipStream_t s, const TileRect *rects_dev, int nrect, int64_t p, int64_t q,
-                const double *Sxx, const double *Sxy, const double *Sigma, double *V,
-                const double *GT, double *Theta, double lamT, double *dT, int *changed,
-                const CdScratch &scr, const WaveProbe *probe = nullptr);
+void theta_wave(hipStream_t s, const TileRect *rects_dev, const int *active, int nrect,
+                int64_t p, int64_t q, const double *Sxx, const double *Sxy, const double *Sigma,
+                double *V, const double *GT, double *Theta, double lamT, double *dT,
+                int *changed, const CdScratch &scr, const WaveProbe *probe = nullptr);
 
 // One wave of the Lambda direction sweep over upper-triangle rects with
 // pairwise-disjoint index sets: exact Gauss-Seidel inside each rect from a
 // snapshot of b = G + SP U + (Psi U)^T, D written (both triangles), then
 // U rows of both index sets updated with the rect's delta.
-void lambda_wave(hipStream_t s, const TileRect *rects_dev, int nrect, int64_t q,
-                 const double *Sigma, const double *Psi, const double *SP, const double *GL,
-                 const double *Lam, double lamL, double *D, double *U, double *dD,
-                 int *changed, const CdScratch &scr, const WaveProbe *probe = nullptr);
+void lambda_wave(hipStream_t s, const TileRect *rects_dev, const int *active, int nrect,
+                 int64_t q, const double *Sigma, const double *Psi, const double *SP,
+                 const double *GL, const double *Lam, double lamL, double *D, double *U,
+                 double *dD, int *changed, const CdScratch &scr, const WaveProbe *probe = nullptr);
 
 }  // namespace cggm
