@@ -73,7 +73,8 @@ def _load():
     lib.orc_gradient.restype = ctypes.c_int
     lib.orc_active_sets.argtypes = [_i64, _i64, _dp, _dp, _dp, _dp, _d, _d, _u8p, _u8p]
     lib.orc_active_sets.restype = None
-    lib.orc_lambda_direction.argtypes = [_i64, _dp, _dp, _dp, _dp, _u8p, _d, _dp]
+    lib.orc_lambda_direction.argtypes = [_i64, _dp, _dp, _dp, _dp, _u8p, _d, ctypes.c_int,
+                                         _dp]
     lib.orc_lambda_direction.restype = None
     lib.orc_line_search.argtypes = [_i64, _i64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _d, _d,
                                     _d, _d, _d, ctypes.c_int, _dp, _dp, _ip]
@@ -81,7 +82,7 @@ def _load():
     lib.orc_theta_sweep.argtypes = [_i64, _i64, _dp, _dp, _dp, _u8p, _d, _dp]
     lib.orc_theta_sweep.restype = None
     lib.orc_solve.argtypes = [_i64, _i64, _i64, _dp, _dp, _d, _d, _d, ctypes.c_int,
-                              ctypes.c_int, ctypes.c_int, _dp, _dp, _ip, _dp,
+                              ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp, _ip, _dp,
                               ctypes.POINTER(_Trace)]
     lib.orc_solve.restype = ctypes.c_int
     _lib = lib
@@ -159,14 +160,15 @@ def active_sets(GL, GT, Lambda, Theta, lamL, lamT):
     return aL.astype(bool), aT.astype(bool)
 
 
-def lambda_direction(Sigma, Psi, GL, Lambda, actL, lamL):
-    """One lexicographic CD pass for the Newton direction of Eq. (6)."""
+def lambda_direction(Sigma, Psi, GL, Lambda, actL, lamL, passes=1):
+    """Lexicographic CD passes (one by default, Sec. 3) for the Newton direction
+    of Eq. (6), from D = 0."""
     Sigma, Psi, GL, Lambda = _c(Sigma), _c(Psi), _c(GL), _c(Lambda)
     actL = _c(actL, np.uint8)
     q = Sigma.shape[0]
     D = np.empty((q, q))
     _load().orc_lambda_direction(q, _p(Sigma), _p(Psi), _p(GL), _p(Lambda), _p(actL),
-                                 lamL, _p(D))
+                                 lamL, int(passes), _p(D))
     return D
 
 
@@ -204,7 +206,7 @@ class SolveResult:
 
 
 def solve(X, Y, lamL, lamT, tol=1e-2, max_iter=200, stall_iters=0, Lambda0=None,
-          Theta0=None) -> SolveResult:
+          Theta0=None, lambda_passes=1) -> SolveResult:
     """Alternating Newton CD (Algorithm 1) to the stopping rule of Sec. 5.1 with tol."""
     X, Y = _c(X), _c(Y)
     n, p = X.shape
@@ -222,8 +224,10 @@ def solve(X, Y, lamL, lamT, tol=1e-2, max_iter=200, stall_iters=0, Lambda0=None,
                                         (_i64p if v.dtype == np.int64 else _dp))
                    for k, v in arrs.items()})
     iters, f = ctypes.c_int(), ctypes.c_double()
+    if lambda_passes < 1:
+        raise ValueError("lambda_passes must be >= 1")
     st = _load().orc_solve(n, p, q, _p(X), _p(Y), lamL, lamT, tol, max_iter, stall_iters,
-                           int(warm), _p(Lam), _p(Th), ctypes.byref(iters), ctypes.byref(f),
+                           int(lambda_passes), int(warm), _p(Lam), _p(Th), ctypes.byref(iters), ctypes.byref(f),
                            ctypes.byref(tr))
     k = iters.value + 1
     trace = {key: v[:k].copy() for key, v in arrs.items()}

@@ -250,12 +250,13 @@ void orc_active_sets(int64_t p, int64_t q, const double *GL, const double *GT,
 
 void orc_lambda_direction(int64_t q, const double *Sigma, const double *Psi,
                           const double *GL, const double *Lambda, const uint8_t *actL,
-                          double lamL, double *D) {
+                          double lamL, int passes, double *D) {
     /* Coordinate descent on  gbar(D) + lamL ||Lambda + D||_1  (Eq. (6)), with the
      * quadratic model gbar(D) = tr(G D) + 1/2 tr(D Sigma D Sigma) + tr(D Sigma D Psi)
      * (Hessian Sigma (x) (Sigma + 2 Psi), Eq. (4)).  U = D Sigma is maintained. */
     double *U = zalloc((size_t)(q * q));
     memset(D, 0, sizeof(double) * (size_t)(q * q));
+    for (int pass = 0; pass < passes; ++pass)
     for (int64_t i = 0; i < q; ++i) {
         for (int64_t j = i; j < q; ++j) {
             if (!actL[IDX(i, j, q)]) continue;
@@ -401,8 +402,8 @@ static int64_t count_mask(size_t count, const uint8_t *m) {
 
 int orc_solve(int64_t n, int64_t p, int64_t q, const double *X, const double *Y,
               double lamL, double lamT, double tol, int max_iter, int stall_iters,
-              int warm, double *Lambda, double *Theta, int *iters, double *f_final,
-              orc_trace *trace) {
+              int lambda_passes, int warm, double *Lambda, double *Theta, int *iters,
+              double *f_final, orc_trace *trace) {
     size_t qq = (size_t)(q * q), pq = (size_t)(p * q);
     double *Sxx = zalloc((size_t)(p * p)), *Sxy = zalloc(pq), *Syy = zalloc(qq);
     double *L = zalloc(qq), *Sigma = zalloc(qq), *Psi = zalloc(qq), *M = zalloc(qq);
@@ -460,7 +461,7 @@ int orc_solve(int64_t n, int64_t p, int64_t q, const double *X, const double *Y,
             break;
         }
         /* Lambda step: Newton direction by one CD pass, then Armijo line search. */
-        orc_lambda_direction(q, Sigma, Psi, GL, Lambda, actL, lamL, D);
+        orc_lambda_direction(q, Sigma, Psi, GL, Lambda, actL, lamL, lambda_passes, D);
         double alpha = 0.0, fa = f;
         int trials = 0;
         orc_line_search(p, q, Sxx, Sxy, Syy, Lambda, Theta, D, GL, lamL, lamT, f, 0.5, 1e-3,

@@ -54,12 +54,13 @@ void orc_active_sets(int64_t p, int64_t q, const double *GL, const double *GT,
                      const double *Lambda, const double *Theta, double lamL,
                      double lamT, uint8_t *actL, uint8_t *actT);
 
-/* One coordinate-descent pass for the generalized Newton direction D of
- * Eq. (6) over S_Lambda in lexicographic (i, j) order, maintaining U = D Sigma.
- * D is written as a full symmetric q x q matrix. */
+/* Coordinate descent for the generalized Newton direction D of Eq. (6):
+ * `passes` passes over S_Lambda, each in lexicographic (i, j) order, from
+ * D = 0, maintaining U = D Sigma (Sec. 3 makes a single pass).  D is written
+ * as a full symmetric q x q matrix. */
 void orc_lambda_direction(int64_t q, const double *Sigma, const double *Psi,
                           const double *GL, const double *Lambda, const uint8_t *actL,
-                          double lamL, double *D);
+                          double lamL, int passes, double *D);
 
 /* Armijo line search on Lambda + alpha D (Algorithm 1): updates Lambda in
  * place with the accepted step and returns alpha (0 when D is not a descent
@@ -93,12 +94,13 @@ typedef struct {
  * stall_iters consecutive iterations (stall_iters > 0) f has not decreased by
  * more than its rounding error and that subgradient norm has not reached a new
  * minimum (the rounding floor), or after
- * max_iter iterations.  Returns ORC_OK / ORC_STALLED / ORC_MAXITER; *iters is
+ * max_iter iterations.  lambda_passes (>= 1) is the number of CD passes of
+ * the Lambda direction per iteration.  Returns ORC_OK / ORC_STALLED / ORC_MAXITER; *iters is
  * the number of completed iterations; trace may be NULL. */
 int orc_solve(int64_t n, int64_t p, int64_t q, const double *X, const double *Y,
               double lamL, double lamT, double tol, int max_iter, int stall_iters,
-              int warm, double *Lambda, double *Theta, int *iters, double *f_final,
-              orc_trace *trace);
+              int lambda_passes, int warm, double *Lambda, double *Theta, int *iters,
+              double *f_final, orc_trace *trace);
 
 #ifdef __cplusplus
 }

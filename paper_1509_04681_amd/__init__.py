@@ -53,7 +53,7 @@ class Options(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int), ("max_ls", ctypes.c_int),
                 ("ls_beta", ctypes.c_double), ("ls_sigma", ctypes.c_double),
                 ("stall_iters", ctypes.c_int), ("sweep", ctypes.c_int),
-                ("tile", ctypes.c_int), ("_pad", ctypes.c_int),
+                ("tile", ctypes.c_int), ("lambda_passes", ctypes.c_int),
                 ("workspace_budget", ctypes.c_size_t),
                 ("warm_Lambda", _vp), ("warm_Theta", _vp),
                 ("trace", ctypes.POINTER(TraceEntry)), ("trace_cap", ctypes.c_int),
@@ -162,7 +162,7 @@ class SolveResult:
 def cggm_solve(X, Y, lam_Lambda: float, lam_Theta: float, tol: float = 1e-2, *,
                max_iter: int = 500, max_ls: int = 30, ls_beta: float = 0.5,
                ls_sigma: float = 1e-3, stall_iters: int = 3, sweep: int = CGGM_SWEEP_TILED,
-               tile: int = 0, workspace_budget: int = 0, warm_Lambda=None, warm_Theta=None,
+               tile: int = 0, lambda_passes: int = 3, workspace_budget: int = 0, warm_Lambda=None, warm_Theta=None,
                trace_cap: int | None = None, keep_csr: bool = False, kernel_stats: bool = False,
                stream=None) -> SolveResult:
     """Alternating Newton CD (Algorithm 1) on device X (n x p) and Y (n x q), float64."""
@@ -174,6 +174,7 @@ def cggm_solve(X, Y, lam_Lambda: float, lam_Theta: float, tol: float = 1e-2, *,
     lib.cggm_default_options(ctypes.byref(opt))
     opt.max_iter, opt.max_ls, opt.ls_beta, opt.ls_sigma = max_iter, max_ls, ls_beta, ls_sigma
     opt.stall_iters, opt.sweep, opt.tile = stall_iters, sweep, tile
+    opt.lambda_passes = lambda_passes
     opt.workspace_budget = workspace_budget
     if warm_Lambda is not None:
         opt.warm_Lambda = _dev(warm_Lambda, "warm_Lambda").value

@@ -407,9 +407,11 @@ __global__ __launch_bounds__(BLOCK) void lambda_gs_kernel(
     for (int r = 0; r < R; ++r) {
         const int64_t i = rc.r0 + r;
         const bool colok = inC && (!diag || c >= r);
-        double lamv = 0.0, g = 0.0, b = 0.0, s_ij = 0.0, p_ij = 0.0, s_jj = 0.0, p_jj = 0.0;
+        double lamv = 0.0, d0 = 0.0, g = 0.0, b = 0.0, s_ij = 0.0, p_ij = 0.0, s_jj = 0.0,
+               p_jj = 0.0;
         if (inC) {
             lamv = Lam[i * q + rc.c0 + c];
+            d0 = D[i * q + rc.c0 + c];
             g = GL[i * q + rc.c0 + c];
             b = Bs[r][c];
             s_ij = sIJ[r][c];
@@ -430,8 +432,10 @@ __global__ __launch_bounds__(BLOCK) void lambda_gs_kernel(
         while (mask) {
             const int l = __ffsll((unsigned long long)mask) - 1;
             mask &= mask - 1;
-            // c = Lambda_ij + D_ij with D_ij = 0 until the coordinate is visited
-            const double cand = soft_threshold(lamv - b * ainv, thr) - lamv;
+            // c = Lambda_ij + D_ij with D_ij as left by earlier passes (zero on
+            // the first), unchanged until the coordinate is visited
+            const double cv = lamv + d0;
+            const double cand = soft_threshold(cv - b * ainv, thr) - cv;
             const double mu = readlane_f64(cand, l);
             if (mu != 0.0) {
                 const double mue = (diag && l == r) ? 0.5 * mu : mu;
@@ -444,9 +448,9 @@ __global__ __launch_bounds__(BLOCK) void lambda_gs_kernel(
                 any_change = 1;
             }
         }
-        if (colok) {
-            D[i * q + rc.c0 + c] = mu_mine;
-            D[(int64_t)(rc.c0 + c) * q + i] = mu_mine;
+        if (colok && mu_mine != 0.0) {
+            D[i * q + rc.c0 + c] = d0 + mu_mine;
+            D[(int64_t)(rc.c0 + c) * q + i] = d0 + mu_mine;
         }
         if (inC) {
             if (!diag) {

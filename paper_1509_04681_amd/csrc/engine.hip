@@ -390,12 +390,16 @@ void run_theta_sweep(Ctx &c, const Schedule &sch, KernelTimer *kt = nullptr) {
     }
 }
 
-void run_lambda_sweep(Ctx &c, const Schedule &sch, KernelTimer *kt = nullptr) {
+// One CD pass over S_Lambda for the Newton direction; D and U start at zero
+// on the first pass and carry over to further passes (pass > 0).
+void run_lambda_sweep(Ctx &c, const Schedule &sch, KernelTimer *kt = nullptr, int pass = 0) {
     Work &w = c.w;
-    fill(c.s, w.q * w.q, 0.0, w.D);
-    fill(c.s, w.q * w.q, 0.0, w.U);
-    lambda_activity(c.s, w.rects_lambda, (int)sch.rects.size(), w.q, w.GL, w.Lam, c.lamL,
-                    w.act_lambda);
+    if (pass == 0) {
+        fill(c.s, w.q * w.q, 0.0, w.D);
+        fill(c.s, w.q * w.q, 0.0, w.U);
+        lambda_activity(c.s, w.rects_lambda, (int)sch.rects.size(), w.q, w.GL, w.Lam, c.lamL,
+                        w.act_lambda);
+    }
     for (int k = 0; k < sch.waves(); ++k) {
         const int b = sch.wave_start[k], e = sch.wave_start[k + 1];
         WaveProbe pr;
@@ -482,6 +486,7 @@ int solve_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q
     if (opt_in) opt = *opt_in;
     if (opt.max_iter < 0 || opt.max_ls < 1 || !(opt.ls_beta > 0.0 && opt.ls_beta < 1.0) ||
         !(opt.ls_sigma > 0.0 && opt.ls_sigma < 1.0) || opt.stall_iters < 0 ||
+        opt.lambda_passes < 1 ||
         (opt.sweep != CGGM_SWEEP_TILED && opt.sweep != CGGM_SWEEP_SEQUENTIAL))
         fail(CGGM_EINVAL, "invalid options");
     const auto [tileL, tileT] = tile_edges(opt.tile);
@@ -660,7 +665,13 @@ int solve_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q
 
         // ---- Lambda: Newton direction by one CD pass, Armijo line search ----
         CGGM_HIP(hipEventRecord(ev[2], s));
-        run_lambda_sweep(c, la_sched, &kt_lambda);
+        for (int pass = 0; pass < opt.lambda_passes; ++pass) {
+            run_lambda_sweep(c, la_sched, &kt_lambda, pass);
+            if (pass + 1 < opt.lambda_passes) {
+                CGGM_HIP(hipStreamSynchronize(s));
+                kt_lambda.collect();
+            }
+        }
         reduce_direction(s, q, w.GL, w.Lam, w.D, w.partials, w.scal + S_DIR);
         double hd[2];
         CGGM_HIP(hipMemcpyAsync(hd, w.scal + S_DIR, sizeof(hd), hipMemcpyDeviceToHost, s));
@@ -669,7 +680,8 @@ int solve_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q
         double delta = hd[0] + lamL * hd[1];
         if (!(delta < 0.0) && !seq) {
             // Descent guard: redo the direction one tile per wave.
-            run_lambda_sweep(c, la_safe);
+            for (int pass = 0; pass < opt.lambda_passes; ++pass) run_lambda_sweep(c, la_safe,
+                                                                                  nullptr, pass);
             ++last_fallbacks;
             reduce_direction(s, q, w.GL, w.Lam, w.D, w.partials, w.scal + S_DIR);
             CGGM_HIP(hipMemcpyAsync(hd, w.scal + S_DIR, sizeof(hd), hipMemcpyDeviceToHost, s));
@@ -920,6 +932,7 @@ void cggm_default_options(cggm_options *opt) {
     opt->stall_iters = 3;
     opt->sweep = CGGM_SWEEP_TILED;
     opt->tile = 0;
+    opt->lambda_passes = 3;
 }
 
 size_t cggm_solve_workspace_bytes(int64_t n, int64_t p, int64_t q) {

@@ -69,6 +69,10 @@ def test_argument_errors_without_device(lib):
     opt.tile = 65
     assert lib.cggm_solve(fake, fake, 4, 3, 2, 0.1, 0.1, 0.01, ctypes.byref(opt),
                           ctypes.byref(r), None) == m.CGGM_EINVAL
+    lib.cggm_default_options(ctypes.byref(opt))
+    opt.lambda_passes = 0
+    assert lib.cggm_solve(fake, fake, 4, 3, 2, 0.1, 0.1, 0.01, ctypes.byref(opt),
+                          ctypes.byref(r), None) == m.CGGM_EINVAL
 
 
 def test_workspace_budget_is_checked_before_allocation(lib):
@@ -93,3 +97,4 @@ def test_default_options(lib):
     assert (opt.max_iter, opt.max_ls, opt.ls_beta, opt.ls_sigma, opt.stall_iters) == \
         (500, 30, 0.5, 1e-3, 3)
     assert opt.sweep == m.CGGM_SWEEP_TILED
+    assert opt.lambda_passes == 3

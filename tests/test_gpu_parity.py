@@ -107,15 +107,18 @@ def test_objective_rejects_non_pd(cg):
     assert ei.value.code == cg.CGGM_ENOTPD
 
 
-@pytest.mark.parametrize("p,q,n,seed", [(24, 20, 60, 0), (9, 33, 40, 1)])
-def test_sequential_order_reproduces_oracle_iterates(cg, orc, p, q, n, seed):
+@pytest.mark.parametrize("p,q,n,seed,passes", [(24, 20, 60, 0, 1), (9, 33, 40, 1, 1),
+                                               (24, 20, 60, 0, 3), (9, 33, 40, 1, 2)])
+def test_sequential_order_reproduces_oracle_iterates(cg, orc, p, q, n, seed, passes):
     """With one coordinate per wave in lexicographic order the GPU runs the
-    oracle's exact Gauss-Seidel sequence: every iterate agrees to rounding."""
+    oracle's exact Gauss-Seidel sequence (one or several passes of the Lambda
+    direction): every iterate agrees to rounding."""
     pr = synth.chain_problem(p=p, q=q, n=n, density=0.1, lam=0.08, seed=seed)
     k = 6
     g = cg.cggm_solve(dev(pr.X), dev(pr.Y), pr.lam_Lambda, pr.lam_Theta, tol=0.0, max_iter=k,
-                      stall_iters=0, sweep=cg.CGGM_SWEEP_SEQUENTIAL)
-    o = orc.solve(pr.X, pr.Y, pr.lam_Lambda, pr.lam_Theta, tol=0.0, max_iter=k)
+                      stall_iters=0, sweep=cg.CGGM_SWEEP_SEQUENTIAL, lambda_passes=passes)
+    o = orc.solve(pr.X, pr.Y, pr.lam_Lambda, pr.lam_Theta, tol=0.0, max_iter=k,
+                  lambda_passes=passes)
     fg = np.array([t["f"] for t in g.trace])
     np.testing.assert_allclose(fg, o.trace["f"], rtol=1e-11)
     np.testing.assert_array_equal([t["m_Lambda"] for t in g.trace], o.trace["mL"])
@@ -151,7 +154,7 @@ def kkt_violation(X, Y, Lam, Theta, lamL, lamT):
 
 def solve_both(cg, orc, X, Y, lamL, lamT, **kw):
     g = cg.cggm_solve(dev(X), dev(Y), lamL, lamT, tol=0.0, max_iter=5000, **kw)
-    o = orc.solve(X, Y, lamL, lamT, tol=0.0, max_iter=5000, stall_iters=3)
+    o = orc.solve(X, Y, lamL, lamT, tol=0.0, max_iter=5000, stall_iters=3, lambda_passes=3)
     return g, o
 
 

@@ -207,6 +207,40 @@ def test_lambda_cd_second_coordinate_sees_first(oracle_lib):
     assert D[i2, j2] == pytest.approx(mu, rel=1e-4, abs=1e-7)
 
 
+def test_lambda_cd_passes_solve_newton_subproblem(oracle_lib):
+    """Repeated passes converge to the minimiser of the l1-penalised quadratic
+    model of Eq. (6) over the active set.  Its optimality conditions are checked
+    with the model gradient b = G + H[D] built from central differences of the
+    gradient map (H[D] = d/de G(Lambda + e D)), not from the CD's own update
+    formulas: for active (i, j), b_ij = -lam sign(Lambda + D)_ij where
+    Lambda + D is nonzero and |b_ij| <= lam where it is zero."""
+    o = oracle_lib
+    rng = np.random.default_rng(25)
+    p, q = 4, 5
+    X, Y = random_problem(p, q, 30, seed=26)
+    S = o.stats(X, Y)
+    Lam, Theta = random_state(p, q, rng)
+    GL, _, Sig, Psi = o.gradient(S, Lam, Theta)
+    lam = 0.05
+    act = np.ones((q, q), bool)
+    act[0, 3] = act[3, 0] = False                   # one inactive pair stays at zero
+    D = o.lambda_direction(Sig, Psi, GL, Lam, act, lam, passes=4000)
+    assert D[0, 3] == 0.0 and D[3, 0] == 0.0
+    eps = 1e-6                                      # truncation error ~3e-9 here
+    Gp = o.gradient(S, Lam + eps * D, Theta)[0]
+    Gm = o.gradient(S, Lam - eps * D, Theta)[0]
+    b = GL + (Gp - Gm) / (2 * eps)
+    x = Lam + D
+    nz = act & (np.abs(x) > 1e-12)
+    zero = act & ~nz
+    assert nz.sum() > 0
+    np.testing.assert_allclose(b[nz], -lam * np.sign(x[nz]), rtol=0, atol=1e-7)
+    assert np.all(np.abs(b[zero]) <= lam + 1e-7)
+    # one pass is not yet at the solution on this instance (the pin is not vacuous)
+    D1 = o.lambda_direction(Sig, Psi, GL, Lam, act, lam, passes=1)
+    assert np.abs(D1 - D).max() > 1e-6
+
+
 def test_theta_cd_steps_are_exact_minimisers(oracle_lib):
     """g is quadratic in Theta; sequential steps on two coordinates of the same
     row and one of another row must each minimise f exactly along its axis."""
