@@ -15,13 +15,14 @@
 // of the same wave see each other's updates only through the next wave's
 // snapshot.
 //
-// A wave runs three kernels:
+// A wave runs four kernels:
 //   1. snapshot: the MFMA column-slab products of every tile, split over the
-//      K range into parts of about SNAP_ROWS rows, one wavefront per
-//      (tile, 32x32 quadrant, K part); partial tiles go to a scratch buffer;
-//   2. Gauss-Seidel: one workgroup per tile sums its partials in part order
-//      (deterministic), adds the gradient term and runs the exact in-tile CD;
-//   3. update of the maintained product's rows with the tile deltas.
+//      K range into parts, one wavefront per (tile, 64x32 block, K part);
+//      partial tiles go to a scratch buffer;
+//   2. the sum of each tile's partials in part order (deterministic);
+//   3. Gauss-Seidel: one workgroup per tile adds the gradient term to the
+//      summed snapshot and runs the exact in-tile CD;
+//   4. update of the maintained product's rows with the tile deltas.
 // Which tiles have active coordinates is decided once per sweep (the screen
 // uses the gradient and the parameters at the start of the sweep).
 #include <math.h>
@@ -35,8 +36,7 @@ namespace cggm {
 
 namespace {
 
-constexpr int T = LAMBDA_TILE;    // 32
-constexpr int LD = T + 1;
+constexpr int T = LAMBDA_TILE;    // 64
 constexpr int TT = THETA_TILE;    // 64
 constexpr int LDT = TT + 1;
 
@@ -74,96 +74,126 @@ struct SnapArgs {
     int64_t ldb[NPAIR];
 };
 
-// One wavefront per workgroup computes one 32 x 32 quadrant of one tile's
+// One wavefront per workgroup computes one WM x WN block of one tile's
 // snapshot over one part of the K range, loading its MFMA operands straight
 // from HBM (16 consecutive doubles per operand row, U k-steps in flight) and
 // writing the partial from its accumulators.  No LDS, so many wavefronts stay
 // resident per CU to cover the memory latency.
+//
+// Workgroups are dealt to the 8 XCDs round robin by block index, and each XCD
+// has its own L2.  The blocks of one (tile, part) read the same operand
+// column slabs, so their block indices are chosen congruent mod 8: later
+// readers of a slab hit the L2 of the first.
+constexpr int NXCD = 8;
+inline int64_t snapshot_blocks(int64_t groups, int blocks_per_group) {
+    return (groups + NXCD - 1) / NXCD * NXCD * blocks_per_group;
+}
+// Block of one wavefront: 64 x 32 (6 operand loads per 8 MFMAs per k-step),
+// U = 4 k-steps per batch; 136 VGPRs + 64 AGPRs, two waves per SIMD.
+constexpr int SNAP_WM = 64, SNAP_WN = 32, SNAP_U = 4;
+template <int TS>
+constexpr int snap_blocks_per_tile() {
+    return (TS / SNAP_WM) * (TS / SNAP_WN);
+}
 template <int TS, int NPAIR>
 __global__ __launch_bounds__(WAVE) void snapshot_kernel(const TileRect *__restrict__ rects,
                                                         const int *__restrict__ active, int S,
-                                                        int64_t K, SnapArgs<NPAIR> args,
+                                                        int nrect, int64_t K,
+                                                        SnapArgs<NPAIR> args,
                                                         double *__restrict__ partial) {
-    constexpr int NQD = TS / 32, NQ = NQD * NQD, U = 4;
+    constexpr int WM = SNAP_WM, WN = SNAP_WN, U = SNAP_U;
+    constexpr int NBN = TS / WN, NB = (TS / WM) * NBN, MI = WM / 16, NJ = WN / 16;
     const int64_t wg = blockIdx.x;
-    const int quad = (int)(wg % NQ);
-    const int64_t t = wg / NQ;
+    const int64_t rest = wg / NXCD;
+    const int blk = (int)(rest % NB);
+    const int64_t t = (rest / NB) * NXCD + wg % NXCD;   // (tile, part) group
+    if (t >= (int64_t)nrect * S) return;
     const int s = (int)(t % S);
     const int e = (int)(t / S);
     if (!active[e]) return;
     const TileRect rc = rects[e];
     const int R = rc.r1 - rc.r0, C = rc.c1 - rc.c0;
-    const int mo = (quad / NQD) * 32, no = (quad % NQD) * 32;
-    if (mo >= R || no >= C) return;                  // quadrant outside a ragged tile
+    const int mo = (blk / NBN) * WM, no = (blk % NBN) * WN;
+    if (mo >= R || no >= C) return;                  // block outside a ragged tile
     const int lane = threadIdx.x, col = lane & 15, krow = lane >> 4;
     const int64_t ksteps = (K + 3) / 4;
     const int64_t s0 = (ksteps * s) / S, s1 = (ksteps * (s + 1)) / S;
-    const bool am0 = mo + col < R, am1 = mo + col + 16 < R;
-    const bool bn0 = no + col < C, bn1 = no + col + 16 < C;
-    v4d acc[2][2];
+    bool am[MI], bn[NJ];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < MI; ++i) am[i] = mo + i * 16 + col < R;
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < NJ; ++j) bn[j] = no + j * 16 + col < C;
+    v4d acc[MI][NJ];
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int pp = 0; pp < NPAIR; ++pp) {
         const double *A = args.A[pp] + rc.r0 + mo;
         const double *B = args.B[pp] + rc.c0 + no;
         const int64_t lda = args.lda[pp], ldb = args.ldb[pp];
         for (int64_t st = s0; st < s1; st += U) {
-            double a[U][2], b[U][2];
+            double a[U][MI], b[U][NJ];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int64_t k = (st + u) * 4 + krow;
                 const bool kv = (st + u) < s1 && k < K;
-                a[u][0] = (kv && am0) ? A[k * lda + col] : 0.0;
-                a[u][1] = (kv && am1) ? A[k * lda + col + 16] : 0.0;
-                b[u][0] = (kv && bn0) ? B[k * ldb + col] : 0.0;
-                b[u][1] = (kv && bn1) ? B[k * ldb + col + 16] : 0.0;
+#pragma unroll
+                for (int i = 0; i < MI; ++i)
+                    a[u][i] = (kv && am[i]) ? A[k * lda + col + i * 16] : 0.0;
+#pragma unroll
+                for (int j = 0; j < NJ; ++j)
+                    b[u][j] = (kv && bn[j]) ? B[k * ldb + col + j * 16] : 0.0;
             }
 #pragma unroll
             for (int u = 0; u < U; ++u)
 #pragma unroll
-                for (int i = 0; i < 2; ++i)
+                for (int i = 0; i < MI; ++i)
 #pragma unroll
-                    for (int j = 0; j < 2; ++j)
+                    for (int j = 0; j < NJ; ++j)
                         acc[i][j] = mfma_f64_16x16x4(a[u][i], b[u][j], acc[i][j]);
         }
     }
     double *out = partial + ((int64_t)e * S + s) * TS * TS;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < NJ; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
                 out[(mo + i * 16 + krow + 4 * r) * TS + no + j * 16 + col] = acc[i][j][r];
 }
 
-// Sum of the S partials of tile e in part order, for m < R, n < C.
-template <int TS, int LDO>
-__device__ void sum_partials(const double *__restrict__ partial, int e, int S, int R, int C,
-                             double (*out)[LDO]) {
-    const double *base = partial + (int64_t)e * S * TS * TS;
-    for (int k = threadIdx.x; k < TS * TS; k += BLOCK) {
-        const int m = k / TS, n = k % TS;
-        double v = 0.0;
-        if (m < R && n < C) {
-            int s = 0;
-            for (; s + 4 <= S; s += 4) {      // four independent loads in flight
-                const double v0 = base[(int64_t)(s + 0) * TS * TS + k];
-                const double v1 = base[(int64_t)(s + 1) * TS * TS + k];
-                const double v2 = base[(int64_t)(s + 2) * TS * TS + k];
-                const double v3 = base[(int64_t)(s + 3) * TS * TS + k];
-                v += v0;
-                v += v1;
-                v += v2;
-                v += v3;
-            }
-            for (; s < S; ++s) v += base[(int64_t)s * TS * TS + k];
-        }
-        out[m][n] = v;
+// Sum of the S partial snapshots of every active tile, in part order
+// (deterministic), into part 0; one thread per tile entry, eight loads in
+// flight.  Entries outside a ragged tile are summed too and never read.
+template <int TS>
+__global__ __launch_bounds__(BLOCK) void snapshot_sum_kernel(const int *__restrict__ active,
+                                                             int S, double *__restrict__ partial) {
+    const int e = blockIdx.y;
+    if (!active[e]) return;
+    const int k = blockIdx.x * BLOCK + threadIdx.x;
+    double *base = partial + (int64_t)e * S * TS * TS + k;
+    double v = base[0];
+    int s = 1;
+    for (; s + 8 <= S; s += 8) {
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t[u] = base[(int64_t)(s + u) * TS * TS];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v += t[u];
     }
+    for (; s < S; ++s) v += base[(int64_t)s * TS * TS];
+    base[0] = v;
+}
+
+template <int TS>
+void sum_snapshots(hipStream_t st, const int *active, int nrect, int S, double *partial) {
+    static_assert((TS * TS) % BLOCK == 0, "whole blocks per tile");
+    if (S <= 1) return;
+    snapshot_sum_kernel<TS><<<dim3(TS * TS / BLOCK, nrect), BLOCK, 0, st>>>(active, S, partial);
+    CGGM_LAUNCH_CHECK();
 }
 
 // ------------------------------------------------------------------ Theta ---
@@ -189,11 +219,12 @@ __global__ __launch_bounds__(BLOCK) void theta_gs_kernel(
     __shared__ double Bs[TT][LDT];    // gradient snapshot, then corrected in place
     __shared__ double sxx[TT][LDT];   // Sxx[I, I]
     __shared__ double sig[TT][LDT];   // Sigma[J, J]
-    sum_partials<TT, LDT>(partial, e, S, R, C, Bs);
+    const double *snap = partial + (int64_t)e * S * TT * TT;   // summed into part 0
     for (int k = tid; k < TT * TT; k += BLOCK) {
         const int r = k / TT, c = k % TT;
-        if (r < R && c < C)
-            Bs[r][c] = 2.0 * Sxy[(int64_t)(rc.r0 + r) * q + rc.c0 + c] + 2.0 * Bs[r][c];
+        Bs[r][c] = (r < R && c < C)
+                       ? 2.0 * Sxy[(int64_t)(rc.r0 + r) * q + rc.c0 + c] + 2.0 * snap[k]
+                       : 0.0;
         sxx[r][c] = (r < R && c < R) ? Sxx[(int64_t)(rc.r0 + r) * p + rc.r0 + c] : 0.0;
         sig[r][c] = (r < C && c < C) ? Sigma[(int64_t)(rc.c0 + r) * q + rc.c0 + c] : 0.0;
     }
@@ -213,48 +244,70 @@ __global__ __launch_bounds__(BLOCK) void theta_gs_kernel(
     __syncthreads();
     if (wid != 0) return;
 
-    // Exact Gauss-Seidel by one wave: lane c owns column c of the tile.
+    // Exact Gauss-Seidel by one wave: lane c owns column c of the tile.  Theta
+    // and G of the next row are fetched while the current row is solved.
     const int c = lane;
     const bool colok = c < C;
+    const double sjj = colok ? sig[c][c] : 1.0;
     int any_change = 0;
     double *dTe = dT + (int64_t)e * TT * TT;
-    for (int r = 0; r < R; ++r) {
-        const int64_t i = rc.r0 + r;
-        double th = 0.0, g = 0.0, b = 0.0, sjj = 1.0;
+    double th_n = 0.0, g_n = 0.0;
+    auto fetch_row = [&](int r) {
         if (colok) {
-            th = Theta[i * q + rc.c0 + c];
-            g = GT[i * q + rc.c0 + c];
-            b = Bs[r][c];
-            sjj = sig[c][c];
+            const int64_t ro = (int64_t)(rc.r0 + r) * q + rc.c0 + c;
+            th_n = Theta[ro];
+            g_n = GT[ro];
         }
+    };
+    fetch_row(0);
+    for (int r = 0; r < R; ++r) {
+        double th = th_n;
+        const double g = g_n;
+        if (r + 1 < R) fetch_row(r + 1);
+        const int64_t i = rc.r0 + r;
+        double b = Bs[r][c];
         const double sii = sxx[r][r];
-        const double a = 2.0 * sii * sjj;
+        const double a = 2.0 * sii * sjj, two_sii = 2.0 * sii;
         const bool act = colok && a > 0.0 && (fabs(g) > lamT || th != 0.0);
         uint64_t mask = __ballot(act);
         const double ainv = act ? 1.0 / a : 0.0;
         const double thr = lamT * ainv;
+        const double th0 = th;
         double w = 0.0, mu_mine = 0.0;
-        while (mask) {
-            const int l = __ffsll((unsigned long long)mask) - 1;
-            mask &= mask - 1;
-            const double cand = soft_threshold(th - b * ainv, thr) - th;
-            const double mu = readlane_f64(cand, l);
-            if (mu != 0.0) {
-                const double s_l = colok ? sig[l][c] : 0.0;
-                b += 2.0 * sii * s_l * mu;           // same-row coupling Sxx_ii Sigma_lc
+        if (mask) {
+            int l = __ffsll((unsigned long long)mask) - 1;
+            double s_l = sig[l][c];
+            for (;;) {
+                mask &= mask - 1;
+                const int ln = mask ? __ffsll((unsigned long long)mask) - 1 : l;
+                const double s_n = sig[ln][c];
+                const double cand = soft_threshold(th0 - b * ainv, thr) - th0;
+                const double mu = readlane_f64(cand, l);
+                b += two_sii * s_l * mu;             // same-row coupling Sxx_ii Sigma_lc
                 w += s_l * mu;
-                if (c == l) {
-                    mu_mine = mu;
-                    th += mu;
-                }
-                any_change = 1;
+                if (c == l) mu_mine = mu;
+                if (!mask) break;
+                l = ln;
+                s_l = s_n;
             }
         }
+        if (__ballot(mu_mine != 0.0)) any_change = 1;
+        th = th0 + mu_mine;
         if (colok) {
-            Theta[i * q + rc.c0 + c] = th;
+            if (mu_mine != 0.0) Theta[i * q + rc.c0 + c] = th;
             dTe[r * TT + c] = mu_mine;
-            // later rows: b[r2][c] += 2 Sxx[r2][r] sum_l mu_l Sigma[l][c]
-            for (int r2 = r + 1; r2 < R; ++r2) Bs[r2][c] += 2.0 * sxx[r2][r] * w;
+        }
+        // later rows: b[r2][c] += 2 Sxx[r2][r] sum_l mu_l Sigma[l][c]
+        // (lanes outside the tile add zeros: their sig entries are zero)
+        const double w2 = 2.0 * w;
+        for (int r2 = r + 1; r2 < R; r2 += 4) {
+            double bv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (r2 + u < R) bv[u] = Bs[r2 + u][c];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (r2 + u < R) Bs[r2 + u][c] = bv[u] + sxx[r2 + u][r] * w2;
         }
     }
     if (lane == 0) changed[e] = any_change;
@@ -352,12 +405,23 @@ __global__ __launch_bounds__(BLOCK, 4) void theta_v_update_kernel(
 // coordinate (i', j') by
 //   mu_e [SP_i'i S_lj' + SP_i'l S_ij' + P_ij' S_i'l + P_lj' S_ii']
 // for a move at (i, l), with mu_e = mu (l != i) or mu / 2 (l == i).
+// A 64 x 64 block of doubles in LDS with an XOR swizzle: element (r, c) sits
+// at r * 64 + (c ^ r), so a row (fixed r, lane c) and a column (fixed c, lane r)
+// of the block both touch 64 distinct slots.
+struct Swz64 {
+    double *p;
+    __device__ __forceinline__ double &operator()(int r, int c) const {
+        return p[r * 64 + (c ^ r)];
+    }
+};
+
 __global__ __launch_bounds__(BLOCK) void lambda_gs_kernel(
     const TileRect *__restrict__ rects, const int *__restrict__ active, int S,
     const double *__restrict__ partial, int64_t q, const double *__restrict__ Sigma,
     const double *__restrict__ Psi, const double *__restrict__ GL,
     const double *__restrict__ Lam, double lamL, double *__restrict__ D,
     double *__restrict__ dD, int *__restrict__ changed, unsigned long long *__restrict__ ctr) {
+    static_assert(T == 64, "the Lambda tile is one wavefront wide");
     const int e = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
     if (!active[e]) {
@@ -367,19 +431,21 @@ __global__ __launch_bounds__(BLOCK) void lambda_gs_kernel(
     const TileRect rc = rects[e];
     const int R = rc.r1 - rc.r0, C = rc.c1 - rc.c0;
     const bool diag = rc.r0 == rc.c0;
-    __shared__ double Bs[T][LD];
-    __shared__ double sII[T][LD], pII[T][LD], sJJ[T][LD], pJJ[T][LD], sIJ[T][LD], pIJ[T][LD];
-    sum_partials<T, LD>(partial, e, S, R, C, Bs);
+    // b snapshot, and the Sigma / Psi blocks (I, J) and (J, J); the rows of
+    // the (I, I) blocks are read per row from global memory (Sigma and Psi are
+    // symmetric, so row r of a block also serves as its column r).
+    __shared__ double lds[5 * T * T];
+    const Swz64 Bs{lds}, sIJ{lds + T * T}, pIJ{lds + 2 * T * T}, sJJ{lds + 3 * T * T},
+        pJJ{lds + 4 * T * T};
+    const double *snap = partial + (int64_t)e * S * T * T;    // summed into part 0
     for (int k = tid; k < T * T; k += BLOCK) {
         const int r = k / T, c = k % T;
-        const bool ii = r < R && c < R, jj = r < C && c < C, ij = r < R && c < C;
-        if (ij) Bs[r][c] += GL[(int64_t)(rc.r0 + r) * q + rc.c0 + c];
-        sII[r][c] = ii ? Sigma[(int64_t)(rc.r0 + r) * q + rc.r0 + c] : 0.0;
-        pII[r][c] = ii ? Psi[(int64_t)(rc.r0 + r) * q + rc.r0 + c] : 0.0;
-        sJJ[r][c] = jj ? Sigma[(int64_t)(rc.c0 + r) * q + rc.c0 + c] : 0.0;
-        pJJ[r][c] = jj ? Psi[(int64_t)(rc.c0 + r) * q + rc.c0 + c] : 0.0;
-        sIJ[r][c] = ij ? Sigma[(int64_t)(rc.r0 + r) * q + rc.c0 + c] : 0.0;
-        pIJ[r][c] = ij ? Psi[(int64_t)(rc.r0 + r) * q + rc.c0 + c] : 0.0;
+        const bool ij = r < R && c < C, jj = r < C && c < C;
+        Bs(r, c) = ij ? snap[k] + GL[(int64_t)(rc.r0 + r) * q + rc.c0 + c] : 0.0;
+        sIJ(r, c) = ij ? Sigma[(int64_t)(rc.r0 + r) * q + rc.c0 + c] : 0.0;
+        pIJ(r, c) = ij ? Psi[(int64_t)(rc.r0 + r) * q + rc.c0 + c] : 0.0;
+        sJJ(r, c) = jj ? Sigma[(int64_t)(rc.c0 + r) * q + rc.c0 + c] : 0.0;
+        pJJ(r, c) = jj ? Psi[(int64_t)(rc.c0 + r) * q + rc.c0 + c] : 0.0;
     }
     if (ctr && tid == 0) {
         const int64_t RC = (int64_t)R * C;
@@ -402,24 +468,38 @@ __global__ __launch_bounds__(BLOCK) void lambda_gs_kernel(
 
     const int c = lane;
     const bool inC = c < C;
+    const double s_jj = sJJ(c, c), p_jj = pJJ(c, c);   // zero outside the tile
     int any_change = 0;
     double *dDe = dD + (int64_t)e * T * T;
+    // Per-row global operands, fetched one row ahead: lane r2 holds
+    // Sigma_II[r][r2] and Psi_II[r][r2]; lane c holds Lambda, D and G at (r, c).
+    // (The prefetch of D's next row precedes this row's writes: the only
+    // writes into later rows of the tile are the mirror entries of a diagonal
+    // tile, below the diagonal, which the coordinate loop never reads.)
+    const bool inR = lane < R;
+    double srow_n = 0.0, prow_n = 0.0, lam_n = 0.0, d_n = 0.0, g_n = 0.0;
+    auto fetch_row = [&](int r) {
+        const int64_t ro = (int64_t)(rc.r0 + r) * q;
+        if (inR) {
+            srow_n = Sigma[ro + rc.r0 + lane];
+            prow_n = Psi[ro + rc.r0 + lane];
+        }
+        if (inC) {
+            lam_n = Lam[ro + rc.c0 + c];
+            d_n = D[ro + rc.c0 + c];
+            g_n = GL[ro + rc.c0 + c];
+        }
+    };
+    fetch_row(0);
     for (int r = 0; r < R; ++r) {
+        const double srow = srow_n, prow = prow_n, lamv = lam_n, d0 = d_n, g = g_n;
+        if (r + 1 < R) fetch_row(r + 1);
         const int64_t i = rc.r0 + r;
         const bool colok = inC && (!diag || c >= r);
-        double lamv = 0.0, d0 = 0.0, g = 0.0, b = 0.0, s_ij = 0.0, p_ij = 0.0, s_jj = 0.0,
-               p_jj = 0.0;
-        if (inC) {
-            lamv = Lam[i * q + rc.c0 + c];
-            d0 = D[i * q + rc.c0 + c];
-            g = GL[i * q + rc.c0 + c];
-            b = Bs[r][c];
-            s_ij = sIJ[r][c];
-            p_ij = pIJ[r][c];
-            s_jj = sJJ[c][c];
-            p_jj = pJJ[c][c];
-        }
-        const double sii = sII[r][r], pii = pII[r][r], spii = sii + pii;
+        const double s_ij = sIJ(r, c), p_ij = pIJ(r, c);
+        double b = Bs(r, c);
+        const double sii = readlane_f64(srow, r), pii = readlane_f64(prow, r);
+        const double spii = sii + pii;
         const bool self = diag && c == r;
         const double a = self ? sii * sii + 2.0 * sii * pii
                               : s_ij * s_ij + sii * s_jj + sii * p_jj + s_jj * pii +
@@ -428,24 +508,32 @@ __global__ __launch_bounds__(BLOCK) void lambda_gs_kernel(
         uint64_t mask = __ballot(act);
         const double ainv = act ? 1.0 / a : 0.0;
         const double thr = lamL * ainv;
+        // c = Lambda_ij + D_ij with D_ij as left by earlier passes (zero on the
+        // first), unchanged until the coordinate is visited
+        const double cv = lamv + d0;
         double w1 = 0.0, w4 = 0.0, mu_mine = 0.0;
-        while (mask) {
-            const int l = __ffsll((unsigned long long)mask) - 1;
-            mask &= mask - 1;
-            // c = Lambda_ij + D_ij with D_ij as left by earlier passes (zero on
-            // the first), unchanged until the coordinate is visited
-            const double cv = lamv + d0;
-            const double cand = soft_threshold(cv - b * ainv, thr) - cv;
-            const double mu = readlane_f64(cand, l);
-            if (mu != 0.0) {
-                const double mue = (diag && l == r) ? 0.5 * mu : mu;
+        if (mask) {
+            // Active coordinates of the row in lane order; the (J, J) rows of
+            // the next coordinate are read while the current one is solved.
+            int l = __ffsll((unsigned long long)mask) - 1;
+            double sJl = sJJ(l, c), pJl = pJJ(l, c);
+            for (;;) {
+                mask &= mask - 1;
+                const int ln = mask ? __ffsll((unsigned long long)mask) - 1 : l;
+                const double sJn = sJJ(ln, c), pJn = pJJ(ln, c);
                 const double s_il = readlane_f64(s_ij, l), p_il = readlane_f64(p_ij, l);
-                const double sJl = sJJ[l][c], pJl = pJJ[l][c];
-                b += mue * (spii * sJl + (s_il + p_il) * s_ij + p_ij * s_il + pJl * sii);
+                const double x = spii * sJl + (s_il + p_il) * s_ij + p_ij * s_il + pJl * sii;
+                const double cand = soft_threshold(cv - b * ainv, thr) - cv;
+                const double mu = readlane_f64(cand, l);
+                const double mue = (diag && l == r) ? 0.5 * mu : mu;
+                b += mue * x;
                 w1 += mue * sJl;
                 w4 += mue * pJl;
                 if (c == l) mu_mine = mu;
-                any_change = 1;
+                if (!mask) break;
+                l = ln;
+                sJl = sJn;
+                pJl = pJn;
             }
         }
         if (colok && mu_mine != 0.0) {
@@ -461,28 +549,53 @@ __global__ __launch_bounds__(BLOCK) void lambda_gs_kernel(
             }
         }
         // Corrections of the later rows r2 of the tile:
-        //   b[r2][c] += SP[r2][r] w1_c + S[r][c] w2_r2 + P[r][c] w3_r2 + S[r][r2] w4_c
-        //   w2_r2 = sum_l SP[r2][l] mu_e,l,   w3_r2 = sum_l S[r2][l] mu_e,l.
+        //   b[r2][c] += SP_II[r2][r] w1_c + S_IJ[r][c] w2_r2 + P_IJ[r][c] w3_r2
+        //               + S_II[r][r2] w4_c,
+        //   w2_r2 = sum_l SP_IJ[r2][l] mu_e,l,   w3_r2 = sum_l S_IJ[r2][l] mu_e,l.
         const double mue_mine = (diag && c == r) ? 0.5 * mu_mine : mu_mine;
         uint64_t moved = __ballot(mu_mine != 0.0);
         if (moved == 0) continue;
+        any_change = 1;
         double w2 = 0.0, w3 = 0.0;            // lane r2 accumulates row r2's values
-        const int r2l = lane;
-        while (moved) {
-            const int l = __ffsll((unsigned long long)moved) - 1;
-            moved &= moved - 1;
-            const double m = readlane_f64(mue_mine, l);
-            if (r2l < R) {
-                const double sv = sIJ[r2l][l];
-                w2 += (sv + pIJ[r2l][l]) * m;
+        if (__popcll(moved) >= 16) {
+            // dense row: all 64 columns, four partial sums, loads in flight
+            double a2[4] = {0.0, 0.0, 0.0, 0.0}, a3[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int l0 = 0; l0 < T; l0 += 4) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const double m = readlane_f64(mue_mine, l0 + u);
+                    const double sv = sIJ(lane, l0 + u);
+                    a2[u] += (sv + pIJ(lane, l0 + u)) * m;
+                    a3[u] += sv * m;
+                }
+            }
+            w2 = (a2[0] + a2[1]) + (a2[2] + a2[3]);
+            w3 = (a3[0] + a3[1]) + (a3[2] + a3[3]);
+        } else {
+            while (moved) {
+                const int l = __ffsll((unsigned long long)moved) - 1;
+                moved &= moved - 1;
+                const double m = readlane_f64(mue_mine, l);
+                const double sv = sIJ(lane, l);
+                w2 += (sv + pIJ(lane, l)) * m;
                 w3 += sv * m;
             }
         }
-        for (int r2 = r + 1; r2 < R; ++r2) {
-            const double w2r = readlane_f64(w2, r2), w3r = readlane_f64(w3, r2);
-            if (inC)
-                Bs[r2][c] += (sII[r2][r] + pII[r2][r]) * w1 + s_ij * w2r + p_ij * w3r +
-                             sII[r][r2] * w4;
+        // (lanes outside the tile add zeros: their LDS entries are zero)
+        for (int r2 = r + 1; r2 < R; r2 += 4) {
+            double bv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (r2 + u < R) bv[u] = Bs(r2 + u, c);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (r2 + u < R) {
+                    const int rr = r2 + u;
+                    const double w2r = readlane_f64(w2, rr), w3r = readlane_f64(w3, rr);
+                    const double s_r2 = readlane_f64(srow, rr), p_r2 = readlane_f64(prow, rr);
+                    Bs(rr, c) = bv[u] + ((s_r2 + p_r2) * w1 + s_ij * w2r + p_ij * w3r + s_r2 * w4);
+                }
+            }
         }
     }
     if (lane == 0) changed[e] = any_change;
@@ -546,12 +659,14 @@ void theta_wave(hipStream_t s, const TileRect *rects_dev, const int *active, int
                 double *V, const double *GT, double *Theta, double lamT, double *dT,
                 int *changed, const CdScratch &scr, const WaveProbe *probe) {
     if (nrect <= 0) return;
-    const int S = snapshot_parts(nrect, 4, p);
+    constexpr int NB = snap_blocks_per_tile<TT>();
+    const int S = snapshot_parts(nrect, NB, p);
     SnapArgs<1> args{{Sxx}, {p}, {V}, {q}};
     record(s, probe, 0);
-    snapshot_kernel<TT, 1><<<(unsigned)((int64_t)nrect * S * 4), WAVE, 0, s>>>(
-        rects_dev, active, S, p, args, scr.partial);
+    snapshot_kernel<TT, 1><<<(unsigned)snapshot_blocks((int64_t)nrect * S, NB), WAVE, 0, s>>>(
+        rects_dev, active, S, nrect, p, args, scr.partial);
     CGGM_LAUNCH_CHECK();
+    sum_snapshots<TT>(s, active, nrect, S, scr.partial);
     record(s, probe, 1);
     theta_gs_kernel<<<nrect, BLOCK, 0, s>>>(rects_dev, active, S, scr.partial, p, q, Sxx, Sxy,
                                             Sigma, GT, Theta, lamT, dT, changed,
@@ -570,14 +685,16 @@ void lambda_wave(hipStream_t s, const TileRect *rects_dev, const int *active, in
                  const double *GL, const double *Lam, double lamL, double *D, double *U,
                  double *dD, int *changed, const CdScratch &scr, const WaveProbe *probe) {
     if (nrect <= 0) return;
-    const int S = snapshot_parts(nrect, 1, q);
+    constexpr int NB = snap_blocks_per_tile<T>();
+    const int S = snapshot_parts(nrect, NB, q);
     // b snapshot: G + (SP U)[I, J] + ((Psi U)[J, I])^T
     //   = G + SP[:, I]^T U[:, J] + U[:, I]^T Psi[:, J]   (SP, Psi symmetric)
     SnapArgs<2> args{{SP, U}, {q, q}, {U, Psi}, {q, q}};
     record(s, probe, 0);
-    snapshot_kernel<T, 2><<<(unsigned)((int64_t)nrect * S), WAVE, 0, s>>>(rects_dev, active, S, q,
-                                                                          args, scr.partial);
+    snapshot_kernel<T, 2><<<(unsigned)snapshot_blocks((int64_t)nrect * S, NB), WAVE, 0, s>>>(
+        rects_dev, active, S, nrect, q, args, scr.partial);
     CGGM_LAUNCH_CHECK();
+    sum_snapshots<T>(s, active, nrect, S, scr.partial);
     record(s, probe, 1);
     lambda_gs_kernel<<<nrect, BLOCK, 0, s>>>(rects_dev, active, S, scr.partial, q, Sigma, Psi, GL,
                                              Lam, lamL, D, dD, changed,

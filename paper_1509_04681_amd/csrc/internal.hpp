@@ -128,7 +128,7 @@ struct TileRect {
     int32_t r0, r1, c0, c1;   // rows [r0, r1), columns [c0, c1)
 };
 
-constexpr int LAMBDA_TILE = 32;   // tile edge of the Lambda CD tiles
+constexpr int LAMBDA_TILE = 64;   // tile edge of the Lambda CD tiles
 constexpr int THETA_TILE = 64;    // tile edge of the Theta CD tiles
 
 // Optional instrumentation of a wave: events recorded before the snapshot,
