@@ -58,6 +58,7 @@ def main():
     ap.add_argument("--chunk", type=int, default=25)
     ap.add_argument("--max-iter", type=int, default=20000)
     ap.add_argument("--state-dir", default=None)
+    ap.add_argument("--lambda-passes", type=int, default=1)
     args = ap.parse_args()
     pr = synth.workload(args.workload, seed=args.seed)
     state = args.state_dir
@@ -72,7 +73,8 @@ def main():
     t0 = time.time()
     while True:
         r = oracle.solve(pr.X, pr.Y, pr.lam_Lambda, pr.lam_Theta, tol=0.0,
-                         max_iter=args.chunk, stall_iters=3, Lambda0=Lam, Theta0=Th)
+                         max_iter=args.chunk, stall_iters=3, Lambda0=Lam, Theta0=Th,
+                         lambda_passes=args.lambda_passes)
         Lam, Th = r.Lambda, r.Theta
         done += r.iters
         fs.extend(float(v) for v in r.trace["f"][: r.iters])
@@ -101,8 +103,8 @@ def main():
         "borderline_Lambda": pack_mask((np.abs(Lam) >= 1e-7) & (np.abs(Lam) <= 1e-5)),
         "borderline_Theta": pack_mask((np.abs(Th) >= 1e-7) & (np.abs(Th) <= 1e-5)),
         "f_trace_head": fs[:50],
-        "generator": "synth.workload(%r, seed=%r) -> oracle.solve(tol=0, stall_iters=3)"
-                     % (args.workload, args.seed),
+        "generator": "synth.workload(%r, seed=%r) -> oracle.solve(tol=0, stall_iters=3, "
+                     "lambda_passes=%d)" % (args.workload, args.seed, args.lambda_passes),
     }
     with open(os.path.join(HERE, f"{args.workload}.json"), "w") as fh:
         json.dump(out, fh, indent=1)
