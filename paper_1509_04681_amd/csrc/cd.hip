@@ -28,6 +28,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "device_common.hpp"
 #include "internal.hpp"
@@ -38,6 +39,10 @@ namespace {
 
 constexpr int T = LAMBDA_TILE;    // 64
 constexpr int TT = THETA_TILE;    // 64
+// Rows with at least this many active coordinates take the unrolled
+// register-operand scan in the Gauss-Seidel kernels; sparser rows iterate over
+// their active lanes only.
+constexpr int GS_DENSE_ROW = 16;
 constexpr int LDT = TT + 1;
 
 // ----------------------------------------------------------------- activity --
@@ -249,6 +254,9 @@ __global__ __launch_bounds__(BLOCK) void theta_gs_kernel(
     const int c = lane;
     const bool colok = c < C;
     const double sjj = colok ? sig[c][c] : 1.0;
+    double sigc[TT];                 // lane c keeps column c of Sigma[J, J]
+#pragma unroll
+    for (int l = 0; l < TT; ++l) sigc[l] = sig[l][c];
     int any_change = 0;
     double *dTe = dT + (int64_t)e * TT * TT;
     double th_n = 0.0, g_n = 0.0;
@@ -261,40 +269,49 @@ __global__ __launch_bounds__(BLOCK) void theta_gs_kernel(
     };
     fetch_row(0);
     for (int r = 0; r < R; ++r) {
-        double th = th_n;
+        const double th0 = th_n;
         const double g = g_n;
         if (r + 1 < R) fetch_row(r + 1);
         const int64_t i = rc.r0 + r;
         double b = Bs[r][c];
         const double sii = sxx[r][r];
         const double a = 2.0 * sii * sjj, two_sii = 2.0 * sii;
-        const bool act = colok && a > 0.0 && (fabs(g) > lamT || th != 0.0);
-        uint64_t mask = __ballot(act);
+        const bool act = colok && a > 0.0 && (fabs(g) > lamT || th0 != 0.0);
+        const uint64_t mask = __ballot(act);
         const double ainv = act ? 1.0 / a : 0.0;
         const double thr = lamT * ainv;
-        const double th0 = th;
-        double w = 0.0, mu_mine = 0.0;
-        if (mask) {
-            int l = __ffsll((unsigned long long)mask) - 1;
-            double s_l = sig[l][c];
-            for (;;) {
-                mask &= mask - 1;
-                const int ln = mask ? __ffsll((unsigned long long)mask) - 1 : l;
-                const double s_n = sig[ln][c];
-                const double cand = soft_threshold(th0 - b * ainv, thr) - th0;
-                const double mu = readlane_f64(cand, l);
-                b += two_sii * s_l * mu;             // same-row coupling Sxx_ii Sigma_lc
-                w += s_l * mu;
-                if (c == l) mu_mine = mu;
-                if (!mask) break;
-                l = ln;
-                s_l = s_n;
+        double w = 0.0, mu_mine = 0.0, th_new = th0;
+        // Coordinate l (lane order): new value s = S_thr(Theta - b / a) from
+        // lane l; every lane moves b by 2 Sxx_ii Sigma_lc (s - Theta_l).  The
+        // chain from one coordinate's b to the next is b -> t -> clamp -> s ->
+        // broadcast -> b.
+        auto step = [&](int l, double sig_l) {
+            const double x = two_sii * sig_l;
+            const double th_l = readlane_f64(th0, l);
+            const double t = th0 - b * ainv;
+            const double st = t - fmax(fmin(t, thr), -thr);     // S_thr(t), exact zeros
+            const double s_l = readlane_f64(st, l);
+            const double mu = s_l - th_l;
+            b = fma(s_l, x, fma(-th_l, x, b));
+            w += sig_l * mu;
+            if (c == l) {
+                mu_mine = mu;
+                th_new = s_l;
+            }
+        };
+        if (__popcll(mask) >= GS_DENSE_ROW) {
+#pragma unroll
+            for (int l = 0; l < TT; ++l)
+                if ((mask >> l) & 1ull) step(l, sigc[l]);
+        } else {
+            for (uint64_t m = mask; m; m &= m - 1) {
+                const int l = __ffsll((unsigned long long)m) - 1;
+                step(l, sig[l][c]);
             }
         }
         if (__ballot(mu_mine != 0.0)) any_change = 1;
-        th = th0 + mu_mine;
         if (colok) {
-            if (mu_mine != 0.0) Theta[i * q + rc.c0 + c] = th;
+            if (mu_mine != 0.0) Theta[i * q + rc.c0 + c] = th_new;
             dTe[r * TT + c] = mu_mine;
         }
         // later rows: b[r2][c] += 2 Sxx[r2][r] sum_l mu_l Sigma[l][c]
@@ -374,7 +391,75 @@ __device__ void rowblock_update(const double *__restrict__ Delta, bool trans, in
     }
 }
 
-constexpr int UPD_CHUNKS = 4;   // 64-column chunks per update workgroup
+#if CGGM_UPD_PIPE
+// Variant: the next chunk's Out values and S operands are fetched into
+// registers while the current chunk is multiplied.
+template <int TR, int TK>
+__device__ void rowblock_update_pipe(const double *__restrict__ Delta, bool trans, int R, int Kd,
+                                     const double *__restrict__ S, int64_t lds,
+                                     double *__restrict__ Out, int64_t ldo, int64_t c_begin,
+                                     int64_t c_end, double (*dl)[TR + 2]) {
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
+    for (int e = tid; e < TK * TR; e += BLOCK) {
+        const int k = e / TR, m = e % TR;
+        dl[k][m] = (m < R && k < Kd) ? (trans ? Delta[k * TK + m] : Delta[m * TK + k]) : 0.0;
+    }
+    __syncthreads();
+    constexpr int KST = TK / 4, NI = TR / 16;
+    const int col = lane & 15, krow = lane >> 4;
+    double on[NI * 4], sn[KST];
+    auto fetch = [&](int64_t c0) {
+        const int64_t n = c0 + wid * 16 + col;
+        const bool nv = n < c_end;
+#pragma unroll
+        for (int i = 0; i < NI; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = i * 16 + krow + 4 * r;
+                on[i * 4 + r] = (nv && m < R) ? Out[(int64_t)m * ldo + n] : 0.0;
+            }
+#pragma unroll
+        for (int ks = 0; ks < KST; ++ks) {
+            const int k = ks * 4 + krow;
+            sn[ks] = (nv && k < Kd) ? S[(int64_t)k * lds + n] : 0.0;
+        }
+    };
+    if (c_begin < c_end) fetch(c_begin);
+#pragma unroll 1
+    for (int64_t c0 = c_begin; c0 < c_end; c0 += 64) {
+        v4d acc[NI];
+        double sv[KST];
+#pragma unroll
+        for (int i = 0; i < NI; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[i][r] = on[i * 4 + r];
+#pragma unroll
+        for (int ks = 0; ks < KST; ++ks) sv[ks] = sn[ks];
+        if (c0 + 64 < c_end) fetch(c0 + 64);
+#pragma unroll
+        for (int ks = 0; ks < KST; ++ks)
+#pragma unroll
+            for (int i = 0; i < NI; ++i)
+                acc[i] = mfma_f64_16x16x4(dl[ks * 4 + krow][i * 16 + col], sv[ks], acc[i]);
+        const int64_t n = c0 + wid * 16 + col;
+        if (n < c_end) {
+#pragma unroll
+            for (int i = 0; i < NI; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int m = i * 16 + krow + 4 * r;
+                    if (m < R) Out[(int64_t)m * ldo + n] = acc[i][r];
+                }
+        }
+    }
+}
+#define rowblock_update rowblock_update_pipe
+#endif
+
+#ifndef CGGM_UPD_CHUNKS
+#define CGGM_UPD_CHUNKS 4
+#endif
+constexpr int UPD_CHUNKS = CGGM_UPD_CHUNKS;   // 64-column chunks per update workgroup
 
 // V[I, :] += dTheta[I, J] Sigma[J, :] for every changed tile of the wave.
 __global__ __launch_bounds__(BLOCK, 4) void theta_v_update_kernel(
@@ -469,6 +554,14 @@ __global__ __launch_bounds__(BLOCK) void lambda_gs_kernel(
     const int c = lane;
     const bool inC = c < C;
     const double s_jj = sJJ(c, c), p_jj = pJJ(c, c);   // zero outside the tile
+    // lane c keeps column c of the (J, J) blocks in registers for the whole
+    // tile (one wavefront per SIMD here, so the register file allows it)
+    double sJc[T], pJc[T];
+#pragma unroll
+    for (int l = 0; l < T; ++l) {
+        sJc[l] = sJJ(l, c);
+        pJc[l] = pJJ(l, c);
+    }
     int any_change = 0;
     double *dDe = dD + (int64_t)e * T * T;
     // Per-row global operands, fetched one row ahead: lane r2 holds
@@ -505,40 +598,71 @@ __global__ __launch_bounds__(BLOCK) void lambda_gs_kernel(
                               : s_ij * s_ij + sii * s_jj + sii * p_jj + s_jj * pii +
                                     2.0 * s_ij * p_ij;
         const bool act = colok && a > 0.0 && (fabs(g) > lamL || lamv != 0.0);
-        uint64_t mask = __ballot(act);
+        const uint64_t mask = __ballot(act);
         const double ainv = act ? 1.0 / a : 0.0;
         const double thr = lamL * ainv;
         // c = Lambda_ij + D_ij with D_ij as left by earlier passes (zero on the
         // first), unchanged until the coordinate is visited
         const double cv = lamv + d0;
-        double w1 = 0.0, w4 = 0.0, mu_mine = 0.0;
-        if (mask) {
-            // Active coordinates of the row in lane order; the (J, J) rows of
-            // the next coordinate are read while the current one is solved.
-            int l = __ffsll((unsigned long long)mask) - 1;
-            double sJl = sJJ(l, c), pJl = pJJ(l, c);
-            for (;;) {
-                mask &= mask - 1;
-                const int ln = mask ? __ffsll((unsigned long long)mask) - 1 : l;
-                const double sJn = sJJ(ln, c), pJn = pJJ(ln, c);
-                const double s_il = readlane_f64(s_ij, l), p_il = readlane_f64(p_ij, l);
-                const double x = spii * sJl + (s_il + p_il) * s_ij + p_ij * s_il + pJl * sii;
-                const double cand = soft_threshold(cv - b * ainv, thr) - cv;
-                const double mu = readlane_f64(cand, l);
-                const double mue = (diag && l == r) ? 0.5 * mu : mu;
+        double w1 = 0.0, w4 = 0.0, mu_mine = 0.0, s_mine = 0.0;
+        // Coordinate l of the row (lane order): its new value is
+        // s = S_thr(cv - b / a), broadcast from lane l; every lane then moves
+        // b by mu_e x_l with mu = s - cv_l.  The chain from one coordinate's b
+        // to the next is b -> t -> clamp -> s -> broadcast -> b; the coupling
+        // x_l and the cv_l term do not depend on b.  A diagonal tile halves
+        // the move of its self coordinate (l == r).
+        // One coordinate step; the (J, J) column entries come from registers
+        // (dense rows, unrolled scan) or from LDS (sparse rows).
+        auto step = [&](int l, double sJl, double pJl, auto diag_tile) {
+            constexpr bool DIAG = decltype(diag_tile)::value;
+            const double s_il = readlane_f64(s_ij, l), p_il = readlane_f64(p_ij, l);
+            const double cv_l = readlane_f64(cv, l);
+            const double x = spii * sJl + (s_il + p_il) * s_ij + p_ij * s_il + pJl * sii;
+            const double t = cv - b * ainv;
+            const double st = t - fmax(fmin(t, thr), -thr);     // S_thr(t), exact zeros
+            const double s_l = readlane_f64(st, l);
+            const double mu = s_l - cv_l;
+            double mue = mu;
+            if (DIAG && l == r) {
+                mue = 0.5 * mu;
                 b += mue * x;
-                w1 += mue * sJl;
-                w4 += mue * pJl;
-                if (c == l) mu_mine = mu;
-                if (!mask) break;
-                l = ln;
-                sJl = sJn;
-                pJl = pJn;
+            } else {
+                b = fma(s_l, x, fma(-cv_l, x, b));
             }
+            w1 += mue * sJl;
+            w4 += mue * pJl;
+            if (c == l) {
+                mu_mine = mu;
+                s_mine = s_l;
+            }
+        };
+        auto row_dense = [&](auto diag_tile) {
+#pragma unroll
+            for (int l = 0; l < T; ++l)
+                if ((mask >> l) & 1ull) step(l, sJc[l], pJc[l], diag_tile);
+        };
+        auto row_sparse = [&](auto diag_tile) {
+            for (uint64_t m = mask; m; m &= m - 1) {
+                const int l = __ffsll((unsigned long long)m) - 1;
+                step(l, sJJ(l, c), pJJ(l, c), diag_tile);
+            }
+        };
+        if (__popcll(mask) >= GS_DENSE_ROW) {
+            if (diag)
+                row_dense(std::integral_constant<bool, true>{});
+            else
+                row_dense(std::integral_constant<bool, false>{});
+        } else if (mask) {
+            if (diag)
+                row_sparse(std::integral_constant<bool, true>{});
+            else
+                row_sparse(std::integral_constant<bool, false>{});
         }
         if (colok && mu_mine != 0.0) {
-            D[i * q + rc.c0 + c] = d0 + mu_mine;
-            D[(int64_t)(rc.c0 + c) * q + i] = d0 + mu_mine;
+            // new D = S - Lambda, so a thresholded coordinate gives exactly
+            // Lambda + D = 0
+            D[i * q + rc.c0 + c] = s_mine - lamv;
+            D[(int64_t)(rc.c0 + c) * q + i] = s_mine - lamv;
         }
         if (inC) {
             if (!diag) {

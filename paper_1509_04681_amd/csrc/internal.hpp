@@ -34,11 +34,13 @@ enum { UPLO_FULL = 0, UPLO_LOWER = 1 };
 enum { KRANGE_FULL = 0, KRANGE_FROM_ROW = 1 };
 
 // C = alpha op(A) op(B) + beta C, all row-major FP64, op(X) = X or X^T.
-// uplo = UPLO_LOWER computes only the 64x64 output tiles on or below the
-// diagonal (entries above the diagonal inside those tiles are written too).
-// krange = KRANGE_FROM_ROW starts the inner sum of output tile row-block I at
-// k = I * 64 (for products whose A operand is zero above that row, as in
-// L^{-T} L^{-1}).
+// Output tiles are 128 x 128 when M, N and K are all >= 256, else 64 x 64.
+// uplo = UPLO_LOWER computes only the output tiles on or below the diagonal
+// (entries above the diagonal inside those tiles are written too).
+// krange = KRANGE_FROM_ROW starts the inner sum of an output tile at k = its
+// first row (for products whose A operand is zero above that row, as in
+// L^{-T} L^{-1}).  C may alias A or B only when every output tile reads
+// exactly the operand rows / columns it writes (one K chunk per tile row).
 void gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
           const double *A, int64_t lda, const double *B, int64_t ldb, double beta, double *C,
           int64_t ldc, int uplo = UPLO_FULL, int krange = KRANGE_FULL);

@@ -12,15 +12,130 @@ namespace cggm {
 
 namespace {
 
-constexpr int GEMM_TS = 64;
-
 // --------------------------------------------------------------- GEMM -------
+// C = alpha op(A) op(B) + beta C with 128 x 128 output tiles per workgroup:
+// each of the 4 waves owns a 64 x 64 quarter as 4 x 4 MFMA 16x16 blocks
+// (64 accumulator doubles per lane), so every operand value read from LDS
+// feeds four MFMAs.  The K range is staged through LDS in chunks of 16 with
+// two buffers: the next chunk's global loads are in flight while the current
+// chunk is multiplied, and one barrier per chunk separates the phases.
+constexpr int GT = 128;             // output tile edge
+constexpr int GKC = 16;             // K chunk
+constexpr int GPAD = 8;             // LDS row padding (doubles)
+constexpr int GPER = GT * GKC / BLOCK;   // operand elements per thread per chunk (8)
+
+struct GemmSmem {
+    double a[2][GKC][GT + GPAD];    // a[buf][k][m] = op(A)[m0 + m][kc + k]
+    double b[2][GKC][GT + GPAD];    // b[buf][k][n] = op(B)[kc + k][n0 + n]
+};
+
 template <bool TA, bool TB>
 __global__ __launch_bounds__(BLOCK) void gemm_kernel(int64_t M, int64_t N, int64_t K,
                                                      double alpha, const double *A, int64_t lda,
                                                      const double *B, int64_t ldb, double beta,
                                                      double *C, int64_t ldc, int uplo,
                                                      int krange) {
+    const int64_t bm = blockIdx.y, bn = blockIdx.x;
+    if (uplo == UPLO_LOWER && bn > bm) return;
+    __shared__ GemmSmem sm;
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
+    const int64_t m0 = bm * GT, n0 = bn * GT;
+    const int64_t k0 = (krange == KRANGE_FROM_ROW) ? std::min<int64_t>(m0, K) : 0;
+    const int64_t k1 = K;
+    // Element e = tid + BLOCK * r of a chunk: coordinates chosen so that
+    // consecutive threads read consecutive addresses of the stored operand.
+    auto a_coord = [&](int e, int &k, int &m) {
+        if (TA) { k = e / GT; m = e % GT; }
+        else { m = e / GKC; k = e % GKC; }
+    };
+    auto b_coord = [&](int e, int &k, int &n) {
+        if (TB) { n = e / GKC; k = e % GKC; }
+        else { k = e / GT; n = e % GT; }
+    };
+    double ra[GPER], rb[GPER];
+    auto load = [&](int64_t kc) {
+#pragma unroll
+        for (int r = 0; r < GPER; ++r) {
+            const int e = tid + BLOCK * r;
+            int k, m, n;
+            a_coord(e, k, m);
+            const int64_t gk = kc + k, gm = m0 + m;
+            ra[r] = (gk < k1 && gm < M) ? (TA ? A[gk * lda + gm] : A[gm * lda + gk]) : 0.0;
+            b_coord(e, k, n);
+            const int64_t gk2 = kc + k, gn = n0 + n;
+            rb[r] = (gk2 < k1 && gn < N) ? (TB ? B[gn * ldb + gk2] : B[gk2 * ldb + gn]) : 0.0;
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int r = 0; r < GPER; ++r) {
+            const int e = tid + BLOCK * r;
+            int k, m, n;
+            a_coord(e, k, m);
+            sm.a[buf][k][m] = ra[r];
+            b_coord(e, k, n);
+            sm.b[buf][k][n] = rb[r];
+        }
+    };
+    v4d acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    const int wm = (wid >> 1) * 64, wn = (wid & 1) * 64;
+    const int col = lane & 15, krow = lane >> 4;
+    int buf = 0;
+    if (k0 < k1) {
+        load(k0);
+        store(0);
+    }
+    __syncthreads();
+    for (int64_t kc = k0; kc < k1; kc += GKC) {
+        const bool next = kc + GKC < k1;
+        if (next) load(kc + GKC);
+#pragma unroll
+        for (int ks = 0; ks < GKC / 4; ++ks) {
+            const int k = ks * 4 + krow;
+            double av[4], bv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) av[i] = sm.a[buf][k][wm + i * 16 + col];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bv[j] = sm.b[buf][k][wn + j * 16 + col];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = mfma_f64_16x16x4(av[i], bv[j], acc[i][j]);
+        }
+        if (next) store(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = m0 + wm + i * 16 + krow + 4 * r;
+                const int64_t cc = n0 + wn + j * 16 + col;
+                if (row < M && cc < N) {
+                    double *c = C + row * ldc + cc;
+                    const double v = alpha * acc[i][j][r];
+                    *c = (beta == 0.0) ? v : v + beta * (*c);
+                }
+            }
+}
+
+constexpr int GEMM_TS = 64;
+
+// 64 x 64 output tiles (4 waves x 32 x 32), single LDS buffer: used for the
+// thin products of the blocked factorizations (K or an output side of 64).
+template <bool TA, bool TB>
+__global__ __launch_bounds__(BLOCK) void gemm64_kernel(int64_t M, int64_t N, int64_t K,
+                                                       double alpha, const double *A,
+                                                       int64_t lda, const double *B, int64_t ldb,
+                                                       double beta, double *C, int64_t ldc,
+                                                       int uplo, int krange) {
     const int64_t bm = blockIdx.y, bn = blockIdx.x;
     if (uplo == UPLO_LOWER && bn > bm) return;
     __shared__ TileSmem<GEMM_TS> sm;
@@ -48,64 +163,63 @@ __global__ __launch_bounds__(BLOCK) void gemm_kernel(int64_t M, int64_t N, int64
 
 // ------------------------------------------------------------ Cholesky ------
 
-// W = L^{-1} of the nb x nb lower-triangular block in d (LDS), column c by
-// thread c (forward substitution on e_c), written to Wk (PB x PB, zero above
-// the diagonal and outside nb).
-__device__ void invert_lower_block(const double (*d)[PB + 1], double (*w)[PB + 1], int nb,
-                                   double *Wk) {
-    const int c = threadIdx.x;
-    if (c < nb) {
-        for (int i = c; i < nb; ++i) {
-            double s = (i == c) ? 1.0 : 0.0;
-            for (int m = c; m < i; ++m) s -= d[i][m] * w[m][c];
-            w[i][c] = s / d[i][i];
-        }
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < PB * PB; e += blockDim.x) {
-        const int i = e / PB, j = e % PB;
-        Wk[e] = (i < nb && j <= i) ? w[i][j] : 0.0;
-    }
-}
-
 // Factor the diagonal block A[kb:kb+nb, kb:kb+nb] = L_kk L_kk^T in LDS (one
-// workgroup), store L_kk in place and L_kk^{-1} in Wk (PB x PB); *notpd = 1 if
-// a pivot is not positive.
+// wavefront), store L_kk in place and L_kk^{-1} in Wk (PB x PB, zero above the
+// diagonal and outside nb); *notpd = 1 if a pivot is not positive.
+//   Factor: left-looking, column j at a time, lane i computes
+//     L_ij = (A_ij - sum_{k<j} L_ik L_jk) / L_jj   (L_jj from lane j);
+//   inverse: forward substitution by rows, lane c computes
+//     W_ic = (delta_ic - sum_{m<i} L_im W_mc) / L_ii.
+// Every step is one dot product per lane (two partial sums); the LDS rows are
+// padded so a column read across lanes is conflict-free.
 __global__ __launch_bounds__(WAVE) void potrf_diag_kernel(double *A, int64_t q, int64_t kb,
                                                           int nb, int *notpd, double *Wk) {
     __shared__ double d[PB][PB + 1];
     __shared__ double w[PB][PB + 1];
-    __shared__ int bad;
-    const int tid = threadIdx.x;
-    for (int e = tid; e < nb * nb; e += blockDim.x) {
-        const int i = e / nb, j = e % nb;
-        if (j <= i) d[i][j] = A[(kb + i) * q + kb + j];
-    }
-    if (tid == 0) bad = 0;
+    const int lane = threadIdx.x;
+#pragma unroll 8
+    for (int i = 0; i < PB; ++i)
+        d[i][lane] = (i < nb && lane <= i) ? A[(kb + i) * q + kb + lane] : 0.0;
     __syncthreads();
+    bool bad = false;
+    const bool row_ok = lane < nb;
     for (int j = 0; j < nb; ++j) {
-        if (tid == 0) {
-            const double v = d[j][j];
-            if (!(v > 0.0) || !isfinite(v)) bad = 1;
-            d[j][j] = (v > 0.0 && isfinite(v)) ? sqrt(v) : 1.0;
+        double a0 = 0.0, a1 = 0.0;
+        int k = 0;
+        for (; k + 1 < j; k += 2) {
+            a0 += d[lane][k] * d[j][k];
+            a1 += d[lane][k + 1] * d[j][k + 1];
         }
-        __syncthreads();
-        const double djj = d[j][j];
-        for (int i = j + 1 + tid; i < nb; i += blockDim.x) d[i][j] /= djj;
-        __syncthreads();
-        const int w = nb - j - 1;
-        for (int e = tid; e < w * w; e += blockDim.x) {
-            const int i = j + 1 + e / w, c = j + 1 + e % w;
-            if (c <= i) d[i][c] -= d[i][j] * d[c][j];
-        }
+        if (k < j) a0 += d[lane][k] * d[j][k];
+        const double sv = (row_ok && lane >= j) ? d[lane][j] - (a0 + a1) : 0.0;
+        const double pivot = readlane_f64(sv, j);
+        const bool good = pivot > 0.0 && isfinite(pivot);
+        bad |= !good;
+        const double ljj = good ? sqrt(pivot) : 1.0;
+        if (lane == j)
+            d[j][j] = ljj;
+        else if (row_ok && lane > j)
+            d[lane][j] = sv / ljj;
         __syncthreads();
     }
-    for (int e = tid; e < nb * nb; e += blockDim.x) {
-        const int i = e / nb, j = e % nb;
-        if (j <= i) A[(kb + i) * q + kb + j] = d[i][j];
+    for (int i = 0; i < nb; ++i) {
+        double a0 = 0.0, a1 = 0.0;
+        int m = 0;
+        for (; m + 1 < i; m += 2) {
+            a0 += d[i][m] * w[m][lane];
+            a1 += d[i][m + 1] * w[m + 1][lane];
+        }
+        if (m < i) a0 += d[i][m] * w[m][lane];
+        const double v = ((lane == i) ? 1.0 : 0.0) - (a0 + a1);
+        w[i][lane] = (lane <= i) ? v / d[i][i] : 0.0;
+        __syncthreads();
     }
-    if (tid == 0 && bad) *notpd = 1;
-    invert_lower_block(d, w, nb, Wk);
+#pragma unroll 8
+    for (int i = 0; i < PB; ++i) {
+        if (i < nb && lane <= i) A[(kb + i) * q + kb + lane] = d[i][lane];
+        Wk[i * PB + lane] = (i < nb && lane <= i && lane < nb) ? w[i][lane] : 0.0;
+    }
+    if (lane == 0 && bad) *notpd = 1;
 }
 
 // ---------------------------------------------------------- elementwise -----
@@ -289,19 +403,31 @@ void gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, doub
           const double *A, int64_t lda, const double *B, int64_t ldb, double beta, double *C,
           int64_t ldc, int uplo, int krange) {
     if (M <= 0 || N <= 0) return;
-    dim3 grid((unsigned)((N + GEMM_TS - 1) / GEMM_TS), (unsigned)((M + GEMM_TS - 1) / GEMM_TS));
-    if (ta && tb)
-        gemm_kernel<true, true><<<grid, BLOCK, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C,
-                                                       ldc, uplo, krange);
-    else if (ta)
-        gemm_kernel<true, false><<<grid, BLOCK, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C,
-                                                        ldc, uplo, krange);
-    else if (tb)
-        gemm_kernel<false, true><<<grid, BLOCK, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C,
-                                                        ldc, uplo, krange);
+    // Large products take the 128 x 128 tiles; the thin ones of the blocked
+    // factorizations (K = 64, or 64 output rows / columns) keep 64 x 64 tiles.
+    const bool big = M >= 2 * GT && N >= 2 * GT && K >= 2 * GT;
+    const int64_t ts = big ? GT : GEMM_TS;
+    dim3 grid((unsigned)((N + ts - 1) / ts), (unsigned)((M + ts - 1) / ts));
+#define CGGM_GEMM_LAUNCH(KER)                                                                   \
+    do {                                                                                        \
+        if (ta && tb)                                                                           \
+            KER<true, true><<<grid, BLOCK, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, \
+                                                   uplo, krange);                               \
+        else if (ta)                                                                            \
+            KER<true, false><<<grid, BLOCK, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C,     \
+                                                    ldc, uplo, krange);                         \
+        else if (tb)                                                                            \
+            KER<false, true><<<grid, BLOCK, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C,     \
+                                                    ldc, uplo, krange);                         \
+        else                                                                                    \
+            KER<false, false><<<grid, BLOCK, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C,    \
+                                                     ldc, uplo, krange);                        \
+    } while (0)
+    if (big)
+        CGGM_GEMM_LAUNCH(gemm_kernel);
     else
-        gemm_kernel<false, false><<<grid, BLOCK, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta,
-                                                         C, ldc, uplo, krange);
+        CGGM_GEMM_LAUNCH(gemm64_kernel);
+#undef CGGM_GEMM_LAUNCH
     CGGM_LAUNCH_CHECK();
 }
 
