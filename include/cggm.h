@@ -100,7 +100,7 @@ typedef struct {
     int sweep;             /* CGGM_SWEEP_TILED or CGGM_SWEEP_SEQUENTIAL        */
     int tile;              /* CD tile edge for CGGM_SWEEP_TILED (0 = default)  */
     int lambda_passes;     /* CD passes of the Lambda direction over S_Lambda
-                              per iteration (Sec. 3 makes one; default 3)     */
+                              per iteration (Sec. 3 makes one; default 4)     */
     size_t workspace_budget;   /* bytes of device workspace allowed (0 = any)  */
     const double *warm_Lambda; /* device q x q start (NULL = identity)         */
     const double *warm_Theta;  /* device p x q start (NULL = zero)             */

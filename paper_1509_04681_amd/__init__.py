@@ -162,8 +162,9 @@ class SolveResult:
 def cggm_solve(X, Y, lam_Lambda: float, lam_Theta: float, tol: float = 1e-2, *,
                max_iter: int = 500, max_ls: int = 30, ls_beta: float = 0.5,
                ls_sigma: float = 1e-3, stall_iters: int = 3, sweep: int = CGGM_SWEEP_TILED,
-               tile: int = 0, lambda_passes: int = 3, workspace_budget: int = 0, warm_Lambda=None, warm_Theta=None,
-               trace_cap: int | None = None, keep_csr: bool = False, kernel_stats: bool = False,
+               tile: int = 0, lambda_passes: int = 4, workspace_budget: int = 0,
+               warm_Lambda=None, warm_Theta=None, trace_cap: int | None = None,
+               keep_csr: bool = False, kernel_stats: bool = False,
                stream=None) -> SolveResult:
     """Alternating Newton CD (Algorithm 1) on device X (n x p) and Y (n x q), float64."""
     import torch

@@ -391,78 +391,12 @@ __device__ void rowblock_update(const double *__restrict__ Delta, bool trans, in
     }
 }
 
-#if CGGM_UPD_PIPE
-// Variant: the next chunk's Out values and S operands are fetched into
-// registers while the current chunk is multiplied.
-template <int TR, int TK>
-__device__ void rowblock_update_pipe(const double *__restrict__ Delta, bool trans, int R, int Kd,
-                                     const double *__restrict__ S, int64_t lds,
-                                     double *__restrict__ Out, int64_t ldo, int64_t c_begin,
-                                     int64_t c_end, double (*dl)[TR + 2]) {
-    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
-    for (int e = tid; e < TK * TR; e += BLOCK) {
-        const int k = e / TR, m = e % TR;
-        dl[k][m] = (m < R && k < Kd) ? (trans ? Delta[k * TK + m] : Delta[m * TK + k]) : 0.0;
-    }
-    __syncthreads();
-    constexpr int KST = TK / 4, NI = TR / 16;
-    const int col = lane & 15, krow = lane >> 4;
-    double on[NI * 4], sn[KST];
-    auto fetch = [&](int64_t c0) {
-        const int64_t n = c0 + wid * 16 + col;
-        const bool nv = n < c_end;
-#pragma unroll
-        for (int i = 0; i < NI; ++i)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int m = i * 16 + krow + 4 * r;
-                on[i * 4 + r] = (nv && m < R) ? Out[(int64_t)m * ldo + n] : 0.0;
-            }
-#pragma unroll
-        for (int ks = 0; ks < KST; ++ks) {
-            const int k = ks * 4 + krow;
-            sn[ks] = (nv && k < Kd) ? S[(int64_t)k * lds + n] : 0.0;
-        }
-    };
-    if (c_begin < c_end) fetch(c_begin);
-#pragma unroll 1
-    for (int64_t c0 = c_begin; c0 < c_end; c0 += 64) {
-        v4d acc[NI];
-        double sv[KST];
-#pragma unroll
-        for (int i = 0; i < NI; ++i)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) acc[i][r] = on[i * 4 + r];
-#pragma unroll
-        for (int ks = 0; ks < KST; ++ks) sv[ks] = sn[ks];
-        if (c0 + 64 < c_end) fetch(c0 + 64);
-#pragma unroll
-        for (int ks = 0; ks < KST; ++ks)
-#pragma unroll
-            for (int i = 0; i < NI; ++i)
-                acc[i] = mfma_f64_16x16x4(dl[ks * 4 + krow][i * 16 + col], sv[ks], acc[i]);
-        const int64_t n = c0 + wid * 16 + col;
-        if (n < c_end) {
-#pragma unroll
-            for (int i = 0; i < NI; ++i)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int m = i * 16 + krow + 4 * r;
-                    if (m < R) Out[(int64_t)m * ldo + n] = acc[i][r];
-                }
-        }
-    }
-}
-#define rowblock_update rowblock_update_pipe
-#endif
 
-#ifndef CGGM_UPD_CHUNKS
-#define CGGM_UPD_CHUNKS 4
-#endif
-constexpr int UPD_CHUNKS = CGGM_UPD_CHUNKS;   // 64-column chunks per update workgroup
+constexpr int UPD_CHUNKS = 4;   // 64-column chunks per update workgroup
+constexpr int UPD_MINB = 4;     // workgroups per CU the update kernels are built for
 
 // V[I, :] += dTheta[I, J] Sigma[J, :] for every changed tile of the wave.
-__global__ __launch_bounds__(BLOCK, 4) void theta_v_update_kernel(
+__global__ __launch_bounds__(BLOCK, UPD_MINB) void theta_v_update_kernel(
     const TileRect *__restrict__ rects, int64_t q, const double *__restrict__ Sigma,
     const double *__restrict__ dT, const int *__restrict__ changed, double *__restrict__ V) {
     const int e = blockIdx.y;
@@ -604,7 +538,7 @@ __global__ __launch_bounds__(BLOCK) void lambda_gs_kernel(
         // c = Lambda_ij + D_ij with D_ij as left by earlier passes (zero on the
         // first), unchanged until the coordinate is visited
         const double cv = lamv + d0;
-        double w1 = 0.0, w4 = 0.0, mu_mine = 0.0, s_mine = 0.0;
+        double w1 = 0.0, w4 = 0.0, mu_mine = 0.0, s_mine;
         // Coordinate l of the row (lane order): its new value is
         // s = S_thr(cv - b / a), broadcast from lane l; every lane then moves
         // b by mu_e x_l with mu = s - cv_l.  The chain from one coordinate's b
@@ -613,13 +547,16 @@ __global__ __launch_bounds__(BLOCK) void lambda_gs_kernel(
         // the move of its self coordinate (l == r).
         // One coordinate step; the (J, J) column entries come from registers
         // (dense rows, unrolled scan) or from LDS (sparse rows).
+        const double sp_ij = s_ij + p_ij;
+        const double thr_hi = __builtin_canonicalize(thr), thr_lo = __builtin_canonicalize(-thr);
         auto step = [&](int l, double sJl, double pJl, auto diag_tile) {
             constexpr bool DIAG = decltype(diag_tile)::value;
             const double s_il = readlane_f64(s_ij, l), p_il = readlane_f64(p_ij, l);
             const double cv_l = readlane_f64(cv, l);
-            const double x = spii * sJl + (s_il + p_il) * s_ij + p_ij * s_il + pJl * sii;
+            // x = SP_ii S_lc + SP_il S_ic + P_ic S_il + P_lc S_ii
+            const double x = fma(spii, sJl, fma(sii, pJl, fma(s_il, sp_ij, p_il * s_ij)));
             const double t = cv - b * ainv;
-            const double st = t - fmax(fmin(t, thr), -thr);     // S_thr(t), exact zeros
+            const double st = t - fmax(fmin(t, thr_hi), thr_lo);   // S_thr(t), exact zeros
             const double s_l = readlane_f64(st, l);
             const double mu = s_l - cv_l;
             double mue = mu;
@@ -631,10 +568,7 @@ __global__ __launch_bounds__(BLOCK) void lambda_gs_kernel(
             }
             w1 += mue * sJl;
             w4 += mue * pJl;
-            if (c == l) {
-                mu_mine = mu;
-                s_mine = s_l;
-            }
+            s_mine = (c == l) ? st : s_mine;
         };
         auto row_dense = [&](auto diag_tile) {
 #pragma unroll
@@ -647,6 +581,7 @@ __global__ __launch_bounds__(BLOCK) void lambda_gs_kernel(
                 step(l, sJJ(l, c), pJJ(l, c), diag_tile);
             }
         };
+        s_mine = cv;                         // unvisited lanes keep their value
         if (__popcll(mask) >= GS_DENSE_ROW) {
             if (diag)
                 row_dense(std::integral_constant<bool, true>{});
@@ -658,6 +593,7 @@ __global__ __launch_bounds__(BLOCK) void lambda_gs_kernel(
             else
                 row_sparse(std::integral_constant<bool, false>{});
         }
+        mu_mine = ((mask >> c) & 1ull) ? s_mine - cv : 0.0;
         if (colok && mu_mine != 0.0) {
             // new D = S - Lambda, so a thresholded coordinate gives exactly
             // Lambda + D = 0
@@ -727,7 +663,7 @@ __global__ __launch_bounds__(BLOCK) void lambda_gs_kernel(
 
 // U[I, :] += dD Sigma[J, :] and U[J, :] += dD^T Sigma[I, :] (off-diagonal
 // tiles), or U[I, :] += dD_sym Sigma[I, :] (diagonal tiles).
-__global__ __launch_bounds__(BLOCK, 4) void lambda_u_update_kernel(
+__global__ __launch_bounds__(BLOCK, UPD_MINB) void lambda_u_update_kernel(
     const TileRect *__restrict__ rects, int64_t q, const double *__restrict__ Sigma,
     const double *__restrict__ dD, const int *__restrict__ changed, double *__restrict__ U) {
     const int e = blockIdx.y, half = blockIdx.z;

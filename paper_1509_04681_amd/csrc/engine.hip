@@ -932,7 +932,7 @@ void cggm_default_options(cggm_options *opt) {
     opt->stall_iters = 3;
     opt->sweep = CGGM_SWEEP_TILED;
     opt->tile = 0;
-    opt->lambda_passes = 3;
+    opt->lambda_passes = 4;
 }
 
 size_t cggm_solve_workspace_bytes(int64_t n, int64_t p, int64_t q) {

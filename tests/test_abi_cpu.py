@@ -97,4 +97,4 @@ def test_default_options(lib):
     assert (opt.max_iter, opt.max_ls, opt.ls_beta, opt.ls_sigma, opt.stall_iters) == \
         (500, 30, 0.5, 1e-3, 3)
     assert opt.sweep == m.CGGM_SWEEP_TILED
-    assert opt.lambda_passes == 3
+    assert opt.lambda_passes == 4
