@@ -740,31 +740,54 @@ void theta_wave(hipStream_t s, const TileRect *rects_dev, const int *active, int
     record(s, probe, 3);
 }
 
-void lambda_wave(hipStream_t s, const TileRect *rects_dev, const int *active, int nrect,
-                 int64_t q, const double *Sigma, const double *Psi, const double *SP,
-                 const double *GL, const double *Lam, double lamL, double *D, double *U,
-                 double *dD, int *changed, const CdScratch &scr, const WaveProbe *probe) {
-    if (nrect <= 0) return;
+int lambda_snapshot(hipStream_t s, const TileRect *rects_dev, const int *active, int nrect,
+                    int64_t q, const double *SP, const double *U, const double *Psi,
+                    const CdScratch &scr) {
+    if (nrect <= 0) return 0;
     constexpr int NB = snap_blocks_per_tile<T>();
     const int S = snapshot_parts(nrect, NB, q);
     // b snapshot: G + (SP U)[I, J] + ((Psi U)[J, I])^T
     //   = G + SP[:, I]^T U[:, J] + U[:, I]^T Psi[:, J]   (SP, Psi symmetric)
     SnapArgs<2> args{{SP, U}, {q, q}, {U, Psi}, {q, q}};
-    record(s, probe, 0);
     snapshot_kernel<T, 2><<<(unsigned)snapshot_blocks((int64_t)nrect * S, NB), WAVE, 0, s>>>(
         rects_dev, active, S, nrect, q, args, scr.partial);
     CGGM_LAUNCH_CHECK();
     sum_snapshots<T>(s, active, nrect, S, scr.partial);
-    record(s, probe, 1);
+    return S;
+}
+
+void lambda_gauss_seidel(hipStream_t s, const TileRect *rects_dev, const int *active, int nrect,
+                         int S, int64_t q, const double *Sigma, const double *Psi,
+                         const double *GL, const double *Lam, double lamL, double *D,
+                         double *dD, int *changed, const CdScratch &scr,
+                         unsigned long long *counters) {
+    if (nrect <= 0) return;
     lambda_gs_kernel<<<nrect, BLOCK, 0, s>>>(rects_dev, active, S, scr.partial, q, Sigma, Psi, GL,
-                                             Lam, lamL, D, dD, changed,
-                                             probe ? probe->counters : nullptr);
+                                             Lam, lamL, D, dD, changed, counters);
     CGGM_LAUNCH_CHECK();
-    record(s, probe, 2);
+}
+
+void lambda_update(hipStream_t s, const TileRect *rects_dev, int nrect, int64_t q,
+                   const double *Sigma, const double *dD, const int *changed, double *U) {
+    if (nrect <= 0) return;
     const int64_t cols_per_wg = 64 * UPD_CHUNKS;
     dim3 grid((unsigned)((q + cols_per_wg - 1) / cols_per_wg), (unsigned)nrect, 2);
     lambda_u_update_kernel<<<grid, BLOCK, 0, s>>>(rects_dev, q, Sigma, dD, changed, U);
     CGGM_LAUNCH_CHECK();
+}
+
+void lambda_wave(hipStream_t s, const TileRect *rects_dev, const int *active, int nrect,
+                 int64_t q, const double *Sigma, const double *Psi, const double *SP,
+                 const double *GL, const double *Lam, double lamL, double *D, double *U,
+                 double *dD, int *changed, const CdScratch &scr, const WaveProbe *probe) {
+    if (nrect <= 0) return;
+    record(s, probe, 0);
+    const int S = lambda_snapshot(s, rects_dev, active, nrect, q, SP, U, Psi, scr);
+    record(s, probe, 1);
+    lambda_gauss_seidel(s, rects_dev, active, nrect, S, q, Sigma, Psi, GL, Lam, lamL, D, dD,
+                        changed, scr, probe ? probe->counters : nullptr);
+    record(s, probe, 2);
+    lambda_update(s, rects_dev, nrect, q, Sigma, dD, changed, U);
     record(s, probe, 3);
 }
 

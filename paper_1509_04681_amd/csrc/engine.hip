@@ -339,40 +339,59 @@ TopStats read_top(Ctx &c, bool with_gradient_stats) {
 
 // HIP-event timing of the kernels of one sweep kind: four events per wave
 // (before the snapshot, Gauss-Seidel and update kernels, and after the update).
+// Optional per-stage kernel timing of the CD sweeps: intervals between pairs
+// of events recorded on the stream a stage runs on, summed per stage
+// (0 snapshot, 1 Gauss-Seidel, 2 update) when the events are done.
 struct KernelTimer {
-    std::vector<hipEvent_t> ev;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    struct Interval {
+        int stage;
+        hipEvent_t a, b;
+    };
+    std::vector<Interval> pending;
     unsigned long long *counters = nullptr;
-    int pending = 0;
-    int64_t waves = 0;
+    int64_t waves = 0, pending_waves = 0;
     double ms[3] = {0.0, 0.0, 0.0};
-    void init(int nwaves, unsigned long long *ctr) {
+    bool enabled = false;
+    void init(unsigned long long *ctr) {
         counters = ctr;
-        ev.resize(4 * (size_t)nwaves, nullptr);
-        for (auto &e : ev) CGGM_HIP(hipEventCreate(&e));
+        enabled = true;
     }
     ~KernelTimer() {
-        for (auto &e : ev)
+        for (auto &e : pool)
             if (e) (void)hipEventDestroy(e);
     }
-    bool on() const { return !ev.empty(); }
-    WaveProbe probe(int k) {
+    bool on() const { return enabled; }
+    hipEvent_t event() {
+        if (used == pool.size()) {
+            hipEvent_t e = nullptr;
+            CGGM_HIP(hipEventCreate(&e));
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+    void interval(int stage, hipEvent_t a, hipEvent_t b) { pending.push_back({stage, a, b}); }
+    // Events of one single-stream wave: snapshot [0,1), Gauss-Seidel [1,2), update [2,3).
+    WaveProbe probe() {
         WaveProbe p;
-        for (int j = 0; j < 4; ++j) p.ev[j] = ev[4 * k + j];
+        for (int j = 0; j < 4; ++j) p.ev[j] = event();
+        for (int j = 0; j < 3; ++j) interval(j, p.ev[j], p.ev[j + 1]);
         p.counters = counters;
-        pending = k + 1;
+        ++pending_waves;
         return p;
     }
-    // Sum the stage durations of the recorded waves (their events must be done).
+    // Sum the pending intervals (their events must be done) and recycle the events.
     void collect() {
-        for (int k = 0; k < pending; ++k) {
-            for (int j = 0; j < 3; ++j) {
-                float m = 0.f;
-                CGGM_HIP(hipEventElapsedTime(&m, ev[4 * k + j], ev[4 * k + j + 1]));
-                ms[j] += m;
-            }
-            ++waves;
+        for (const Interval &iv : pending) {
+            float m = 0.f;
+            CGGM_HIP(hipEventElapsedTime(&m, iv.a, iv.b));
+            ms[iv.stage] += m;
         }
-        pending = 0;
+        pending.clear();
+        used = 0;
+        waves += pending_waves;
+        pending_waves = 0;
     }
 };
 
@@ -383,13 +402,15 @@ void run_theta_sweep(Ctx &c, const Schedule &sch, KernelTimer *kt = nullptr) {
     for (int k = 0; k < sch.waves(); ++k) {
         const int b = sch.wave_start[k], e = sch.wave_start[k + 1];
         WaveProbe pr;
-        if (kt && kt->on()) pr = kt->probe(k);
+        if (kt && kt->on()) pr = kt->probe();
         theta_wave(c.s, w.rects_theta + b, w.act_theta + b, e - b, w.p, w.q, w.Sxx, w.Sxy, w.Sig,
                    w.V, w.GT, w.Th, c.lamT, w.dT, w.changed, w.cd,
                    (kt && kt->on()) ? &pr : nullptr);
     }
 }
 
+// One CD pass over S_Lambda for the Newton direction; D and U start at zero
+// on the first pass and carry over to further passes (pass > 0).
 // One CD pass over S_Lambda for the Newton direction; D and U start at zero
 // on the first pass and carry over to further passes (pass > 0).
 void run_lambda_sweep(Ctx &c, const Schedule &sch, KernelTimer *kt = nullptr, int pass = 0) {
@@ -403,7 +424,7 @@ void run_lambda_sweep(Ctx &c, const Schedule &sch, KernelTimer *kt = nullptr, in
     for (int k = 0; k < sch.waves(); ++k) {
         const int b = sch.wave_start[k], e = sch.wave_start[k + 1];
         WaveProbe pr;
-        if (kt && kt->on()) pr = kt->probe(k);
+        if (kt && kt->on()) pr = kt->probe();
         lambda_wave(c.s, w.rects_lambda + b, w.act_lambda + b, e - b, w.q, w.Sig, w.Psi, w.SP,
                     w.GL, w.Lam, c.lamL, w.D, w.U, w.dD, w.changed, w.cd,
                     (kt && kt->on()) ? &pr : nullptr);
@@ -535,8 +556,8 @@ int solve_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q
     KernelTimer kt_lambda, kt_theta;
     if (opt.kstats) {
         fill(s, 16, 0.0, reinterpret_cast<double *>(w.kctr));   // all-zero bits
-        kt_lambda.init(la_sched.waves(), w.kctr);
-        kt_theta.init(th_sched.waves(), w.kctr + 8);
+        kt_lambda.init(w.kctr);
+        kt_theta.init(w.kctr + 8);
     }
 
     auto t0 = std::chrono::steady_clock::now();

@@ -166,6 +166,21 @@ void theta_wave(hipStream_t s, const TileRect *rects_dev, const int *active, int
                 double *V, const double *GT, double *Theta, double lamT, double *dT,
                 int *changed, const CdScratch &scr, const WaveProbe *probe = nullptr);
 
+// The three stages of a Lambda wave (lambda_wave runs them in order).
+// lambda_snapshot returns the number of K parts the Gauss-Seidel stage must be
+// given.  Within one wave every snapshot must complete before any update
+// starts (the updates write rows of U that every snapshot reads).
+int lambda_snapshot(hipStream_t s, const TileRect *rects_dev, const int *active, int nrect,
+                    int64_t q, const double *SP, const double *U, const double *Psi,
+                    const CdScratch &scr);
+void lambda_gauss_seidel(hipStream_t s, const TileRect *rects_dev, const int *active, int nrect,
+                         int S, int64_t q, const double *Sigma, const double *Psi,
+                         const double *GL, const double *Lam, double lamL, double *D,
+                         double *dD, int *changed, const CdScratch &scr,
+                         unsigned long long *counters);
+void lambda_update(hipStream_t s, const TileRect *rects_dev, int nrect, int64_t q,
+                   const double *Sigma, const double *dD, const int *changed, double *U);
+
 // One wave of the Lambda direction sweep over upper-triangle rects with
 // pairwise-disjoint index sets: exact Gauss-Seidel inside each rect from a
 // snapshot of b = G + SP U + (Psi U)^T, D written (both triangles), then

@@ -447,37 +447,66 @@ void transpose(hipStream_t s, int64_t rows, int64_t cols, const double *src, dou
     CGGM_LAUNCH_CHECK();
 }
 
+// Outer panel width of the blocked factorizations: a panel of OB columns is
+// factored (or solved) with PB-wide steps whose updates stay inside the panel,
+// then the rest of the matrix gets one update with K = OB (a large GEMM on the
+// 128 x 128 tiles instead of OB / PB thin ones).
+constexpr int OB = 4 * PB;
+
 void cholesky_inplace(hipStream_t s, int64_t q, double *A, int *notpd_dev, double *Wd) {
-    for (int64_t kb = 0; kb < q; kb += PB) {
-        const int nb = (int)std::min<int64_t>(PB, q - kb);
-        const int64_t below = q - kb - nb;
-        double *Wk = Wd + (kb / PB) * PB * PB;
-        potrf_diag_kernel<<<1, WAVE, 0, s>>>(A, q, kb, nb, notpd_dev, Wk);
-        CGGM_LAUNCH_CHECK();
-        if (below > 0) {                 // below > 0 implies nb == PB
-            // panel: L[below, k] = A[below, k] L_kk^{-T}, in place (one column tile)
-            double *Pw = A + (kb + nb) * q + kb;
-            gemm(s, false, true, below, nb, nb, 1.0, Pw, q, Wk, PB, 0.0, Pw, q);
-            const double *P = A + (kb + nb) * q + kb;
-            gemm(s, false, true, below, below, nb, -1.0, P, q, P, q, 1.0,
-                 A + (kb + nb) * q + kb + nb, q, UPLO_LOWER, KRANGE_FULL);
+    for (int64_t ob = 0; ob < q; ob += OB) {
+        const int64_t oe = std::min<int64_t>(q, ob + OB);
+        for (int64_t kb = ob; kb < oe; kb += PB) {
+            const int nb = (int)std::min<int64_t>(PB, q - kb);
+            const int64_t below = q - kb - nb;
+            double *Wk = Wd + (kb / PB) * PB * PB;
+            potrf_diag_kernel<<<1, WAVE, 0, s>>>(A, q, kb, nb, notpd_dev, Wk);
+            CGGM_LAUNCH_CHECK();
+            if (below > 0) {                 // below > 0 implies nb == PB
+                // panel: L[below, k] = A[below, k] L_kk^{-T}, in place (one column tile)
+                double *Pw = A + (kb + nb) * q + kb;
+                gemm(s, false, true, below, nb, nb, 1.0, Pw, q, Wk, PB, 0.0, Pw, q);
+                // update of the outer panel's remaining columns [kb + nb, oe)
+                const int64_t ncols = oe - (kb + nb);
+                if (ncols > 0)
+                    gemm(s, false, true, below, ncols, nb, -1.0, Pw, q, Pw, q, 1.0,
+                         A + (kb + nb) * q + kb + nb, q, UPLO_LOWER, KRANGE_FULL);
+            }
+        }
+        const int64_t rest = q - oe;
+        if (rest > 0) {
+            // trailing update with the whole outer panel: A[oe:, oe:] -= P P^T
+            const double *P = A + oe * q + ob;
+            gemm(s, false, true, rest, rest, oe - ob, -1.0, P, q, P, q, 1.0, A + oe * q + oe, q,
+                 UPLO_LOWER, KRANGE_FULL);
         }
     }
 }
 
 void trsm_lower_left(hipStream_t s, int64_t q, const double *L, const double *Wd, double *B,
                      int64_t m, int64_t ldb, bool lower_rhs) {
-    for (int64_t kb = 0; kb < q; kb += PB) {
-        const int nb = (int)std::min<int64_t>(PB, q - kb);
-        const int64_t ncols = lower_rhs ? std::min<int64_t>(m, kb + nb) : m;
-        // B_k <- L_kk^{-1} B_k in place (one row tile: every output tile reads its
-        // whole K range before it is written)
-        gemm(s, false, false, nb, ncols, nb, 1.0, Wd + (kb / PB) * PB * PB, PB, B + kb * ldb, ldb,
-             0.0, B + kb * ldb, ldb);
-        const int64_t below = q - kb - nb;
-        if (below > 0)
-            gemm(s, false, false, below, ncols, nb, -1.0, L + (kb + nb) * q + kb, q,
-                 B + kb * ldb, ldb, 1.0, B + (kb + nb) * ldb, ldb);
+    for (int64_t ob = 0; ob < q; ob += OB) {
+        const int64_t oe = std::min<int64_t>(q, ob + OB);
+        for (int64_t kb = ob; kb < oe; kb += PB) {
+            const int nb = (int)std::min<int64_t>(PB, q - kb);
+            const int64_t ncols = lower_rhs ? std::min<int64_t>(m, kb + nb) : m;
+            // B_k <- L_kk^{-1} B_k in place (one row tile: every output tile reads its
+            // whole K range before it is written)
+            gemm(s, false, false, nb, ncols, nb, 1.0, Wd + (kb / PB) * PB * PB, PB,
+                 B + kb * ldb, ldb, 0.0, B + kb * ldb, ldb);
+            // rows of the outer panel below this block
+            const int64_t rows = oe - kb - nb;
+            if (rows > 0)
+                gemm(s, false, false, rows, ncols, nb, -1.0, L + (kb + nb) * q + kb, q,
+                     B + kb * ldb, ldb, 1.0, B + (kb + nb) * ldb, ldb);
+        }
+        const int64_t rest = q - oe;
+        if (rest > 0) {
+            // every row below the outer panel: B[oe:] -= L[oe:, ob:oe] B[ob:oe]
+            const int64_t ncols = lower_rhs ? std::min<int64_t>(m, oe) : m;
+            gemm(s, false, false, rest, ncols, oe - ob, -1.0, L + oe * q + ob, q, B + ob * ldb,
+                 ldb, 1.0, B + oe * ldb, ldb);
+        }
     }
 }
 
