@@ -94,7 +94,8 @@ inline int64_t snapshot_blocks(int64_t groups, int blocks_per_group) {
     return (groups + NXCD - 1) / NXCD * NXCD * blocks_per_group;
 }
 // Block of one wavefront: 64 x 32 (6 operand loads per 8 MFMAs per k-step),
-// U = 4 k-steps per batch; 136 VGPRs + 64 AGPRs, two waves per SIMD.
+// two register batches of U = 4 k-steps (one in flight while the other is
+// multiplied); about 170 VGPRs + 64 AGPRs, two waves per SIMD.
 constexpr int SNAP_WM = 64, SNAP_WN = 32, SNAP_U = 4;
 template <int TS>
 constexpr int snap_blocks_per_tile() {
@@ -133,32 +134,39 @@ __global__ __launch_bounds__(WAVE) void snapshot_kernel(const TileRect *__restri
     for (int i = 0; i < MI; ++i)
 #pragma unroll
         for (int j = 0; j < NJ; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
+#pragma unroll 1
     for (int pp = 0; pp < NPAIR; ++pp) {
         const double *A = args.A[pp] + rc.r0 + mo;
         const double *B = args.B[pp] + rc.c0 + no;
         const int64_t lda = args.lda[pp], ldb = args.ldb[pp];
-        for (int64_t st = s0; st < s1; st += U) {
-            double a[U][MI], b[U][NJ];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int64_t k = (st + u) * 4 + krow;
-                const bool kv = (st + u) < s1 && k < K;
-#pragma unroll
-                for (int i = 0; i < MI; ++i)
-                    a[u][i] = (kv && am[i]) ? A[k * lda + col + i * 16] : 0.0;
-#pragma unroll
-                for (int j = 0; j < NJ; ++j)
-                    b[u][j] = (kv && bn[j]) ? B[k * ldb + col + j * 16] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-#pragma unroll
-                for (int i = 0; i < MI; ++i)
-#pragma unroll
-                    for (int j = 0; j < NJ; ++j)
-                        acc[i][j] = mfma_f64_16x16x4(a[u][i], b[u][j], acc[i][j]);
+        // Two register batches: the loads of the next batch are in flight
+        // while the current one is multiplied (loads past the K range are
+        // predicated off and multiply zeros).
+        double a[2][U][MI], b[2][U][NJ];
+#define SNAP_LOAD(BUF, ST0)                                                              \
+    _Pragma("unroll") for (int u = 0; u < U; ++u) {                                      \
+        const int64_t k = ((ST0) + u) * 4 + krow;                                        \
+        const bool kv = ((ST0) + u) < s1 && k < K;                                       \
+        _Pragma("unroll") for (int i = 0; i < MI; ++i) a[BUF][u][i] =                    \
+            (kv && am[i]) ? A[k * lda + col + i * 16] : 0.0;                             \
+        _Pragma("unroll") for (int j = 0; j < NJ; ++j) b[BUF][u][j] =                    \
+            (kv && bn[j]) ? B[k * ldb + col + j * 16] : 0.0;                             \
+    }
+#define SNAP_MMA(BUF)                                                                    \
+    _Pragma("unroll") for (int u = 0; u < U; ++u)                                        \
+        _Pragma("unroll") for (int i = 0; i < MI; ++i)                                   \
+            _Pragma("unroll") for (int j = 0; j < NJ; ++j)                               \
+                acc[i][j] = mfma_f64_16x16x4(a[BUF][u][i], b[BUF][u][j], acc[i][j]);
+        SNAP_LOAD(0, s0)
+        for (int64_t st = s0; st < s1; st += 2 * U) {
+            SNAP_LOAD(1, st + U)
+            SNAP_MMA(0)
+            SNAP_LOAD(0, st + 2 * U)
+            SNAP_MMA(1)
         }
+#undef SNAP_LOAD
+#undef SNAP_MMA
+
     }
     double *out = partial + ((int64_t)e * S + s) * TS * TS;
 #pragma unroll
