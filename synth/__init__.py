@@ -115,6 +115,146 @@ def chain_problem(p: int, q: int, n: int, density: float, lam: float, seed: int 
                    name=f"chain-p{p}-q{q}-n{n}-rho{density:g}-lam{lam:g}-seed{seed}")
 
 
+# ---------------------------------------------------------------------------
+# The paper's own synthetic workloads (Sec. 5.1).
+#   * chain: Lambda_ii = 2.25, Lambda_{i,i-1} = Lambda_{i-1,i} = 1, Theta_ii = 1
+#     for i < q; with p = 2q the last q inputs are irrelevant (zero rows);
+#   * clustered: Lambda's graph has clusters of 250 nodes, 90% of its edges
+#     join two nodes of one cluster (a cluster drawn uniformly, then two
+#     distinct nodes in it), 10% two distinct nodes anywhere; 5q edges in
+#     total (average degree 10), no repeats, weight 1; the diagonal is the row's
+#     absolute sum plus 1 (strictly diagonally dominant, hence positive
+#     definite -- the paper only asks for a positive definite Lambda).  Theta:
+#     min(p, round(100 sqrt(p))) inputs drawn without replacement; each gets
+#     one edge to a uniform output, then the rest of the 10q edges go to
+#     uniform (selected input, output) pairs without repeats; weight 1.
+#   * X ~ N(0, I) (the paper does not state the input distribution), Y | X
+#     from the model (see _sample_general); RNG order: Lambda, Theta, X, noise.
+# ---------------------------------------------------------------------------
+def paper_chain_problem(q: int, p: int | None = None, n: int = 100, lam: float = 0.1,
+                        seed: int = 0, lam_Theta: float | None = None) -> Problem:
+    p = q if p is None else p
+    rng = np.random.default_rng(seed)
+    Lam = sp.diags([np.ones(q - 1), np.full(q, 2.25), np.ones(q - 1)], [-1, 0, 1],
+                   format="csr", dtype=np.float64)
+    m = min(p, q)
+    Theta = sp.csr_matrix((np.ones(m), (np.arange(m), np.arange(m))), shape=(p, q))
+    X, Y = _sample_general(Lam, Theta, n, rng)
+    lt = lam if lam_Theta is None else lam_Theta
+    return Problem(X=X, Y=Y, lam_Lambda=float(lam), lam_Theta=float(lt), Lambda_true=Lam,
+                   Theta_true=Theta, name=f"paperchain-p{p}-q{q}-n{n}-lam{lam:g}-seed{seed}")
+
+
+def clustered_lambda(q: int, rng: np.random.Generator, cluster: int = 250,
+                     degree: float = 10.0, within: float = 0.9) -> sp.csr_matrix:
+    n_edges = int(round(degree * q / 2))
+    n_clusters = max(1, (q + cluster - 1) // cluster)
+    edges = set()
+    max_edges = q * (q - 1) // 2
+    n_edges = min(n_edges, max_edges)
+    while len(edges) < n_edges:
+        if rng.random() < within:
+            c = int(rng.integers(n_clusters))
+            lo, hi = c * cluster, min(q, (c + 1) * cluster)
+            if hi - lo < 2:
+                continue
+            i, j = rng.integers(lo, hi, 2)
+        else:
+            i, j = rng.integers(0, q, 2)
+        if i == j:
+            continue
+        edges.add((int(min(i, j)), int(max(i, j))))
+    e = np.array(sorted(edges), dtype=np.int64).reshape(-1, 2)
+    rows = np.concatenate([e[:, 0], e[:, 1]])
+    cols = np.concatenate([e[:, 1], e[:, 0]])
+    A = sp.csr_matrix((np.ones(rows.size), (rows, cols)), shape=(q, q))
+    diag = np.asarray(abs(A).sum(axis=1)).ravel() + 1.0
+    return (A + sp.diags(diag)).tocsr()
+
+
+def clustered_theta(p: int, q: int, rng: np.random.Generator) -> sp.csr_matrix:
+    n_inputs = min(p, int(round(100 * np.sqrt(p))))
+    inputs = rng.choice(p, size=n_inputs, replace=False)
+    n_edges = min(10 * q, n_inputs * q)
+    edges = set()
+    for i in inputs[: min(n_inputs, n_edges)]:
+        edges.add((int(i), int(rng.integers(q))))
+    while len(edges) < n_edges:
+        edges.add((int(inputs[rng.integers(n_inputs)]), int(rng.integers(q))))
+    e = np.array(sorted(edges), dtype=np.int64).reshape(-1, 2)
+    return sp.csr_matrix((np.ones(len(e)), (e[:, 0], e[:, 1])), shape=(p, q))
+
+
+def clustered_problem(p: int, q: int, n: int = 200, lam: float = 0.1, seed: int = 0,
+                      lam_Theta: float | None = None) -> Problem:
+    rng = np.random.default_rng(seed)
+    Lam = clustered_lambda(q, rng)
+    Theta = clustered_theta(p, q, rng)
+    X, Y = _sample_general(Lam, Theta, n, rng)
+    lt = lam if lam_Theta is None else lam_Theta
+    return Problem(X=X, Y=Y, lam_Lambda=float(lam), lam_Theta=float(lt), Lambda_true=Lam,
+                   Theta_true=Theta, name=f"clustered-p{p}-q{q}-n{n}-lam{lam:g}-seed{seed}")
+
+
+def _sample_general(Lam: sp.csr_matrix, Theta: sp.csr_matrix, n: int,
+                    rng: np.random.Generator) -> tuple[np.ndarray, np.ndarray]:
+    """X ~ N(0, I); Y = -X Theta Sigma + E with E ~ N(0, Sigma) drawn as
+    E = W Lambda^{-1}, W = Z1 B + Z2 diag(sqrt(r)): B has one row
+    sqrt(|w|) (e_i + sign(w) e_j) per edge (i < j, weight w) and r is the
+    diagonal-dominance margin Lambda_ii - sum_j |Lambda_ij| >= 0, so that
+    Cov(w) = B^T B + diag(r) = Lambda and Cov(e) = Lambda^{-1}.  Solves with
+    Lambda by conjugate gradients; RNG order X, Z1, Z2."""
+    p, q = Theta.shape
+    X = rng.standard_normal((n, p))
+    Lam = sp.csr_matrix(Lam)
+    up = sp.triu(Lam, 1).tocoo()
+    r = Lam.diagonal() - np.asarray(abs(Lam - sp.diags(Lam.diagonal())).sum(axis=1)).ravel()
+    if np.any(r < -1e-12):
+        raise ValueError("the sampler needs a diagonally dominant Lambda")
+    ne = up.nnz
+    w = np.sqrt(np.abs(up.data))
+    B = sp.csr_matrix((np.concatenate([w, w * np.sign(up.data)]),
+                       (np.concatenate([np.arange(ne), np.arange(ne)]),
+                        np.concatenate([up.row, up.col]))), shape=(ne, q))
+    Z1 = rng.standard_normal((n, ne))
+    Z2 = rng.standard_normal((n, q))
+    W = np.asarray((sp.csr_matrix(Z1) @ B).todense()) + Z2 * np.sqrt(np.maximum(r, 0.0))
+    M = np.asarray((sp.csr_matrix(X) @ Theta).todense()) if Theta.nnz else np.zeros((n, q))
+    mean_t = _spd_solve(Lam, M.T)                             # Sigma (X Theta)^T
+    e_t = _spd_solve(Lam, W.T)                                # Lambda^{-1} w^T
+    Y = np.ascontiguousarray((-mean_t + e_t).T)
+    return np.ascontiguousarray(X), Y
+
+
+def _spd_solve(A: sp.csr_matrix, Bm: np.ndarray, rtol: float = 1e-15,
+               max_iter: int = 5000) -> np.ndarray:
+    """A^{-1} Bm for a sparse, strictly diagonally dominant (hence SPD and
+    well-conditioned) A: conjugate gradients on all columns at once, Jacobi
+    preconditioned, until every column's residual is below rtol ||b||."""
+    Bm = np.ascontiguousarray(Bm, dtype=np.float64)
+    dinv = 1.0 / A.diagonal()
+    Xs = Bm * dinv[:, None]
+    R = Bm - A @ Xs
+    Zr = R * dinv[:, None]
+    P = Zr.copy()
+    rz = np.einsum("ij,ij->j", R, Zr)
+    bnorm = np.linalg.norm(Bm, axis=0)
+    for _ in range(max_iter):
+        if np.all(np.linalg.norm(R, axis=0) <= rtol * np.maximum(bnorm, 1e-300)):
+            break
+        AP = A @ P
+        pap = np.einsum("ij,ij->j", P, AP)
+        alpha = np.where(pap > 0, rz / np.where(pap > 0, pap, 1.0), 0.0)
+        Xs += P * alpha
+        R -= AP * alpha
+        Zr = R * dinv[:, None]
+        rz_new = np.einsum("ij,ij->j", R, Zr)
+        beta = np.where(rz > 0, rz_new / np.where(rz > 0, rz, 1.0), 0.0)
+        P = Zr + P * beta
+        rz = rz_new
+    return Xs
+
+
 # Named workloads (shapes, densities and penalties of the benchmark configurations).
 WORKLOADS = {
     # p = q = 40, n = 100, 5% dense Theta, lambda = 0.1
@@ -126,13 +266,27 @@ WORKLOADS = {
     # parity case large enough (K >= 512) that tile gradient snapshots are
     # split over several workgroups
     "chain530": dict(p=530, q=515, n=100, density=0.005, lam=0.5, seed=21),
+    # the paper's own synthetic workloads (Sec. 5.1) at one-GPU test sizes;
+    # penalties chosen by tests/golden/choose_lambda.py (estimated edge counts
+    # of Lambda and of Theta closest to the truth on reduced instances, as
+    # the paper chooses them)
+    "paperchain2k": dict(kind="paperchain", q=2000, n=100, lam=1.9404, lam_Theta=1.5606),
+    "paperchain2k_p2q": dict(kind="paperchain", q=2000, p=4000, n=100, lam=1.9404,
+                             lam_Theta=1.5606),
+    "clustered2k": dict(kind="clustered", p=4000, q=2000, n=200, lam=0.0478, lam_Theta=0.1767),
+    # the size of the paper's active-set-versus-time experiment (Sec. 5.1)
+    "clustered20k": dict(kind="clustered", p=20000, q=10000, n=200, lam=0.0478,
+                         lam_Theta=0.1767),
 }
 
 
 def workload(name: str, seed: int | None = None) -> Problem:
     kw = dict(WORKLOADS[name])
     kw["seed"] = kw.get("seed", 0) if seed is None else seed
-    return chain_problem(**kw)
+    kind = kw.pop("kind", "chain")
+    make = {"chain": chain_problem, "paperchain": paper_chain_problem,
+            "clustered": clustered_problem}[kind]
+    return make(**kw)
 
 
 def random_spd(q: int, rng: np.random.Generator, degree: float = 4.0,
