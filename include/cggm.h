@@ -50,6 +50,17 @@ extern "C" {
                                    order: the order of the paper's Algorithm 1
                                    and of the CPU reference                      */
 
+/* ---- arithmetic ---------------------------------------------------------
+ * FP64: every step in FP64.
+ * MIXED: V = Theta Sigma, the product that only steers the Theta
+ *   coordinate-descent pass (Sec. 3.2), is formed from three-piece BF16 splits
+ *   of Theta and Sigma on the BF16 matrix cores with FP32 accumulation (about
+ *   1e-6 relative error); the Cholesky factor, log det, Sigma, Psi, both
+ *   gradients, the screen, the stopping rule, the objective and the line
+ *   search stay FP64. */
+#define CGGM_PRECISION_FP64 0
+#define CGGM_PRECISION_MIXED 1
+
 /* One record per outer iteration (Algorithm 1), filled when options.trace is
  * non-NULL.  Values describe the iterate at the top of iteration `iter`. */
 typedef struct {
@@ -101,6 +112,8 @@ typedef struct {
     int tile;              /* CD tile edge for CGGM_SWEEP_TILED (0 = default)  */
     int lambda_passes;     /* CD passes of the Lambda direction over S_Lambda
                               per iteration (Sec. 3 makes one; default 4)     */
+    int precision;         /* CGGM_PRECISION_FP64 (default) or
+                              CGGM_PRECISION_MIXED                             */
     size_t workspace_budget;   /* bytes of device workspace allowed (0 = any)  */
     const double *warm_Lambda; /* device q x q start (NULL = identity)         */
     const double *warm_Theta;  /* device p x q start (NULL = zero)             */

@@ -20,6 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcggm.so")
 
 CGGM_OK, CGGM_MAXITER = 0, 1
+CGGM_PRECISION_FP64, CGGM_PRECISION_MIXED = 0, 1
 CGGM_EINVAL, CGGM_ENOTPD, CGGM_ELINESEARCH, CGGM_ENOMEM, CGGM_EHIP = -1, -2, -3, -4, -5
 CGGM_SWEEP_TILED, CGGM_SWEEP_SEQUENTIAL = 0, 1
 
@@ -54,6 +55,7 @@ class Options(ctypes.Structure):
                 ("ls_beta", ctypes.c_double), ("ls_sigma", ctypes.c_double),
                 ("stall_iters", ctypes.c_int), ("sweep", ctypes.c_int),
                 ("tile", ctypes.c_int), ("lambda_passes", ctypes.c_int),
+                ("precision", ctypes.c_int),
                 ("workspace_budget", ctypes.c_size_t),
                 ("warm_Lambda", _vp), ("warm_Theta", _vp),
                 ("trace", ctypes.POINTER(TraceEntry)), ("trace_cap", ctypes.c_int),
@@ -162,7 +164,8 @@ class SolveResult:
 def cggm_solve(X, Y, lam_Lambda: float, lam_Theta: float, tol: float = 1e-2, *,
                max_iter: int = 500, max_ls: int = 30, ls_beta: float = 0.5,
                ls_sigma: float = 1e-3, stall_iters: int = 3, sweep: int = CGGM_SWEEP_TILED,
-               tile: int = 0, lambda_passes: int = 4, workspace_budget: int = 0,
+               tile: int = 0, lambda_passes: int = 4, precision: str = "fp64",
+               workspace_budget: int = 0,
                warm_Lambda=None, warm_Theta=None, trace_cap: int | None = None,
                keep_csr: bool = False, kernel_stats: bool = False,
                stream=None) -> SolveResult:
@@ -176,6 +179,7 @@ def cggm_solve(X, Y, lam_Lambda: float, lam_Theta: float, tol: float = 1e-2, *,
     opt.max_iter, opt.max_ls, opt.ls_beta, opt.ls_sigma = max_iter, max_ls, ls_beta, ls_sigma
     opt.stall_iters, opt.sweep, opt.tile = stall_iters, sweep, tile
     opt.lambda_passes = lambda_passes
+    opt.precision = {"fp64": CGGM_PRECISION_FP64, "mixed": CGGM_PRECISION_MIXED}[precision]
     opt.workspace_budget = workspace_budget
     if warm_Lambda is not None:
         opt.warm_Lambda = _dev(warm_Lambda, "warm_Lambda").value

@@ -204,13 +204,14 @@ struct Work {
     int *act_theta, *act_lambda;                   // per-rect activity of a sweep
     TileRect *rects_theta, *rects_lambda;
     int max_tiles = 0;
+    __bf16 *split_Th = nullptr, *split_Sig = nullptr;   // mixed mode: BF16 pieces
 };
 
 constexpr int NSCAL = 64;
 
 // Layout of the workspace; with a.measure it only sizes it.
 void layout(Arena &a, Work &w, int64_t n, int64_t p, int64_t q, int64_t ntheta_rects,
-            int64_t nlambda_rects, int max_tiles) {
+            int64_t nlambda_rects, int max_tiles, bool mixed = false) {
     const int64_t qq = q * q, pq = p * q, nq = n * q;
     w.n = n, w.p = p, w.q = q;
     w.Sxx = a.take<double>(p * p);
@@ -249,6 +250,10 @@ void layout(Arena &a, Work &w, int64_t n, int64_t p, int64_t q, int64_t ntheta_r
     w.act_lambda = a.take<int>(nlambda_rects);
     w.rects_theta = a.take<TileRect>(ntheta_rects);
     w.rects_lambda = a.take<TileRect>(nlambda_rects);
+    if (mixed) {
+        w.split_Th = a.take<__bf16>(3 * p * split3_stride(q));
+        w.split_Sig = a.take<__bf16>(3 * q * split3_stride(q));
+    }
 }
 
 // Scalars read back at the top of an iteration (offsets into Work::scal).
@@ -268,7 +273,21 @@ struct Ctx {
     hipStream_t s;
     Work &w;
     double lamL, lamT;
+    bool mixed = false;
 };
+
+// V = Theta Sigma: FP64 MFMA, or in mixed mode from the BF16 pieces of Theta
+// and Sigma (Sigma symmetric: its rows are the columns the product needs).
+void theta_sigma(Ctx &c) {
+    Work &w = c.w;
+    if (!c.mixed) {
+        gemm(c.s, false, false, w.p, w.q, w.q, 1.0, w.Th, w.q, w.Sig, w.q, 0.0, w.V, w.q);
+        return;
+    }
+    split3(c.s, w.p, w.q, w.Th, w.q, w.split_Th);
+    split3(c.s, w.q, w.q, w.Sig, w.q, w.split_Sig);
+    gemm_split3_nt(c.s, w.p, w.q, w.q, w.split_Th, w.split_Sig, w.V, w.q);
+}
 
 // Rounding allowance of an FP64 objective evaluation in the Armijo test and
 // the Theta descent guard.
@@ -508,8 +527,10 @@ int solve_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q
     if (opt.max_iter < 0 || opt.max_ls < 1 || !(opt.ls_beta > 0.0 && opt.ls_beta < 1.0) ||
         !(opt.ls_sigma > 0.0 && opt.ls_sigma < 1.0) || opt.stall_iters < 0 ||
         opt.lambda_passes < 1 ||
+        (opt.precision != CGGM_PRECISION_FP64 && opt.precision != CGGM_PRECISION_MIXED) ||
         (opt.sweep != CGGM_SWEEP_TILED && opt.sweep != CGGM_SWEEP_SEQUENTIAL))
         fail(CGGM_EINVAL, "invalid options");
+    const bool mixed = opt.precision == CGGM_PRECISION_MIXED;
     const auto [tileL, tileT] = tile_edges(opt.tile);
     const bool seq = opt.sweep == CGGM_SWEEP_SEQUENTIAL;
     const Schedule th_sched = theta_schedule(p, q, tileT, seq);
@@ -532,7 +553,7 @@ int solve_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q
     sizer.measure = true;
     Work w;
     layout(sizer, w, n, p, q, (int64_t)th_sched.rects.size(), (int64_t)la_sched.rects.size(),
-           max_tiles);
+           max_tiles, mixed);
     if (opt.workspace_budget && sizer.used > opt.workspace_budget)
         fail(CGGM_ENOMEM, "workspace of " + std::to_string(sizer.used) +
                               " bytes exceeds the budget of " +
@@ -545,12 +566,16 @@ int solve_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q
     Arena arena;
     arena.base = (char *)buf.p;
     layout(arena, w, n, p, q, (int64_t)th_sched.rects.size(), (int64_t)la_sched.rects.size(),
-           max_tiles);
+           max_tiles, mixed);
     CGGM_HIP(hipMemcpyAsync(w.rects_theta, th_sched.rects.data(),
                             sizeof(TileRect) * th_sched.rects.size(), hipMemcpyHostToDevice, s));
     CGGM_HIP(hipMemcpyAsync(w.rects_lambda, la_sched.rects.data(),
                             sizeof(TileRect) * la_sched.rects.size(), hipMemcpyHostToDevice, s));
-    Ctx c{s, w, lamL, lamT};
+    Ctx c{s, w, lamL, lamT, mixed};
+    // The Theta descent guard compares FP64 objectives; in mixed mode V carries
+    // the error of the split-BF16 product, so the sweep is exact only to about
+    // that level and the guard allows a correspondingly larger increase.
+    const double theta_guard = mixed ? 1e-10 : F_ROUNDING;
     const int64_t qq = q * q, pq = p * q;
     check_finite(c, X, Y);
     KernelTimer kt_lambda, kt_theta;
@@ -615,12 +640,12 @@ int solve_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q
         reduce_logdet(s, q, w.L, w.partials, w.scal + S_LOGDET);
         TopStats pre = read_top(c, false);
         kt_theta.collect();                       // the last Theta sweep is done
-        if (t > 0 && pre.f > f_after_ls + F_ROUNDING * std::max(1.0, fabs(f_after_ls))) {
+        if (t > 0 && pre.f > f_after_ls + theta_guard * std::max(1.0, fabs(f_after_ls))) {
             // Descent guard: the concurrent tiles of the Theta sweep raised f.
             // Redo the sweep one tile per wave (exact block Gauss-Seidel).
             CGGM_HIP(hipMemcpyAsync(w.Th, w.ThOld, sizeof(double) * pq, hipMemcpyDeviceToDevice,
                                     s));
-            gemm(s, false, false, p, q, q, 1.0, w.Th, q, w.Sig, q, 0.0, w.V, q);
+            theta_sigma(c);
             run_theta_sweep(c, th_safe);
             ++last_fallbacks;
             theta_products(c, X);
@@ -766,7 +791,7 @@ int solve_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q
 
         // ---- Theta: one CD pass on Eq. (7) with Sigma of the new Lambda ----
         CGGM_HIP(hipMemcpyAsync(w.ThOld, w.Th, sizeof(double) * pq, hipMemcpyDeviceToDevice, s));
-        gemm(s, false, false, p, q, q, 1.0, w.Th, q, w.Sig, q, 0.0, w.V, q);   // V = Theta Sigma
+        theta_sigma(c);                                              // V = Theta Sigma
         run_theta_sweep(c, th_sched, &kt_theta);
         theta_products(c, X);
     }
@@ -954,6 +979,7 @@ void cggm_default_options(cggm_options *opt) {
     opt->sweep = CGGM_SWEEP_TILED;
     opt->tile = 0;
     opt->lambda_passes = 4;
+    opt->precision = CGGM_PRECISION_FP64;
 }
 
 size_t cggm_solve_workspace_bytes(int64_t n, int64_t p, int64_t q) {

@@ -125,6 +125,22 @@ void set_int(hipStream_t s, int *dst, int v);
 void reduce_nonfinite(hipStream_t s, int64_t count, const double *x, double *partials,
                       double *out);
 
+// ------------------------------------------------------------- mixed.hip ---
+// Row length of the BF16 pieces of a matrix with `cols` columns (padded to the
+// K step of the split product, the padding zero).
+int64_t split3_stride(int64_t cols);
+
+// The three BF16 pieces hi, mid, lo of X (rows x cols, leading dimension ldx):
+// planes[t * rows * split3_stride(cols) + r * split3_stride(cols) + c].
+void split3(hipStream_t s, int64_t rows, int64_t cols, const double *X, int64_t ldx,
+            __bf16 *planes);
+
+// C (M x N, FP64, leading dimension ldc) = A B^T from the pieces of A (M x K)
+// and B (N x K), the six leading cross products on the BF16 matrix cores with
+// FP32 accumulation.
+void gemm_split3_nt(hipStream_t s, int64_t M, int64_t N, int64_t K, const __bf16 *Ap,
+                    const __bf16 *Bp, double *C, int64_t ldc);
+
 // ---------------------------------------------------------------- cd.hip ---
 struct TileRect {
     int32_t r0, r1, c0, c1;   // rows [r0, r1), columns [c0, c1)

@@ -70,6 +70,10 @@ def test_argument_errors_without_device(lib):
     assert lib.cggm_solve(fake, fake, 4, 3, 2, 0.1, 0.1, 0.01, ctypes.byref(opt),
                           ctypes.byref(r), None) == m.CGGM_EINVAL
     lib.cggm_default_options(ctypes.byref(opt))
+    opt.precision = 2
+    assert lib.cggm_solve(fake, fake, 4, 3, 2, 0.1, 0.1, 0.01, ctypes.byref(opt),
+                          ctypes.byref(r), None) == m.CGGM_EINVAL
+    lib.cggm_default_options(ctypes.byref(opt))
     opt.lambda_passes = 0
     assert lib.cggm_solve(fake, fake, 4, 3, 2, 0.1, 0.1, 0.01, ctypes.byref(opt),
                           ctypes.byref(r), None) == m.CGGM_EINVAL
@@ -98,3 +102,4 @@ def test_default_options(lib):
         (500, 30, 0.5, 1e-3, 3)
     assert opt.sweep == m.CGGM_SWEEP_TILED
     assert opt.lambda_passes == 4
+    assert opt.precision == m.CGGM_PRECISION_FP64

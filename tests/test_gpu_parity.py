@@ -336,3 +336,38 @@ def test_chain2k_converged_solve_is_certified(cg):
     assert np.all(np.diff(fs) <= 1e-14 * np.abs(fs[1:]))
     assert np.array_equal(Lg, Lg.T)
     assert np.all(np.linalg.eigvalsh(Lg) > 0)
+
+
+@pytest.mark.parametrize("name", ["chain40", "chain530"])
+def test_mixed_precision_reaches_the_oracle_optimum(cg, name):
+    """Mixed mode (V = Theta Sigma from split-BF16 products, everything that
+    decides the objective in FP64): the converged objective is within 1e-6 of
+    the oracle's f* and the supports {|x| > 1e-6} agree outside the
+    borderline band."""
+    g0 = load_golden(name)
+    pr = synth.workload(name)
+    g = cg.cggm_solve(dev(pr.X), dev(pr.Y), pr.lam_Lambda, pr.lam_Theta, tol=0.0,
+                      max_iter=5000, precision="mixed")
+    Lg, Tg = g.Lambda.cpu().numpy(), g.Theta.cpu().numpy()
+    sL, sT = np.abs(Lg) > SUPPORT_EPS, np.abs(Tg) > SUPPORT_EPS
+    mL = int(np.sum((sL != g0["support_Lambda"]) & ~g0["borderline_Lambda"]))
+    mT = int(np.sum((sT != g0["support_Theta"]) & ~g0["borderline_Theta"]))
+    rel = abs(g.f - g0["f_star"]) / abs(g0["f_star"])
+    print(f"{name} mixed: f={g.f!r} f*={g0['f_star']!r} rel={rel:.2e} iters={g.iters} "
+          f"status={g.status} support mismatches {mL}/{mT}", flush=True)
+    assert rel <= 1e-6
+    assert mL == 0 and mT == 0
+
+
+def test_mixed_precision_iterates_track_fp64(cg):
+    """The first iterations of a mixed solve stay close to the FP64 ones (the
+    split product only perturbs the Theta pass)."""
+    pr = synth.workload("chain530")
+    kw = dict(tol=0.0, max_iter=8, stall_iters=0)
+    a = cg.cggm_solve(dev(pr.X), dev(pr.Y), pr.lam_Lambda, pr.lam_Theta, **kw)
+    b = cg.cggm_solve(dev(pr.X), dev(pr.Y), pr.lam_Lambda, pr.lam_Theta, precision="mixed", **kw)
+    fa = np.array([t["f"] for t in a.trace])
+    fb = np.array([t["f"] for t in b.trace])
+    print("fp64 vs mixed relative differences:", np.abs(fa - fb) / np.abs(fa), flush=True)
+    assert fa[0] == fb[0]                       # the top of iteration 0 is shared
+    np.testing.assert_allclose(fb, fa, rtol=1e-5)
