@@ -22,8 +22,10 @@
  *   - Return value: CGGM_OK (0), a warning (> 0: results are valid) or an error
  *     (< 0: outputs are left untouched).  cggm_last_error() gives a message for
  *     the last failing call on the calling thread.
- *   - No entry point throws; the library allocates its own device workspace
- *     per call with hipMalloc and frees it before returning.
+ *   - No entry point throws.  The solve entry points allocate their device
+ *     workspace per call with hipMalloc and free it before returning; the
+ *     request server allocates one device pool when it is created and carves
+ *     every request's workspace out of it.
  */
 #ifndef CGGM_H
 #define CGGM_H
@@ -43,6 +45,7 @@ extern "C" {
 #define CGGM_ELINESEARCH (-3) /* no Armijo step found (last iterate returned)   */
 #define CGGM_ENOMEM (-4)      /* workspace over budget or hipMalloc failed      */
 #define CGGM_EHIP (-5)        /* a HIP runtime call failed                      */
+#define CGGM_ECAPACITY (-6)   /* request larger than a server's device pool     */
 
 /* ---- coordinate-descent sweep schedules ------------------------------ */
 #define CGGM_SWEEP_TILED 0      /* conflict-free parallel tile waves (default)   */
@@ -126,9 +129,13 @@ typedef struct {
 /* Fill `opt` with the defaults above. */
 void cggm_default_options(cggm_options *opt);
 
-/* Device bytes cggm_solve would allocate for this shape (the footprint the
- * workspace_budget option is compared against). */
+/* Device bytes cggm_solve would allocate for this shape with default options
+ * (the footprint the workspace_budget option is compared against). */
 size_t cggm_solve_workspace_bytes(int64_t n, int64_t p, int64_t q);
+
+/* The same for the given options (NULL = defaults; the mixed mode needs more);
+ * 0 for invalid sizes or options. */
+size_t cggm_workspace_bytes(int64_t n, int64_t p, int64_t q, const cggm_options *opt);
 
 typedef struct cggm_result cggm_result;   /* opaque, owns device CSR arrays */
 
@@ -160,6 +167,25 @@ typedef struct cggm_result cggm_result;   /* opaque, owns device CSR arrays */
 int cggm_solve(const double *X, const double *Y, int64_t n, int64_t p, int64_t q,
                double lamL, double lamT, double tol, cggm_options *opt,
                cggm_result **out, void *stream);
+
+/*
+ * Regularisation path: the solves of cggm_solve at the npath penalty pairs
+ * (lamL[k], lamT[k]) (host arrays), taken in order, each starting from the
+ * previous point's result (warm starts; the paper solves one penalty pair at a
+ * time, this is the batched form of its Algorithm 1); the first point starts
+ * from options.warm_* or from Lambda = I, Theta = 0.  The statistics Sxx, Sxy, Syy are formed once and
+ * the workspace (Sigma, the factor, the maintained products) stays resident
+ * between points.  Point k's result is bit-for-bit the result of cggm_solve at
+ * (lamL[k], lamT[k]) warm-started from point k-1's Lambda and Theta.
+ * out: host array of npath handles, all filled unless the return value is an
+ * error other than CGGM_ELINESEARCH (then none are).  Returns the first
+ * negative status of a point, else CGGM_MAXITER if a point reached the cap,
+ * else CGGM_OK; each point's own status is in cggm_result_info.  Trace records
+ * of all points are appended in order (iter restarts at 0 for each point).
+ */
+int cggm_solve_path(const double *X, const double *Y, int64_t n, int64_t p, int64_t q,
+                    int npath, const double *lamL, const double *lamT, double tol,
+                    cggm_options *opt, cggm_result **out, void *stream);
 
 /* Scalars of a result: nonzeros of Lambda (both triangles) and Theta, the
  * number of outer iterations, the final objective and the solve status. */
@@ -197,6 +223,79 @@ int cggm_objective(const double *X, const double *Y, int64_t n, int64_t p, int64
 int cggm_gradient(const double *X, const double *Y, int64_t n, int64_t p, int64_t q,
                   const double *Lambda, const double *Theta, double *G_Lambda,
                   double *G_Theta, void *stream);
+
+/* ---- request server (continuous batching on one GPU) --------------------
+ *
+ * Solves regularisation paths of many independent problems concurrently on
+ * one device.  The server owns `slots` worker threads, each with its own HIP
+ * stream (default priority), and one device pool of pool_bytes.  A submitted
+ * request waits in a queue until a slot is idle and the pool has a free
+ * block for its workspace (cggm_workspace_bytes of its shape and options);
+ * it then holds that block until its path is done, so requests that arrive
+ * while others run are admitted as slots and memory free up, and their
+ * kernels overlap on the device.  Admission is first come, first served,
+ * except that a later request that fits may pass a waiting head that does
+ * not fit, at most max_bypass times in a row for the same head.  A request's
+ * results do not depend on what else runs: the kernels are deterministic and
+ * every request has its own workspace and stream.
+ */
+typedef struct cggm_server cggm_server;
+
+typedef struct {
+    const double *X, *Y;      /* device, n x p and n x q; valid until the request
+                                 completes (cggm_server_wait returned)           */
+    int64_t n, p, q;
+    int npath;                /* >= 1 penalty pairs                               */
+    const double *lamL;       /* host, npath values (copied at submit)            */
+    const double *lamT;       /* host, npath values (copied at submit)            */
+    double tol;               /* stopping rule of cggm_solve                      */
+    int precision;            /* CGGM_PRECISION_*                                 */
+    int max_iter;             /* per path point; 0 = default                      */
+    int lambda_passes;        /* 0 = default                                      */
+    double *Lambda_out;       /* device npath x q x q, or NULL                    */
+    double *Theta_out;        /* device npath x p x q, or NULL                    */
+} cggm_request;
+
+typedef struct {
+    int status;               /* as cggm_solve_path, or the error of the request  */
+    int slot;                 /* worker that ran it                               */
+    int iters_total;          /* outer iterations over the path                   */
+    int _pad;
+    double t_submit_ms;       /* times since the server was created               */
+    double t_admit_ms;
+    double t_done_ms;
+    size_t footprint;         /* pool bytes the request held                      */
+} cggm_request_info;
+
+typedef struct {
+    int64_t submitted, completed, rejected;
+    int max_running;          /* most requests on the device at once              */
+    int _pad;
+    size_t pool_bytes;
+    size_t peak_bytes_in_use; /* most pool bytes held at once                     */
+} cggm_server_stats;
+
+/* Create a server on the current device.  slots >= 1; max_bypass >= 0.
+ * Errors: CGGM_EINVAL, CGGM_ENOMEM (the pool cannot be allocated), CGGM_EHIP. */
+int cggm_server_create(int slots, size_t pool_bytes, int max_bypass, cggm_server **out);
+
+/* Queue a request; *ticket identifies it.  Returns at once.  Errors:
+ * CGGM_EINVAL (bad sizes, NULL pointers, penalties, options), CGGM_ECAPACITY
+ * (its workspace exceeds the whole pool: it could never be admitted). */
+int cggm_server_submit(cggm_server *srv, const cggm_request *req, int64_t *ticket);
+
+/* Block until the request is done; fill *info (may be NULL) and, when not
+ * NULL, the host arrays f (npath objectives) and iters (npath counts).  Each
+ * ticket is waited for once; the request's memory on the server is released
+ * then.  Returns the request's status (or CGGM_EINVAL for an unknown ticket). */
+int cggm_server_wait(cggm_server *srv, int64_t ticket, cggm_request_info *info, double *f,
+                     int *iters);
+
+int cggm_server_stats_get(cggm_server *srv, cggm_server_stats *st);
+
+/* Finish every queued and running request, stop the workers, free the pool.
+ * Requests not yet waited for are discarded. */
+void cggm_server_destroy(cggm_server *srv);
 
 /* Static text for a status code; thread-local text of the last error. */
 const char *cggm_status_string(int status);

@@ -6,7 +6,9 @@ memory and the stream.  There is no CPU fallback: importing works without the
 library, but every call raises if ``libcggm.so`` is missing.
 
 Entry points mirror ``include/cggm.h``: :func:`cggm_solve`,
-:func:`cggm_objective`, :func:`cggm_gradient` (plus ``cggm_status_string``).
+:func:`cggm_solve_path`, :func:`cggm_objective`, :func:`cggm_gradient`, the
+request server :class:`Server` (``cggm_server_*``), plus
+``cggm_status_string`` and the workspace-size queries.
 """
 from __future__ import annotations
 
@@ -22,6 +24,7 @@ LIB_PATH = os.path.join(HERE, "libcggm.so")
 CGGM_OK, CGGM_MAXITER = 0, 1
 CGGM_PRECISION_FP64, CGGM_PRECISION_MIXED = 0, 1
 CGGM_EINVAL, CGGM_ENOTPD, CGGM_ELINESEARCH, CGGM_ENOMEM, CGGM_EHIP = -1, -2, -3, -4, -5
+CGGM_ECAPACITY = -6
 CGGM_SWEEP_TILED, CGGM_SWEEP_SEQUENTIAL = 0, 1
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -62,6 +65,30 @@ class Options(ctypes.Structure):
                 ("trace_len", ctypes.c_int), ("kstats", ctypes.POINTER(KernelStats))]
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("X", _vp), ("Y", _vp), ("n", _i64), ("p", _i64), ("q", _i64),
+                ("npath", ctypes.c_int), ("lamL", _dp), ("lamT", _dp), ("tol", ctypes.c_double),
+                ("precision", ctypes.c_int), ("max_iter", ctypes.c_int),
+                ("lambda_passes", ctypes.c_int), ("Lambda_out", _vp), ("Theta_out", _vp)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("slot", ctypes.c_int), ("iters_total", ctypes.c_int),
+                ("_pad", ctypes.c_int), ("t_submit_ms", ctypes.c_double),
+                ("t_admit_ms", ctypes.c_double), ("t_done_ms", ctypes.c_double),
+                ("footprint", ctypes.c_size_t)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("rejected", ctypes.c_int64), ("max_running", ctypes.c_int),
+                ("_pad", ctypes.c_int), ("pool_bytes", ctypes.c_size_t),
+                ("peak_bytes_in_use", ctypes.c_size_t)]
+
+
+PRECISIONS = {"fp64": CGGM_PRECISION_FP64, "mixed": CGGM_PRECISION_MIXED}
+
+
 class CggmError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{msg} (status {code})")
@@ -91,6 +118,24 @@ def load() -> ctypes.CDLL:
     lib.cggm_solve.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_double, ctypes.c_double,
                                ctypes.c_double, ctypes.POINTER(Options), ctypes.POINTER(_vp), _vp]
     lib.cggm_solve.restype = ctypes.c_int
+    lib.cggm_workspace_bytes.argtypes = [_i64, _i64, _i64, ctypes.POINTER(Options)]
+    lib.cggm_workspace_bytes.restype = ctypes.c_size_t
+    lib.cggm_solve_path.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_int, _dp, _dp,
+                                    ctypes.c_double, ctypes.POINTER(Options), ctypes.POINTER(_vp),
+                                    _vp]
+    lib.cggm_solve_path.restype = ctypes.c_int
+    lib.cggm_server_create.argtypes = [ctypes.c_int, ctypes.c_size_t, ctypes.c_int,
+                                       ctypes.POINTER(_vp)]
+    lib.cggm_server_create.restype = ctypes.c_int
+    lib.cggm_server_submit.argtypes = [_vp, ctypes.POINTER(Request), ctypes.POINTER(_i64)]
+    lib.cggm_server_submit.restype = ctypes.c_int
+    lib.cggm_server_wait.argtypes = [_vp, _i64, ctypes.POINTER(RequestInfo), _dp,
+                                     ctypes.POINTER(ctypes.c_int)]
+    lib.cggm_server_wait.restype = ctypes.c_int
+    lib.cggm_server_stats_get.argtypes = [_vp, ctypes.POINTER(ServerStats)]
+    lib.cggm_server_stats_get.restype = ctypes.c_int
+    lib.cggm_server_destroy.argtypes = [_vp]
+    lib.cggm_server_destroy.restype = None
     lib.cggm_result_info.argtypes = [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
                                      ctypes.POINTER(ctypes.c_int), _dp,
                                      ctypes.POINTER(ctypes.c_int)]
@@ -161,49 +206,31 @@ class SolveResult:
     csr: tuple | None = None
 
 
-def cggm_solve(X, Y, lam_Lambda: float, lam_Theta: float, tol: float = 1e-2, *,
-               max_iter: int = 500, max_ls: int = 30, ls_beta: float = 0.5,
-               ls_sigma: float = 1e-3, stall_iters: int = 3, sweep: int = CGGM_SWEEP_TILED,
-               tile: int = 0, lambda_passes: int = 4, precision: str = "fp64",
-               workspace_budget: int = 0,
-               warm_Lambda=None, warm_Theta=None, trace_cap: int | None = None,
-               keep_csr: bool = False, kernel_stats: bool = False,
-               stream=None) -> SolveResult:
-    """Alternating Newton CD (Algorithm 1) on device X (n x p) and Y (n x q), float64."""
-    import torch
-    lib = load()
-    n, p = X.shape
-    q = Y.shape[1]
+def _options(lib, *, max_iter, max_ls, ls_beta, ls_sigma, stall_iters, sweep, tile,
+             lambda_passes, precision, workspace_budget, warm_Lambda, warm_Theta) -> Options:
     opt = Options()
     lib.cggm_default_options(ctypes.byref(opt))
     opt.max_iter, opt.max_ls, opt.ls_beta, opt.ls_sigma = max_iter, max_ls, ls_beta, ls_sigma
     opt.stall_iters, opt.sweep, opt.tile = stall_iters, sweep, tile
     opt.lambda_passes = lambda_passes
-    opt.precision = {"fp64": CGGM_PRECISION_FP64, "mixed": CGGM_PRECISION_MIXED}[precision]
+    opt.precision = PRECISIONS[precision]
     opt.workspace_budget = workspace_budget
     if warm_Lambda is not None:
         opt.warm_Lambda = _dev(warm_Lambda, "warm_Lambda").value
     if warm_Theta is not None:
         opt.warm_Theta = _dev(warm_Theta, "warm_Theta").value
-    cap = (max_iter + 1) if trace_cap is None else trace_cap
-    trace_buf = (TraceEntry * max(cap, 1))()
-    opt.trace = ctypes.cast(trace_buf, ctypes.POINTER(TraceEntry)) if cap > 0 else None
-    opt.trace_cap = cap
-    ks = KernelStats() if kernel_stats else None
-    if ks is not None:
-        opt.kstats = ctypes.pointer(ks)
-    res = ctypes.c_void_p()
-    code = lib.cggm_solve(_dev(X, "X"), _dev(Y, "Y"), n, p, q, float(lam_Lambda),
-                          float(lam_Theta), float(tol), ctypes.byref(opt), ctypes.byref(res),
-                          _stream(stream))
-    if not (code == CGGM_ELINESEARCH and res.value):    # that status still returns a result
-        _check(code)
+    return opt
+
+
+def _take_result(lib, res, p, q, device, keep_csr):
+    """Copy a result handle out (dense device tensors, optional host CSR) and free it."""
+    import torch
     try:
         nL, nT, it, f, st = _i64(), _i64(), ctypes.c_int(), ctypes.c_double(), ctypes.c_int()
         _check(lib.cggm_result_info(res, ctypes.byref(nL), ctypes.byref(nT), ctypes.byref(it),
                                     ctypes.byref(f), ctypes.byref(st)))
-        Lam = torch.empty((q, q), dtype=torch.float64, device=X.device)
-        Th = torch.empty((p, q), dtype=torch.float64, device=X.device)
+        Lam = torch.empty((q, q), dtype=torch.float64, device=device)
+        Th = torch.empty((p, q), dtype=torch.float64, device=device)
         _check(lib.cggm_result_dense(res, ctypes.c_void_p(Lam.data_ptr()),
                                      ctypes.c_void_p(Th.data_ptr()), 0))
         csr = None
@@ -217,19 +244,99 @@ def cggm_solve(X, Y, lam_Lambda: float, lam_Theta: float, tol: float = 1e-2, *,
             csr = ((Lr, Lc[:nL.value], Lv[:nL.value]), (Tr, Tc[:nT.value], Tv[:nT.value]))
     finally:
         lib.cggm_result_free(res)
-    trace = [{k: getattr(trace_buf[i], k) for k, _ in TraceEntry._fields_ if k != "_pad"}
-             for i in range(opt.trace_len)]
-    kst = None
+    return SolveResult(Lambda=Lam, Theta=Th, f=f.value, iters=it.value, status=st.value,
+                       nnz_Lambda=nL.value, nnz_Theta=nT.value, trace=[], csr=csr)
+
+
+def _trace_list(trace_buf, n):
+    return [{k: getattr(trace_buf[i], k) for k, _ in TraceEntry._fields_ if k != "_pad"}
+            for i in range(n)]
+
+
+def cggm_solve(X, Y, lam_Lambda: float, lam_Theta: float, tol: float = 1e-2, *,
+               max_iter: int = 500, max_ls: int = 30, ls_beta: float = 0.5,
+               ls_sigma: float = 1e-3, stall_iters: int = 3, sweep: int = CGGM_SWEEP_TILED,
+               tile: int = 0, lambda_passes: int = 4, precision: str = "fp64",
+               workspace_budget: int = 0,
+               warm_Lambda=None, warm_Theta=None, trace_cap: int | None = None,
+               keep_csr: bool = False, kernel_stats: bool = False,
+               stream=None) -> SolveResult:
+    """Alternating Newton CD (Algorithm 1) on device X (n x p) and Y (n x q), float64."""
+    lib = load()
+    n, p = X.shape
+    q = Y.shape[1]
+    opt = _options(lib, max_iter=max_iter, max_ls=max_ls, ls_beta=ls_beta, ls_sigma=ls_sigma,
+                   stall_iters=stall_iters, sweep=sweep, tile=tile,
+                   lambda_passes=lambda_passes, precision=precision,
+                   workspace_budget=workspace_budget, warm_Lambda=warm_Lambda,
+                   warm_Theta=warm_Theta)
+    cap = (max_iter + 1) if trace_cap is None else trace_cap
+    trace_buf = (TraceEntry * max(cap, 1))()
+    opt.trace = ctypes.cast(trace_buf, ctypes.POINTER(TraceEntry)) if cap > 0 else None
+    opt.trace_cap = cap
+    ks = KernelStats() if kernel_stats else None
+    if ks is not None:
+        opt.kstats = ctypes.pointer(ks)
+    res = ctypes.c_void_p()
+    code = lib.cggm_solve(_dev(X, "X"), _dev(Y, "Y"), n, p, q, float(lam_Lambda),
+                          float(lam_Theta), float(tol), ctypes.byref(opt), ctypes.byref(res),
+                          _stream(stream))
+    if not (code == CGGM_ELINESEARCH and res.value):    # that status still returns a result
+        _check(code)
+    out = _take_result(lib, res, p, q, X.device, keep_csr)
+    out.trace = _trace_list(trace_buf, opt.trace_len)
     if ks is not None:
         kst = {}
-        for k, sweep in enumerate(("lambda", "theta")):
+        for k, sw in enumerate(("lambda", "theta")):
             for j, stage in enumerate(STAGES):
-                kst[f"{sweep}_{stage}"] = {"launches": ks.waves[k], "tiles": ks.tiles[k],
-                                           "ms": ks.ms[k][j], "bytes": ks.bytes[k][j],
-                                           "flops": ks.flops[k][j]}
-    return SolveResult(Lambda=Lam, Theta=Th, f=f.value, iters=it.value, status=st.value,
-                       nnz_Lambda=nL.value, nnz_Theta=nT.value, trace=trace, csr=csr,
-                       kernel_stats=kst)
+                kst[f"{sw}_{stage}"] = {"launches": ks.waves[k], "tiles": ks.tiles[k],
+                                        "ms": ks.ms[k][j], "bytes": ks.bytes[k][j],
+                                        "flops": ks.flops[k][j]}
+        out.kernel_stats = kst
+    return out
+
+
+def cggm_solve_path(X, Y, lam_Lambda, lam_Theta, tol: float = 1e-2, *,
+                    max_iter: int = 500, max_ls: int = 30, ls_beta: float = 0.5,
+                    ls_sigma: float = 1e-3, stall_iters: int = 3,
+                    sweep: int = CGGM_SWEEP_TILED, tile: int = 0, lambda_passes: int = 4,
+                    precision: str = "fp64", workspace_budget: int = 0, warm_Lambda=None,
+                    warm_Theta=None, trace_cap: int | None = None, keep_csr: bool = False,
+                    stream=None) -> list:
+    """Warm-started regularisation path: one SolveResult per (lam_Lambda[k], lam_Theta[k])."""
+    lib = load()
+    n, p = X.shape
+    q = Y.shape[1]
+    lamL = np.ascontiguousarray(lam_Lambda, dtype=np.float64).ravel()
+    lamT = np.ascontiguousarray(lam_Theta, dtype=np.float64).ravel()
+    if lamL.size != lamT.size or lamL.size < 1:
+        raise ValueError("lam_Lambda and lam_Theta must have the same length >= 1")
+    npath = lamL.size
+    opt = _options(lib, max_iter=max_iter, max_ls=max_ls, ls_beta=ls_beta, ls_sigma=ls_sigma,
+                   stall_iters=stall_iters, sweep=sweep, tile=tile,
+                   lambda_passes=lambda_passes, precision=precision,
+                   workspace_budget=workspace_budget, warm_Lambda=warm_Lambda,
+                   warm_Theta=warm_Theta)
+    cap = npath * (max_iter + 1) if trace_cap is None else trace_cap
+    trace_buf = (TraceEntry * max(cap, 1))()
+    opt.trace = ctypes.cast(trace_buf, ctypes.POINTER(TraceEntry)) if cap > 0 else None
+    opt.trace_cap = cap
+    res = (ctypes.c_void_p * npath)()
+    code = lib.cggm_solve_path(_dev(X, "X"), _dev(Y, "Y"), n, p, q, npath,
+                               lamL.ctypes.data_as(_dp), lamT.ctypes.data_as(_dp), float(tol),
+                               ctypes.byref(opt), res, _stream(stream))
+    if not (code == CGGM_ELINESEARCH and res[0]):
+        _check(code)
+    outs = [_take_result(lib, ctypes.c_void_p(res[k]), p, q, X.device, keep_csr)
+            for k in range(npath)]
+    trace = _trace_list(trace_buf, opt.trace_len)
+    k = -1
+    for rec in trace:                       # records of point k start at iter 0
+        if rec["iter"] == 0:
+            k += 1
+        if 0 <= k < npath:
+            outs[k].trace.append(rec)
+    return outs
 
 
 def cggm_objective(X, Y, Lambda, Theta, lam_Lambda: float, lam_Theta: float,
@@ -261,3 +368,89 @@ def cggm_gradient(X, Y, Lambda, Theta, stream=None):
 
 def cggm_solve_workspace_bytes(n: int, p: int, q: int) -> int:
     return int(load().cggm_solve_workspace_bytes(n, p, q))
+
+
+def cggm_workspace_bytes(n: int, p: int, q: int, precision: str = "fp64") -> int:
+    lib = load()
+    opt = Options()
+    lib.cggm_default_options(ctypes.byref(opt))
+    opt.precision = PRECISIONS[precision]
+    return int(lib.cggm_workspace_bytes(n, p, q, ctypes.byref(opt)))
+
+
+class Server:
+    """Continuous-batching request server (``cggm_server_*``): regularisation
+    paths of independent problems solved concurrently on the current device,
+    admitted as worker slots and pool memory free up."""
+
+    def __init__(self, slots: int = 4, pool_bytes: int | None = None, max_bypass: int = 8):
+        import torch
+        self._lib = load()
+        if pool_bytes is None:
+            free, _ = torch.cuda.mem_get_info()
+            pool_bytes = int(free * 0.5)
+        h = ctypes.c_void_p()
+        _check(self._lib.cggm_server_create(int(slots), int(pool_bytes), int(max_bypass),
+                                            ctypes.byref(h)))
+        self._h = h
+        self._held = {}         # ticket -> objects the device work reads or writes
+
+    def submit(self, X, Y, lam_Lambda, lam_Theta, tol: float = 1e-2, *,
+               precision: str = "fp64", max_iter: int = 0, lambda_passes: int = 0,
+               Lambda_out=None, Theta_out=None) -> int:
+        n, p = X.shape
+        q = Y.shape[1]
+        lamL = np.ascontiguousarray(lam_Lambda, dtype=np.float64).ravel()
+        lamT = np.ascontiguousarray(lam_Theta, dtype=np.float64).ravel()
+        if lamL.size != lamT.size:
+            raise ValueError("lam_Lambda and lam_Theta must have the same length")
+        npath = lamL.size
+        r = Request()
+        r.X, r.Y = _dev(X, "X").value, _dev(Y, "Y").value
+        r.n, r.p, r.q, r.npath = n, p, q, npath
+        r.lamL, r.lamT = lamL.ctypes.data_as(_dp), lamT.ctypes.data_as(_dp)
+        r.tol, r.precision = float(tol), PRECISIONS[precision]
+        r.max_iter, r.lambda_passes = int(max_iter), int(lambda_passes)
+        for t, name, shape in ((Lambda_out, "Lambda_out", (npath, q, q)),
+                               (Theta_out, "Theta_out", (npath, p, q))):
+            if t is not None and tuple(t.shape) != shape:
+                raise ValueError(f"{name} must have shape {shape}")
+        r.Lambda_out = _dev(Lambda_out, "Lambda_out").value if Lambda_out is not None else None
+        r.Theta_out = _dev(Theta_out, "Theta_out").value if Theta_out is not None else None
+        ticket = _i64()
+        _check(self._lib.cggm_server_submit(self._h, ctypes.byref(r), ctypes.byref(ticket)))
+        self._held[ticket.value] = (X, Y, Lambda_out, Theta_out, npath)
+        return ticket.value
+
+    def wait(self, ticket: int) -> dict:
+        npath = self._held[ticket][4]
+        info = RequestInfo()
+        f = np.zeros(npath, np.float64)
+        it = np.zeros(npath, np.int32)
+        code = self._lib.cggm_server_wait(self._h, int(ticket), ctypes.byref(info),
+                                          f.ctypes.data_as(_dp),
+                                          it.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+        self._held.pop(ticket, None)
+        if code != CGGM_ELINESEARCH:
+            _check(code)
+        return {"status": info.status, "slot": info.slot, "iters_total": info.iters_total,
+                "t_submit_ms": info.t_submit_ms, "t_admit_ms": info.t_admit_ms,
+                "t_done_ms": info.t_done_ms, "footprint": int(info.footprint),
+                "f": f.tolist(), "iters": it.tolist()}
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(self._lib.cggm_server_stats_get(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_ if k != "_pad"}
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            self._lib.cggm_server_destroy(self._h)
+        self._h = None
+        self._held.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

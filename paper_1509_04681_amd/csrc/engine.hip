@@ -16,6 +16,7 @@
 
 #include "device_common.hpp"
 #include "internal.hpp"
+#include "solver.hpp"
 
 namespace cggm {
 namespace {
@@ -356,8 +357,6 @@ TopStats read_top(Ctx &c, bool with_gradient_stats) {
     return t;
 }
 
-// HIP-event timing of the kernels of one sweep kind: four events per wave
-// (before the snapshot, Gauss-Seidel and update kernels, and after the update).
 // Optional per-stage kernel timing of the CD sweeps: intervals between pairs
 // of events recorded on the stream a stage runs on, summed per stage
 // (0 snapshot, 1 Gauss-Seidel, 2 update) when the events are done.
@@ -428,8 +427,6 @@ void run_theta_sweep(Ctx &c, const Schedule &sch, KernelTimer *kt = nullptr) {
     }
 }
 
-// One CD pass over S_Lambda for the Newton direction; D and U start at zero
-// on the first pass and carry over to further passes (pass > 0).
 // One CD pass over S_Lambda for the Newton direction; D and U start at zero
 // on the first pass and carry over to further passes (pass > 0).
 void run_lambda_sweep(Ctx &c, const Schedule &sch, KernelTimer *kt = nullptr, int pass = 0) {
@@ -514,13 +511,7 @@ std::pair<int, int> tile_edges(int tile) {
 }
 
 // ------------------------------------------------------------------ solve ----
-int solve_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q, double lamL,
-               double lamT, double tol, cggm_options *opt_in, cggm_result **out,
-               hipStream_t s) {
-    if (!X || !Y || !out) fail(CGGM_EINVAL, "NULL pointer argument");
-    check_sizes(n, p, q);
-    check_lambda(lamL, lamT);
-    if (!(tol >= 0.0) || !isfinite(tol)) fail(CGGM_EINVAL, "tol must be finite and >= 0");
+cggm_options checked_options(const cggm_options *opt_in) {
     cggm_options opt;
     cggm_default_options(&opt);
     if (opt_in) opt = *opt_in;
@@ -530,117 +521,171 @@ int solve_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q
         (opt.precision != CGGM_PRECISION_FP64 && opt.precision != CGGM_PRECISION_MIXED) ||
         (opt.sweep != CGGM_SWEEP_TILED && opt.sweep != CGGM_SWEEP_SEQUENTIAL))
         fail(CGGM_EINVAL, "invalid options");
-    const bool mixed = opt.precision == CGGM_PRECISION_MIXED;
-    const auto [tileL, tileT] = tile_edges(opt.tile);
-    const bool seq = opt.sweep == CGGM_SWEEP_SEQUENTIAL;
-    const Schedule th_sched = theta_schedule(p, q, tileT, seq);
-    const Schedule la_sched = lambda_schedule(q, tileL, seq);
-    // Tile-sequential fallbacks of the descent guard: one tile per wave.
-    Schedule th_safe, la_safe;
-    th_safe.wave_start.push_back(0);
-    for (const TileRect &r : th_sched.rects) {
-        th_safe.rects.push_back(r);
-        th_safe.finish_wave();
-    }
-    la_safe.wave_start.push_back(0);
-    for (const TileRect &r : la_sched.rects) {
-        la_safe.rects.push_back(r);
-        la_safe.finish_wave();
-    }
-    const int max_tiles = std::max(1, std::max(th_sched.max_wave, la_sched.max_wave));
+    return opt;
+}
 
-    Arena sizer;
-    sizer.measure = true;
+}  // namespace
+
+struct Solver::Impl {
+    int64_t n, p, q;
+    cggm_options opt;
+    bool mixed, seq;
+    hipStream_t s;
+    Schedule th_sched, la_sched, th_safe, la_safe;   // *_safe: one tile per wave
+    int max_tiles = 1;
+    size_t bytes = 0;
+    DeviceBuffer own;
     Work w;
-    layout(sizer, w, n, p, q, (int64_t)th_sched.rects.size(), (int64_t)la_sched.rects.size(),
-           max_tiles, mixed);
-    if (opt.workspace_budget && sizer.used > opt.workspace_budget)
-        fail(CGGM_ENOMEM, "workspace of " + std::to_string(sizer.used) +
-                              " bytes exceeds the budget of " +
-                              std::to_string(opt.workspace_budget));
-    DeviceBuffer buf;
-    if (hipMalloc(&buf.p, sizer.used) != hipSuccess) {
-        (void)hipGetLastError();
-        fail(CGGM_ENOMEM, "hipMalloc of " + std::to_string(sizer.used) + " bytes failed");
+    const double *X = nullptr;
+    KernelTimer kt_lambda, kt_theta;
+    hipEvent_t ev[5] = {};
+    std::chrono::steady_clock::time_point t0;
+    int trace_len = 0;
+    bool loaded = false, started = false;
+
+    Impl(int64_t n_, int64_t p_, int64_t q_, const cggm_options *o, hipStream_t st)
+        : n(n_), p(p_), q(q_), opt(checked_options(o)), s(st) {
+        check_sizes(n, p, q);
+        mixed = opt.precision == CGGM_PRECISION_MIXED;
+        seq = opt.sweep == CGGM_SWEEP_SEQUENTIAL;
+        const auto [tileL, tileT] = tile_edges(opt.tile);
+        th_sched = theta_schedule(p, q, tileT, seq);
+        la_sched = lambda_schedule(q, tileL, seq);
+        for (auto [src, dst] : {std::pair<Schedule *, Schedule *>{&th_sched, &th_safe},
+                                std::pair<Schedule *, Schedule *>{&la_sched, &la_safe}}) {
+            dst->wave_start.push_back(0);
+            for (const TileRect &r : src->rects) {
+                dst->rects.push_back(r);
+                dst->finish_wave();
+            }
+        }
+        max_tiles = std::max(1, std::max(th_sched.max_wave, la_sched.max_wave));
+        Arena sizer;
+        sizer.measure = true;
+        lay(sizer);
+        bytes = sizer.used;
     }
-    Arena arena;
-    arena.base = (char *)buf.p;
-    layout(arena, w, n, p, q, (int64_t)th_sched.rects.size(), (int64_t)la_sched.rects.size(),
-           max_tiles, mixed);
-    CGGM_HIP(hipMemcpyAsync(w.rects_theta, th_sched.rects.data(),
-                            sizeof(TileRect) * th_sched.rects.size(), hipMemcpyHostToDevice, s));
-    CGGM_HIP(hipMemcpyAsync(w.rects_lambda, la_sched.rects.data(),
-                            sizeof(TileRect) * la_sched.rects.size(), hipMemcpyHostToDevice, s));
+    ~Impl() {
+        for (auto e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+    void lay(Arena &a) {
+        layout(a, w, n, p, q, (int64_t)th_sched.rects.size(), (int64_t)la_sched.rects.size(),
+               max_tiles, mixed);
+    }
+    double ms_since(std::chrono::steady_clock::time_point a) const {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - a)
+            .count();
+    }
+    void bind(void *base) {
+        if (!base) fail(CGGM_EINVAL, "NULL workspace");
+        Arena arena;
+        arena.base = (char *)base;
+        lay(arena);
+        CGGM_HIP(hipMemcpyAsync(w.rects_theta, th_sched.rects.data(),
+                                sizeof(TileRect) * th_sched.rects.size(), hipMemcpyHostToDevice,
+                                s));
+        CGGM_HIP(hipMemcpyAsync(w.rects_lambda, la_sched.rects.data(),
+                                sizeof(TileRect) * la_sched.rects.size(), hipMemcpyHostToDevice,
+                                s));
+        // The host vectors are read by the copies above; they live as long as
+        // the solver, and load() synchronises the stream before returning.
+        for (auto &e : ev) CGGM_HIP(hipEventCreate(&e));
+    }
+    void allocate() {
+        if (opt.workspace_budget && bytes > opt.workspace_budget)
+            fail(CGGM_ENOMEM, "workspace of " + std::to_string(bytes) +
+                                  " bytes exceeds the budget of " +
+                                  std::to_string(opt.workspace_budget));
+        if (hipMalloc(&own.p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            own.p = nullptr;
+            fail(CGGM_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+        }
+        bind(own.p);
+    }
+    void load(const double *X_, const double *Y) {
+        if (!X_ || !Y) fail(CGGM_EINVAL, "NULL pointer argument");
+        X = X_;
+        Ctx c{s, w, 0.0, 0.0, mixed};
+        check_finite(c, X, Y);                 // synchronises the stream
+        if (opt.kstats) {
+            fill(s, 16, 0.0, reinterpret_cast<double *>(w.kctr));   // all-zero bits
+            kt_lambda.init(w.kctr);
+            kt_theta.init(w.kctr + 8);
+        }
+        t0 = std::chrono::steady_clock::now();
+        statistics(c, X, Y);
+        loaded = true;
+    }
+    void start() {
+        if (!loaded) fail(CGGM_EINVAL, "start before load");
+        const int64_t qq = q * q, pq = p * q;
+        Ctx c{s, w, 0.0, 0.0, mixed};
+        // Algorithm 1: Theta = 0, Lambda = I (or the warm start).
+        if (opt.warm_Lambda) {
+            CGGM_HIP(hipMemcpyAsync(w.Lam, opt.warm_Lambda, sizeof(double) * qq,
+                                    hipMemcpyDeviceToDevice, s));
+        } else {
+            set_identity(s, q, w.Lam);
+        }
+        if (opt.warm_Theta) {
+            CGGM_HIP(hipMemcpyAsync(w.Th, opt.warm_Theta, sizeof(double) * pq,
+                                    hipMemcpyDeviceToDevice, s));
+        } else {
+            fill(s, pq, 0.0, w.Th);
+        }
+        CGGM_HIP(hipMemcpyAsync(w.L, w.Lam, sizeof(double) * qq, hipMemcpyDeviceToDevice, s));
+        set_int(s, w.flag, 0);
+        cholesky_inplace(s, q, w.L, w.flag, w.Wd);
+        int hflag = 0;
+        CGGM_HIP(hipMemcpyAsync(&hflag, w.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        CGGM_HIP(hipStreamSynchronize(s));
+        if (hflag) fail(CGGM_ENOTPD, "the warm-start Lambda is not positive definite");
+        spd_inverse_from_cholesky(s, q, w.L, w.Wd, w.U, w.Sig);
+        theta_products(c, X);
+        started = true;
+    }
+    SolveOutcome run(double lamL, double lamT, double tol);
+};
+
+// Algorithm 1 from the current iterate (Lambda, its factor L, Sigma, Theta,
+// A = X Theta and R = A Sigma all current) to the stopping rule.  On return
+// the same quantities are current for the returned iterate.
+SolveOutcome Solver::Impl::run(double lamL, double lamT, double tol) {
+    if (!started) fail(CGGM_EINVAL, "run before start");
+    check_lambda(lamL, lamT);
+    if (!(tol >= 0.0) || !isfinite(tol)) fail(CGGM_EINVAL, "tol must be finite and >= 0");
     Ctx c{s, w, lamL, lamT, mixed};
     // The Theta descent guard compares FP64 objectives; in mixed mode V carries
     // the error of the split-BF16 product, so the sweep is exact only to about
     // that level and the guard allows a correspondingly larger increase.
     const double theta_guard = mixed ? 1e-10 : F_ROUNDING;
     const int64_t qq = q * q, pq = p * q;
-    check_finite(c, X, Y);
-    KernelTimer kt_lambda, kt_theta;
-    if (opt.kstats) {
-        fill(s, 16, 0.0, reinterpret_cast<double *>(w.kctr));   // all-zero bits
-        kt_lambda.init(w.kctr);
-        kt_theta.init(w.kctr + 8);
-    }
-
-    auto t0 = std::chrono::steady_clock::now();
-    auto ms_since = [&](std::chrono::steady_clock::time_point a) {
-        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - a)
-            .count();
-    };
-
-    statistics(c, X, Y);
-    // Algorithm 1: Theta = 0, Lambda = I (or the warm start).
-    if (opt.warm_Lambda) {
-        CGGM_HIP(hipMemcpyAsync(w.Lam, opt.warm_Lambda, sizeof(double) * qq,
-                                hipMemcpyDeviceToDevice, s));
-    } else {
-        set_identity(s, q, w.Lam);
-    }
-    if (opt.warm_Theta) {
-        CGGM_HIP(hipMemcpyAsync(w.Th, opt.warm_Theta, sizeof(double) * pq,
-                                hipMemcpyDeviceToDevice, s));
-    } else {
-        fill(s, pq, 0.0, w.Th);
-    }
-    CGGM_HIP(hipMemcpyAsync(w.L, w.Lam, sizeof(double) * qq, hipMemcpyDeviceToDevice, s));
-    set_int(s, w.flag, 0);
-    cholesky_inplace(s, q, w.L, w.flag, w.Wd);
-    reduce_logdet(s, q, w.L, w.partials, w.scal + S_LOGDET);
-    int hflag = 0;
-    CGGM_HIP(hipMemcpyAsync(&hflag, w.flag, sizeof(int), hipMemcpyDeviceToHost, s));
-    CGGM_HIP(hipStreamSynchronize(s));
-    if (hflag) fail(CGGM_ENOTPD, "the warm-start Lambda is not positive definite");
-    spd_inverse_from_cholesky(s, q, w.L, w.Wd, w.U, w.Sig);
-    theta_products(c, X);
-
-    hipEvent_t ev[5];
-    for (auto &e : ev) CGGM_HIP(hipEventCreate(&e));
-    struct EvGuard {
-        hipEvent_t *e;
-        ~EvGuard() {
-            for (int k = 0; k < 5; ++k) (void)hipEventDestroy(e[k]);
-        }
-    } evg{ev};
 
     int status = CGGM_MAXITER, stalled = 0, t = 0, ls_fail_streak = 0;
     double sg_best = INFINITY, f_prev = INFINITY, f_after_ls = INFINITY;
     bool have_phase = false;
-    int trace_len = 0, last_trials = 0, last_fallbacks = 0;
+    const int trace_first = trace_len;
+    int last_trials = 0, last_fallbacks = 0;
     double last_alpha = 0.0;
     TopStats top{};
     for (t = 0;; ++t) {
         CGGM_HIP(hipEventRecord(ev[0], s));
-        // ---- top of the iteration: objective (A, R already current) --------
-        reduce_dot(s, w.n * q, w.A, w.R, w.partials, w.scal + S_AR);
-        reduce_top_stats(s, p, q, w.Sxy, w.Sxy, w.Th, lamT, 0, w.partials, w.scal + S_THETA);
-        reduce_top_stats(s, q, q, w.Syy, w.Syy, w.Lam, lamL, 1, w.partials, w.scal + S_LAM);
+        // ---- top of the iteration: objective, gradients, screen, stopping
+        // statistics (A, R already current), read back in one transfer ------
+        auto evaluate = [&] {
+            reduce_dot(s, w.n * q, w.A, w.R, w.partials, w.scal + S_AR);
+            gradients(c, X);
+            reduce_top_stats(s, p, q, w.Sxy, w.GT, w.Th, lamT, 0, w.partials, w.scal + S_THETA);
+            reduce_top_stats(s, q, q, w.Syy, w.GL, w.Lam, lamL, 1, w.partials, w.scal + S_LAM);
+        };
         reduce_logdet(s, q, w.L, w.partials, w.scal + S_LOGDET);
-        TopStats pre = read_top(c, false);
+        evaluate();
+        CGGM_HIP(hipEventRecord(ev[1], s));
+        top = read_top(c, true);
         kt_theta.collect();                       // the last Theta sweep is done
-        if (t > 0 && pre.f > f_after_ls + theta_guard * std::max(1.0, fabs(f_after_ls))) {
+        if (t > 0 && top.f > f_after_ls + theta_guard * std::max(1.0, fabs(f_after_ls))) {
             // Descent guard: the concurrent tiles of the Theta sweep raised f.
             // Redo the sweep one tile per wave (exact block Gauss-Seidel).
             CGGM_HIP(hipMemcpyAsync(w.Th, w.ThOld, sizeof(double) * pq, hipMemcpyDeviceToDevice,
@@ -649,15 +694,10 @@ int solve_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q
             run_theta_sweep(c, th_safe);
             ++last_fallbacks;
             theta_products(c, X);
-            reduce_dot(s, w.n * q, w.A, w.R, w.partials, w.scal + S_AR);
-            reduce_top_stats(s, p, q, w.Sxy, w.Sxy, w.Th, lamT, 0, w.partials,
-                             w.scal + S_THETA);
+            evaluate();
+            CGGM_HIP(hipEventRecord(ev[1], s));
+            top = read_top(c, true);
         }
-        gradients(c, X);
-        reduce_top_stats(s, p, q, w.Sxy, w.GT, w.Th, lamT, 0, w.partials, w.scal + S_THETA);
-        reduce_top_stats(s, q, q, w.Syy, w.GL, w.Lam, lamL, 1, w.partials, w.scal + S_LAM);
-        CGGM_HIP(hipEventRecord(ev[1], s));
-        top = read_top(c, true);
         if (opt.trace && trace_len < opt.trace_cap) {
             cggm_trace_entry &te = opt.trace[trace_len++];
             memset(&te, 0, sizeof(te));
@@ -673,7 +713,7 @@ int solve_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q
             float ms = 0.f;
             CGGM_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
             te.ms_gradient = ms;
-            if (t > 0 && trace_len >= 2) {
+            if (t > 0 && trace_len - trace_first >= 2) {
                 cggm_trace_entry &pv = opt.trace[trace_len - 2];
                 pv.alpha = last_alpha;
                 pv.ls_trials = last_trials;
@@ -709,11 +749,12 @@ int solve_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q
             break;
         }
 
-        // ---- Lambda: Newton direction by one CD pass, Armijo line search ----
+        // ---- Lambda: Newton direction by CD passes, Armijo line search -----
         CGGM_HIP(hipEventRecord(ev[2], s));
         for (int pass = 0; pass < opt.lambda_passes; ++pass) {
             run_lambda_sweep(c, la_sched, &kt_lambda, pass);
-            if (pass + 1 < opt.lambda_passes) {
+            if (pass + 1 < opt.lambda_passes && kt_lambda.on()) {
+                // recycle the timing events of this pass
                 CGGM_HIP(hipStreamSynchronize(s));
                 kt_lambda.collect();
             }
@@ -726,8 +767,8 @@ int solve_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q
         double delta = hd[0] + lamL * hd[1];
         if (!(delta < 0.0) && !seq) {
             // Descent guard: redo the direction one tile per wave.
-            for (int pass = 0; pass < opt.lambda_passes; ++pass) run_lambda_sweep(c, la_safe,
-                                                                                  nullptr, pass);
+            for (int pass = 0; pass < opt.lambda_passes; ++pass)
+                run_lambda_sweep(c, la_safe, nullptr, pass);
             ++last_fallbacks;
             reduce_direction(s, q, w.GL, w.Lam, w.D, w.partials, w.scal + S_DIR);
             CGGM_HIP(hipMemcpyAsync(hd, w.scal + S_DIR, sizeof(hd), hipMemcpyDeviceToHost, s));
@@ -795,40 +836,131 @@ int solve_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q
         run_theta_sweep(c, th_sched, &kt_theta);
         theta_products(c, X);
     }
-    opt.trace_len = trace_len;
-    if (opt.kstats) {
-        CGGM_HIP(hipStreamSynchronize(s));
-        kt_theta.collect();
-        unsigned long long h[16];
-        CGGM_HIP(hipMemcpy(h, w.kctr, sizeof(h), hipMemcpyDeviceToHost));
-        cggm_kernel_stats &ks = *opt.kstats;
-        const KernelTimer *kts[2] = {&kt_lambda, &kt_theta};
-        for (int k = 0; k < 2; ++k) {
-            ks.waves[k] = kts[k]->waves;
-            ks.tiles[k] = (int64_t)h[8 * k];
-            for (int j = 0; j < 3; ++j) {
-                ks.ms[k][j] = kts[k]->ms[j];
-                ks.bytes[k][j] = (double)h[8 * k + 1 + 2 * j];
-                ks.flops[k][j] = (double)h[8 * k + 2 + 2 * j];
-            }
-        }
-    }
-    if (opt_in) opt_in->trace_len = trace_len;
+    SolveOutcome o;
+    o.status = status;
+    o.iters = t;
+    o.f = top.f;
+    return o;
+}
 
+Solver::Solver(int64_t n, int64_t p, int64_t q, const cggm_options *opt, hipStream_t s)
+    : impl_(new Impl(n, p, q, opt, s)) {}
+Solver::~Solver() = default;
+size_t Solver::footprint() const { return impl_->bytes; }
+void Solver::allocate() { impl_->allocate(); }
+void Solver::bind(void *base) { impl_->bind(base); }
+void Solver::load(const double *X, const double *Y) { impl_->load(X, Y); }
+void Solver::start() { impl_->start(); }
+SolveOutcome Solver::run(double lamL, double lamT, double tol) {
+    return impl_->run(lamL, lamT, tol);
+}
+int Solver::trace_len() const { return impl_->trace_len; }
+
+void Solver::copy_dense(double *Lambda, double *Theta) {
+    Impl &m = *impl_;
+    if (Lambda)
+        CGGM_HIP(hipMemcpyAsync(Lambda, m.w.Lam, sizeof(double) * m.q * m.q,
+                                hipMemcpyDeviceToDevice, m.s));
+    if (Theta)
+        CGGM_HIP(hipMemcpyAsync(Theta, m.w.Th, sizeof(double) * m.p * m.q,
+                                hipMemcpyDeviceToDevice, m.s));
+}
+
+cggm_result *Solver::make_result(const SolveOutcome &o) {
+    Impl &m = *impl_;
+    const int64_t qq = m.q * m.q, pq = m.p * m.q;
     auto *res = new ResultImpl();
     std::unique_ptr<ResultImpl> guard(res);
-    res->p = p;
-    res->q = q;
-    res->iters = t;
-    res->f = top.f;
-    res->status = status;
+    res->p = m.p;
+    res->q = m.q;
+    res->iters = o.iters;
+    res->f = o.f;
+    res->status = o.status;
     CGGM_HIP(hipMalloc(&res->Lam, sizeof(double) * qq));
     CGGM_HIP(hipMalloc(&res->Th, sizeof(double) * pq));
-    CGGM_HIP(hipMemcpyAsync(res->Lam, w.Lam, sizeof(double) * qq, hipMemcpyDeviceToDevice, s));
-    CGGM_HIP(hipMemcpyAsync(res->Th, w.Th, sizeof(double) * pq, hipMemcpyDeviceToDevice, s));
-    to_csr(s, q, q, res->Lam, &res->L_rowptr, &res->L_col, &res->L_val, &res->nnzL);
-    to_csr(s, p, q, res->Th, &res->T_rowptr, &res->T_col, &res->T_val, &res->nnzT);
-    *out = reinterpret_cast<cggm_result *>(guard.release());
+    copy_dense(res->Lam, res->Th);
+    to_csr(m.s, m.q, m.q, res->Lam, &res->L_rowptr, &res->L_col, &res->L_val, &res->nnzL);
+    to_csr(m.s, m.p, m.q, res->Th, &res->T_rowptr, &res->T_col, &res->T_val, &res->nnzT);
+    return reinterpret_cast<cggm_result *>(guard.release());
+}
+
+void Solver::finish_kernel_stats() {
+    Impl &m = *impl_;
+    if (!m.opt.kstats) return;
+    CGGM_HIP(hipStreamSynchronize(m.s));
+    m.kt_theta.collect();
+    unsigned long long h[16];
+    CGGM_HIP(hipMemcpyAsync(h, m.w.kctr, sizeof(h), hipMemcpyDeviceToHost, m.s));
+    CGGM_HIP(hipStreamSynchronize(m.s));
+    cggm_kernel_stats &ks = *m.opt.kstats;
+    const KernelTimer *kts[2] = {&m.kt_lambda, &m.kt_theta};
+    for (int k = 0; k < 2; ++k) {
+        ks.waves[k] = kts[k]->waves;
+        ks.tiles[k] = (int64_t)h[8 * k];
+        for (int j = 0; j < 3; ++j) {
+            ks.ms[k][j] = kts[k]->ms[j];
+            ks.bytes[k][j] = (double)h[8 * k + 1 + 2 * j];
+            ks.flops[k][j] = (double)h[8 * k + 2 + 2 * j];
+        }
+    }
+}
+
+size_t solve_footprint(int64_t n, int64_t p, int64_t q, const cggm_options *opt) {
+    Solver sv(n, p, q, opt, nullptr);
+    return sv.footprint();
+}
+
+void set_last_error(const std::string &msg) { g_last_error = msg; }
+std::string last_error_text() { return g_last_error; }
+
+int combine_status(int acc, int s) {
+    if (acc < 0) return acc;
+    if (s < 0) return s;
+    return std::max(acc, s);
+}
+
+namespace {
+
+int solve_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q, double lamL,
+               double lamT, double tol, cggm_options *opt_in, cggm_result **out,
+               hipStream_t s) {
+    if (!X || !Y || !out) fail(CGGM_EINVAL, "NULL pointer argument");
+    check_sizes(n, p, q);
+    check_lambda(lamL, lamT);
+    if (!(tol >= 0.0) || !isfinite(tol)) fail(CGGM_EINVAL, "tol must be finite and >= 0");
+    Solver sv(n, p, q, opt_in, s);
+    sv.allocate();
+    sv.load(X, Y);
+    sv.start();
+    const SolveOutcome o = sv.run(lamL, lamT, tol);
+    sv.finish_kernel_stats();
+    if (opt_in) opt_in->trace_len = sv.trace_len();
+    *out = sv.make_result(o);
+    return o.status;
+}
+
+int solve_path_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q,
+                    int npath, const double *lamL, const double *lamT, double tol,
+                    cggm_options *opt_in, cggm_result **out, hipStream_t s) {
+    if (!X || !Y || !out || !lamL || !lamT) fail(CGGM_EINVAL, "NULL pointer argument");
+    if (npath < 1) fail(CGGM_EINVAL, "npath must be >= 1");
+    check_sizes(n, p, q);
+    for (int k = 0; k < npath; ++k) check_lambda(lamL[k], lamT[k]);
+    if (!(tol >= 0.0) || !isfinite(tol)) fail(CGGM_EINVAL, "tol must be finite and >= 0");
+    Solver sv(n, p, q, opt_in, s);
+    sv.allocate();
+    sv.load(X, Y);
+    sv.start();
+    std::vector<std::unique_ptr<ResultImpl>> res;
+    int status = CGGM_OK;
+    for (int k = 0; k < npath; ++k) {
+        const SolveOutcome o = sv.run(lamL[k], lamT[k], tol);
+        res.emplace_back(reinterpret_cast<ResultImpl *>(sv.make_result(o)));
+        status = combine_status(status, o.status);
+    }
+    sv.finish_kernel_stats();
+    if (opt_in) opt_in->trace_len = sv.trace_len();
+    for (int k = 0; k < npath; ++k) out[k] = reinterpret_cast<cggm_result *>(res[k].release());
     return status;
 }
 
@@ -943,23 +1075,6 @@ int gradient_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_
     return CGGM_OK;
 }
 
-template <class F>
-int guarded(F f) {
-    try {
-        g_last_error.clear();
-        return f();
-    } catch (const Failure &e) {
-        g_last_error = e.what();
-        return e.code;
-    } catch (const std::bad_alloc &) {
-        g_last_error = "host allocation failed";
-        return CGGM_ENOMEM;
-    } catch (const std::exception &e) {
-        g_last_error = e.what();
-        return CGGM_EHIP;
-    }
-}
-
 }  // namespace
 }  // namespace cggm
 
@@ -983,21 +1098,31 @@ void cggm_default_options(cggm_options *opt) {
 }
 
 size_t cggm_solve_workspace_bytes(int64_t n, int64_t p, int64_t q) {
-    if (n < 1 || p < 1 || q < 1) return 0;
-    const Schedule th = theta_schedule(p, q, THETA_TILE, false);
-    const Schedule la = lambda_schedule(q, LAMBDA_TILE, false);
-    Arena sizer;
-    sizer.measure = true;
-    Work w;
-    layout(sizer, w, n, p, q, (int64_t)th.rects.size(), (int64_t)la.rects.size(),
-           std::max(1, std::max(th.max_wave, la.max_wave)));
-    return sizer.used;
+    return cggm_workspace_bytes(n, p, q, nullptr);
+}
+
+size_t cggm_workspace_bytes(int64_t n, int64_t p, int64_t q, const cggm_options *opt) {
+    size_t bytes = 0;
+    const int st = guarded([&] {
+        bytes = solve_footprint(n, p, q, opt);
+        return CGGM_OK;
+    });
+    return st == CGGM_OK ? bytes : 0;
 }
 
 int cggm_solve(const double *X, const double *Y, int64_t n, int64_t p, int64_t q, double lamL,
                double lamT, double tol, cggm_options *opt, cggm_result **out, void *stream) {
     return guarded([&] {
         return solve_impl(X, Y, n, p, q, lamL, lamT, tol, opt, out, (hipStream_t)stream);
+    });
+}
+
+int cggm_solve_path(const double *X, const double *Y, int64_t n, int64_t p, int64_t q,
+                    int npath, const double *lamL, const double *lamT, double tol,
+                    cggm_options *opt, cggm_result **out, void *stream) {
+    return guarded([&] {
+        return solve_path_impl(X, Y, n, p, q, npath, lamL, lamT, tol, opt, out,
+                               (hipStream_t)stream);
     });
 }
 
@@ -1074,6 +1199,7 @@ const char *cggm_status_string(int status) {
         case CGGM_ELINESEARCH: return "line search found no Armijo step";
         case CGGM_ENOMEM: return "out of device memory or over the workspace budget";
         case CGGM_EHIP: return "HIP runtime error";
+        case CGGM_ECAPACITY: return "request larger than the server's device memory";
         default: return "unknown status";
     }
 }

@@ -289,6 +289,61 @@ def workload(name: str, seed: int | None = None) -> Problem:
     return make(**kw)
 
 
+# ---------------------------------------------------------------------------
+# Request streams (batched and served solves): problems of mixed shapes.
+#   * Lambda: the chain above, or a random sparse graph of mean degree 4
+#     (2q uniform undirected edges without repeats, weight -0.5, diagonal =
+#     the row's absolute sum + 0.25: diagonally dominant, hence positive
+#     definite);
+#   * Theta: exactly round(density p q) nonzeros, +-U[0.5, 1], as above;
+#   * X ~ N(0, I); Y | X from the model; shapes drawn uniformly from the given
+#     integer ranges; RNG order per problem: kind, p, q, n, Lambda, Theta, X,
+#     noise.  Arrival times are drawn separately by the caller.
+# ---------------------------------------------------------------------------
+def random_sparse_lambda(q: int, rng: np.random.Generator, degree: float = 4.0,
+                         weight: float = -0.5, ridge: float = 0.25) -> sp.csr_matrix:
+    m = min(int(round(degree * q / 2)), q * (q - 1) // 2)
+    edges = set()
+    while len(edges) < m:
+        i, j = rng.integers(0, q, 2)
+        if i != j:
+            edges.add((int(min(i, j)), int(max(i, j))))
+    e = np.array(sorted(edges), dtype=np.int64).reshape(-1, 2)
+    rows = np.concatenate([e[:, 0], e[:, 1]])
+    cols = np.concatenate([e[:, 1], e[:, 0]])
+    A = sp.csr_matrix((np.full(rows.size, weight), (rows, cols)), shape=(q, q))
+    diag = np.asarray(abs(A).sum(axis=1)).ravel() + ridge
+    return (A + sp.diags(diag)).tocsr()
+
+
+def stream_problem(seed: int, p_range=(100, 4000), q_range=(100, 4000),
+                   n_range=(200, 2000), density: float = 0.01) -> Problem:
+    """One problem of a request stream (chain or random-sparse Lambda, 50/50)."""
+    rng = np.random.default_rng(seed)
+    kind = "chain" if rng.random() < 0.5 else "random"
+    p = int(rng.integers(p_range[0], p_range[1] + 1))
+    q = int(rng.integers(q_range[0], q_range[1] + 1))
+    n = int(rng.integers(n_range[0], n_range[1] + 1))
+    Lam = chain_lambda(q) if kind == "chain" else random_sparse_lambda(q, rng)
+    Theta = sparse_theta(p, q, density, rng)
+    X, Y = _sample_general(Lam, Theta, n, rng)
+    return Problem(X=X, Y=Y, lam_Lambda=0.0, lam_Theta=0.0, Lambda_true=Lam, Theta_true=Theta,
+                   name=f"{kind}-p{p}-q{q}-n{n}-rho{density:g}-seed{seed}")
+
+
+def penalty_path(X: np.ndarray, Y: np.ndarray, points: int = 12, ratio: float = 0.1):
+    """Log-spaced penalty pairs from the smallest penalties with an all-zero
+    solution off the diagonal (lam_Lambda = max off-diagonal abs(Y^T Y / n),
+    lam_Theta = 2 max abs(X^T Y / n)) down to `ratio` times those."""
+    n = X.shape[0]
+    Syy = Y.T @ Y / n
+    np.fill_diagonal(Syy, 0.0)
+    lL = float(np.abs(Syy).max()) if Y.shape[1] > 1 else 1.0
+    lT = float(2.0 * np.abs(X.T @ Y / n).max())
+    g = np.geomspace(1.0, ratio, points)
+    return lL * g, lT * g
+
+
 def random_spd(q: int, rng: np.random.Generator, degree: float = 4.0,
                weight: float = -0.5, ridge: float = 0.25) -> np.ndarray:
     """Dense random sparse-pattern precision matrix: uniform random undirected edges

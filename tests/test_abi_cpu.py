@@ -40,7 +40,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 def test_status_strings(lib):
     import paper_1509_04681_amd as m
-    for code in (0, 1, -1, -2, -3, -4, -5):
+    for code in (0, 1, -1, -2, -3, -4, -5, -6):
         assert m.cggm_status_string(code) != "unknown status"
     assert m.cggm_status_string(42) == "unknown status"
 
@@ -103,3 +103,47 @@ def test_default_options(lib):
     assert opt.sweep == m.CGGM_SWEEP_TILED
     assert opt.lambda_passes == 4
     assert opt.precision == m.CGGM_PRECISION_FP64
+
+
+def test_path_and_workspace_arguments_without_device(lib):
+    import paper_1509_04681_amd as m
+    fake = ctypes.c_void_p(64)
+    lam = (ctypes.c_double * 3)(0.3, 0.2, 0.1)
+    bad = (ctypes.c_double * 3)(0.3, -0.2, 0.1)
+    out = (ctypes.c_void_p * 3)()
+    dp = ctypes.POINTER(ctypes.c_double)
+    L = ctypes.cast(lam, dp)
+    assert lib.cggm_solve_path(fake, fake, 4, 3, 2, 0, L, L, 0.01, None, out, None) \
+        == m.CGGM_EINVAL
+    assert lib.cggm_solve_path(fake, fake, 4, 3, 2, 3, None, L, 0.01, None, out, None) \
+        == m.CGGM_EINVAL
+    assert lib.cggm_solve_path(fake, fake, 4, 3, 2, 3, L, ctypes.cast(bad, dp), 0.01, None, out,
+                               None) == m.CGGM_EINVAL
+    assert lib.cggm_solve_path(fake, fake, 4, 3, 2, 3, L, L, 0.01, None, None, None) \
+        == m.CGGM_EINVAL
+    # footprints: the mixed mode adds the BF16 planes; invalid options give 0
+    fp64 = m.cggm_workspace_bytes(300, 200, 100)
+    assert fp64 == m.cggm_solve_workspace_bytes(300, 200, 100)
+    assert m.cggm_workspace_bytes(300, 200, 100, "mixed") >= fp64 + 2 * 3 * (200 + 100) * 128
+    opt = m.Options()
+    lib.cggm_default_options(ctypes.byref(opt))
+    opt.lambda_passes = 0
+    assert lib.cggm_workspace_bytes(300, 200, 100, ctypes.byref(opt)) == 0
+    assert lib.cggm_workspace_bytes(0, 200, 100, None) == 0
+
+
+def test_server_arguments_without_device(lib):
+    import paper_1509_04681_amd as m
+    h = ctypes.c_void_p()
+    assert lib.cggm_server_create(0, 1 << 20, 4, ctypes.byref(h)) == m.CGGM_EINVAL
+    assert lib.cggm_server_create(65, 1 << 20, 4, ctypes.byref(h)) == m.CGGM_EINVAL
+    assert lib.cggm_server_create(2, 100, 4, ctypes.byref(h)) == m.CGGM_EINVAL
+    assert lib.cggm_server_create(2, 1 << 20, -1, ctypes.byref(h)) == m.CGGM_EINVAL
+    assert lib.cggm_server_create(2, 1 << 20, 4, None) == m.CGGM_EINVAL
+    t = ctypes.c_int64()
+    req = m.Request()
+    assert lib.cggm_server_submit(None, ctypes.byref(req), ctypes.byref(t)) == m.CGGM_EINVAL
+    assert lib.cggm_server_wait(None, 1, None, None, None) == m.CGGM_EINVAL
+    st = m.ServerStats()
+    assert lib.cggm_server_stats_get(None, ctypes.byref(st)) == m.CGGM_EINVAL
+    lib.cggm_server_destroy(None)

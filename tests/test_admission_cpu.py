@@ -1,0 +1,21 @@
+"""Host test of the request server's device-pool allocator and admission rule
+(paper_1509_04681_amd/csrc/admission.hpp): compiled with g++ and run, no GPU."""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+def test_admission_rule(tmp_path):
+    exe = tmp_path / "admission_test"
+    subprocess.run(["g++", "-std=c++17", "-O1", "-Wall", "-Werror",
+                    "-I", os.path.join(ROOT, "paper_1509_04681_amd", "csrc"),
+                    os.path.join(ROOT, "tests", "cpp", "admission_test.cpp"), "-o", str(exe)],
+                   check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "checks passed" in r.stdout
