@@ -58,9 +58,10 @@ extern "C" {
  * MIXED: V = Theta Sigma, the product that only steers the Theta
  *   coordinate-descent pass (Sec. 3.2), is formed from three-piece BF16 splits
  *   of Theta and Sigma on the BF16 matrix cores with FP32 accumulation (about
- *   1e-6 relative error); the Cholesky factor, log det, Sigma, Psi, both
- *   gradients, the screen, the stopping rule, the objective and the line
- *   search stay FP64. */
+ *   1e-6 relative error) until the subgradient falls below 1e-4 of the
+ *   stopping scale (||Lambda||_1 + ||Theta||_1), then in FP64; the Cholesky
+ *   factor, log det, Sigma, Psi, both gradients, the screen, the stopping
+ *   rule, the objective and the line search stay FP64. */
 #define CGGM_PRECISION_FP64 0
 #define CGGM_PRECISION_MIXED 1
 

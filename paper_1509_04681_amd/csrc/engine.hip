@@ -657,10 +657,15 @@ SolveOutcome Solver::Impl::run(double lamL, double lamT, double tol) {
     check_lambda(lamL, lamT);
     if (!(tol >= 0.0) || !isfinite(tol)) fail(CGGM_EINVAL, "tol must be finite and >= 0");
     Ctx c{s, w, lamL, lamT, mixed};
-    // The Theta descent guard compares FP64 objectives; in mixed mode V carries
-    // the error of the split-BF16 product, so the sweep is exact only to about
-    // that level and the guard allows a correspondingly larger increase.
-    const double theta_guard = mixed ? 1e-10 : F_ROUNDING;
+    // Mixed mode forms V from split-BF16 products while the iterate is far
+    // from the optimum and switches to FP64 for the rest of the run once the
+    // subgradient falls below MIXED_FP64_BELOW of the stopping scale: the
+    // ~1e-6 relative error of V would otherwise bound how far the Theta sweep
+    // can reduce the subgradient.
+    constexpr double MIXED_FP64_BELOW = 1e-4;
+    // The Theta descent guard compares FP64 objectives; after a sweep steered
+    // by the split-BF16 V it allows the larger increase that error permits.
+    bool swept_mixed = c.mixed;
     const int64_t qq = q * q, pq = p * q;
 
     int status = CGGM_MAXITER, stalled = 0, t = 0, ls_fail_streak = 0;
@@ -685,6 +690,7 @@ SolveOutcome Solver::Impl::run(double lamL, double lamT, double tol) {
         CGGM_HIP(hipEventRecord(ev[1], s));
         top = read_top(c, true);
         kt_theta.collect();                       // the last Theta sweep is done
+        const double theta_guard = swept_mixed ? 1e-10 : F_ROUNDING;
         if (t > 0 && top.f > f_after_ls + theta_guard * std::max(1.0, fabs(f_after_ls))) {
             // Descent guard: the concurrent tiles of the Theta sweep raised f.
             // Redo the sweep one tile per wave (exact block Gauss-Seidel).
@@ -729,6 +735,7 @@ SolveOutcome Solver::Impl::run(double lamL, double lamT, double tol) {
             }
         }
         last_fallbacks = 0;
+        if (c.mixed && top.subgrad < MIXED_FP64_BELOW * top.l1) c.mixed = false;
         if (top.subgrad < tol * top.l1) {
             status = CGGM_OK;
             break;
@@ -832,6 +839,7 @@ SolveOutcome Solver::Impl::run(double lamL, double lamT, double tol) {
 
         // ---- Theta: one CD pass on Eq. (7) with Sigma of the new Lambda ----
         CGGM_HIP(hipMemcpyAsync(w.ThOld, w.Th, sizeof(double) * pq, hipMemcpyDeviceToDevice, s));
+        swept_mixed = c.mixed;
         theta_sigma(c);                                              // V = Theta Sigma
         run_theta_sweep(c, th_sched, &kt_theta);
         theta_products(c, X);
