@@ -55,13 +55,16 @@ extern "C" {
 
 /* ---- arithmetic ---------------------------------------------------------
  * FP64: every step in FP64.
- * MIXED: V = Theta Sigma, the product that only steers the Theta
- *   coordinate-descent pass (Sec. 3.2), is formed from three-piece BF16 splits
- *   of Theta and Sigma on the BF16 matrix cores with FP32 accumulation (about
- *   1e-6 relative error) until the subgradient falls below 1e-4 of the
- *   stopping scale (||Lambda||_1 + ||Theta||_1), then in FP64; the Cholesky
- *   factor, log det, Sigma, Psi, both gradients, the screen, the stopping
- *   rule, the objective and the line search stay FP64. */
+ * MIXED: while the subgradient is above 1e-4 of the stopping scale
+ *   (||Lambda||_1 + ||Theta||_1), the coordinate-descent sweeps (Sec. 3.1,
+ *   3.2) stream FP32 copies of Sigma, Psi, Sigma + Psi and Sxx and maintain
+ *   U = D Sigma and V = Theta Sigma in FP32, with their products on the FP32
+ *   matrix cores, and V is formed from three-piece BF16 splits of Theta and
+ *   Sigma on the BF16 matrix cores with FP32 accumulation; afterwards the
+ *   sweeps run in FP64.  The Cholesky factor, log det, Sigma, Psi, both
+ *   gradients, the screen, the stopping rule, the objective, the line search
+ *   and the coordinate updates themselves stay FP64, so the Armijo test and
+ *   the fixed point of the iteration are those of the FP64 mode. */
 #define CGGM_PRECISION_FP64 0
 #define CGGM_PRECISION_MIXED 1
 

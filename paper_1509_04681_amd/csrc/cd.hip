@@ -71,11 +71,13 @@ __global__ __launch_bounds__(BLOCK) void tile_activity_kernel(const TileRect *__
 // ----------------------------------------------------------------- snapshot --
 // Operand pairs of the snapshot products: out[m][n] += sum_k A[k][r0 + m] B[k][c0 + n]
 // (A, B symmetric or stored so that the tile's rows/columns are column slabs).
-template <int NPAIR>
+// The operands are FP64, or FP32 copies in the mixed mode (converted to FP64
+// in registers; the products accumulate in FP64).
+template <int NPAIR, class E>
 struct SnapArgs {
-    const double *A[NPAIR];
+    const E *A[NPAIR];
     int64_t lda[NPAIR];
-    const double *B[NPAIR];
+    const E *B[NPAIR];
     int64_t ldb[NPAIR];
 };
 
@@ -101,11 +103,11 @@ template <int TS>
 constexpr int snap_blocks_per_tile() {
     return (TS / SNAP_WM) * (TS / SNAP_WN);
 }
-template <int TS, int NPAIR>
+template <int TS, int NPAIR, class E>
 __global__ __launch_bounds__(WAVE) void snapshot_kernel(const TileRect *__restrict__ rects,
                                                         const int *__restrict__ active, int S,
                                                         int nrect, int64_t K,
-                                                        SnapArgs<NPAIR> args,
+                                                        SnapArgs<NPAIR, E> args,
                                                         double *__restrict__ partial) {
     constexpr int WM = SNAP_WM, WN = SNAP_WN, U = SNAP_U;
     constexpr int NBN = TS / WN, NB = (TS / WM) * NBN, MI = WM / 16, NJ = WN / 16;
@@ -136,8 +138,8 @@ __global__ __launch_bounds__(WAVE) void snapshot_kernel(const TileRect *__restri
         for (int j = 0; j < NJ; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll 1
     for (int pp = 0; pp < NPAIR; ++pp) {
-        const double *A = args.A[pp] + rc.r0 + mo;
-        const double *B = args.B[pp] + rc.c0 + no;
+        const E *A = args.A[pp] + rc.r0 + mo;
+        const E *B = args.B[pp] + rc.c0 + no;
         const int64_t lda = args.lda[pp], ldb = args.ldb[pp];
         // Two register batches: the loads of the next batch are in flight
         // while the current one is multiplied (loads past the K range are
@@ -148,9 +150,9 @@ __global__ __launch_bounds__(WAVE) void snapshot_kernel(const TileRect *__restri
         const int64_t k = ((ST0) + u) * 4 + krow;                                        \
         const bool kv = ((ST0) + u) < s1 && k < K;                                       \
         _Pragma("unroll") for (int i = 0; i < MI; ++i) a[BUF][u][i] =                    \
-            (kv && am[i]) ? A[k * lda + col + i * 16] : 0.0;                             \
+            (kv && am[i]) ? (double)A[k * lda + col + i * 16] : 0.0;                     \
         _Pragma("unroll") for (int j = 0; j < NJ; ++j) b[BUF][u][j] =                    \
-            (kv && bn[j]) ? B[k * ldb + col + j * 16] : 0.0;                             \
+            (kv && bn[j]) ? (double)B[k * ldb + col + j * 16] : 0.0;                     \
     }
 #define SNAP_MMA(BUF)                                                                    \
     _Pragma("unroll") for (int u = 0; u < U; ++u)                                        \
@@ -176,6 +178,111 @@ __global__ __launch_bounds__(WAVE) void snapshot_kernel(const TileRect *__restri
 #pragma unroll
             for (int r = 0; r < 4; ++r)
                 out[(mo + i * 16 + krow + 4 * r) * TS + no + j * 16 + col] = acc[i][j][r];
+}
+
+// ------------------------------------------------ FP32 operands (mixed mode) --
+// The mixed-mode snapshot and update read FP32 copies of the streamed
+// operands (row length a multiple of 4, padding zero) and multiply on the
+// FP32 matrix cores: v_mfma_f32_16x16x4f32, where lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16] and holds D[4 (l / 16) + r][l % 16].
+// So that a lane loads 16 (8) bytes at once, MFMA block i of a 64-row block
+// takes the rows {4 c + i} and block j of a 32-column block the columns
+// {2 c + j} (c = 0..15): one float4 (float2) load gives a lane its values for
+// all four (two) blocks.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ f32x4 mfma_f32_16x16x4(float a, float b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Up to four (two) consecutive floats from p; entries at or past `valid` are
+// zero and not read.  A full vector is read only when all of it is valid.
+__device__ __forceinline__ f32x4 load4_upto(const float *p, int valid) {
+    if (valid >= 4) return *reinterpret_cast<const f32x4 *>(p);
+    f32x4 v = {0.f, 0.f, 0.f, 0.f};
+    if (valid > 0) v[0] = p[0];
+    if (valid > 1) v[1] = p[1];
+    if (valid > 2) v[2] = p[2];
+    return v;
+}
+__device__ __forceinline__ f32x2 load2_upto(const float *p, int valid) {
+    if (valid >= 2) return *reinterpret_cast<const f32x2 *>(p);
+    f32x2 v = {0.f, 0.f};
+    if (valid > 0) v[0] = p[0];
+    return v;
+}
+
+// The snapshot of snapshot_kernel from FP32 operands (same blocks, parts and
+// XCD mapping), FP32 accumulation, FP64 partials.
+template <int TS, int NPAIR>
+__global__ __launch_bounds__(WAVE) void snapshot32_kernel(const TileRect *__restrict__ rects,
+                                                          const int *__restrict__ active, int S,
+                                                          int nrect, int64_t K,
+                                                          SnapArgs<NPAIR, float> args,
+                                                          double *__restrict__ partial) {
+    constexpr int WM = SNAP_WM, WN = SNAP_WN, U = SNAP_U;
+    static_assert(WM == 64 && WN == 32, "float4 rows and float2 columns per lane");
+    constexpr int NBN = TS / WN, NB = (TS / WM) * NBN;
+    const int64_t wg = blockIdx.x;
+    const int64_t rest = wg / NXCD;
+    const int blk = (int)(rest % NB);
+    const int64_t t = (rest / NB) * NXCD + wg % NXCD;   // (tile, part) group
+    if (t >= (int64_t)nrect * S) return;
+    const int s = (int)(t % S);
+    const int e = (int)(t / S);
+    if (!active[e]) return;
+    const TileRect rc = rects[e];
+    const int R = rc.r1 - rc.r0, C = rc.c1 - rc.c0;
+    const int mo = (blk / NBN) * WM, no = (blk % NBN) * WN;
+    if (mo >= R || no >= C) return;                  // block outside a ragged tile
+    const int lane = threadIdx.x, col = lane & 15, krow = lane >> 4;
+    const int ra = R - mo - 4 * col;                 // valid rows of this lane's float4
+    const int cb = C - no - 2 * col;                 // valid columns of its float2
+    const int64_t ksteps = (K + 3) / 4;
+    const int64_t s0 = (ksteps * s) / S, s1 = (ksteps * (s + 1)) / S;
+    f32x4 acc[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+    for (int pp = 0; pp < NPAIR; ++pp) {
+        const float *A = args.A[pp] + rc.r0 + mo + 4 * col;
+        const float *B = args.B[pp] + rc.c0 + no + 2 * col;
+        const int64_t lda = args.lda[pp], ldb = args.ldb[pp];
+        f32x4 a[2][U];
+        f32x2 b[2][U];
+#define SNAP32_LOAD(BUF, ST0)                                                            \
+    _Pragma("unroll") for (int u = 0; u < U; ++u) {                                      \
+        const int64_t k = ((ST0) + u) * 4 + krow;                                        \
+        const bool kv = ((ST0) + u) < s1 && k < K;                                       \
+        a[BUF][u] = kv ? load4_upto(A + k * lda, ra) : f32x4{0.f, 0.f, 0.f, 0.f};        \
+        b[BUF][u] = kv ? load2_upto(B + k * ldb, cb) : f32x2{0.f, 0.f};                  \
+    }
+#define SNAP32_MMA(BUF)                                                                  \
+    _Pragma("unroll") for (int u = 0; u < U; ++u)                                        \
+        _Pragma("unroll") for (int i = 0; i < 4; ++i)                                    \
+            _Pragma("unroll") for (int j = 0; j < 2; ++j)                                \
+                acc[i][j] = mfma_f32_16x16x4(a[BUF][u][i], b[BUF][u][j], acc[i][j]);
+        SNAP32_LOAD(0, s0)
+        for (int64_t st = s0; st < s1; st += 2 * U) {
+            SNAP32_LOAD(1, st + U)
+            SNAP32_MMA(0)
+            SNAP32_LOAD(0, st + 2 * U)
+            SNAP32_MMA(1)
+        }
+#undef SNAP32_LOAD
+#undef SNAP32_MMA
+    }
+    double *out = partial + ((int64_t)e * S + s) * TS * TS;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                out[(mo + 4 * (4 * krow + r) + i) * TS + no + 2 * col + j] = (double)acc[i][j][r];
 }
 
 // Sum of the S partial snapshots of every active tile, in part order
@@ -220,7 +327,8 @@ __global__ __launch_bounds__(BLOCK) void theta_gs_kernel(
     const double *__restrict__ partial, int64_t p, int64_t q, const double *__restrict__ Sxx,
     const double *__restrict__ Sxy, const double *__restrict__ Sigma,
     const double *__restrict__ GT, double *__restrict__ Theta, double lamT,
-    double *__restrict__ dT, int *__restrict__ changed, unsigned long long *__restrict__ ctr) {
+    double *__restrict__ dT, int *__restrict__ changed, unsigned long long *__restrict__ ctr,
+    int esz) {
     const int e = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
     if (!active[e]) {
@@ -245,13 +353,13 @@ __global__ __launch_bounds__(BLOCK) void theta_gs_kernel(
         const int64_t RC = (int64_t)R * C;
         atomicAdd(ctr + 0, 1ull);
         // snapshot: slabs Sxx[:, I] and V[:, J]
-        atomicAdd(ctr + 1, (unsigned long long)(8 * p * (R + C)));
+        atomicAdd(ctr + 1, (unsigned long long)(esz * p * (R + C)));
         atomicAdd(ctr + 2, (unsigned long long)(2 * RC * p));
         // Gauss-Seidel: Sxx[I, I], Sigma[J, J], Sxy / G / Theta reads, Theta and delta writes
         atomicAdd(ctr + 3, (unsigned long long)(8 * (R * R + C * C + 5 * RC)));
         atomicAdd(ctr + 4, (unsigned long long)(4 * RC * C));
         // update: Sigma[J, :] read, V[I, :] read and written
-        atomicAdd(ctr + 5, (unsigned long long)(8 * q * (C + 2 * R)));
+        atomicAdd(ctr + 5, (unsigned long long)(esz * q * (C + 2 * R)));
         atomicAdd(ctr + 6, (unsigned long long)(2 * RC * q));
     }
     __syncthreads();
@@ -345,10 +453,12 @@ __global__ __launch_bounds__(BLOCK) void theta_gs_kernel(
 // every 64-column chunk, loads its S operands straight from global memory (one
 // 128-byte row segment per k-step) and read-modify-writes Out from the MFMA
 // accumulators.  All BLOCK threads call it.
-template <int TR, int TK>
+// S and Out are FP64, or FP32 copies in the mixed mode (the products
+// accumulate in FP64 either way).
+template <int TR, int TK, class E>
 __device__ void rowblock_update(const double *__restrict__ Delta, bool trans, int R, int Kd,
-                                const double *__restrict__ S, int64_t lds,
-                                double *__restrict__ Out, int64_t ldo, int64_t c_begin,
+                                const E *__restrict__ S, int64_t lds,
+                                E *__restrict__ Out, int64_t ldo, int64_t c_begin,
                                 int64_t c_end, double (*dl)[TR + 2]) {
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
     for (int e = tid; e < TK * TR; e += BLOCK) {
@@ -370,7 +480,7 @@ __device__ void rowblock_update(const double *__restrict__ Delta, bool trans, in
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int m = i * 16 + krow + 4 * r;
-                acc[i][r] = (nv && m < R) ? Out[(int64_t)m * ldo + n] : 0.0;
+                acc[i][r] = (nv && m < R) ? (double)Out[(int64_t)m * ldo + n] : 0.0;
             }
 #pragma unroll 1
         for (int h = 0; h < 2; ++h) {
@@ -378,7 +488,7 @@ __device__ void rowblock_update(const double *__restrict__ Delta, bool trans, in
 #pragma unroll
             for (int ks = 0; ks < KH; ++ks) {
                 const int k = (h * KH + ks) * 4 + krow;
-                bv[ks] = (nv && k < Kd) ? S[(int64_t)k * lds + n] : 0.0;
+                bv[ks] = (nv && k < Kd) ? (double)S[(int64_t)k * lds + n] : 0.0;
             }
 #pragma unroll
             for (int ks = 0; ks < KH; ++ks)
@@ -393,20 +503,82 @@ __device__ void rowblock_update(const double *__restrict__ Delta, bool trans, in
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int m = i * 16 + krow + 4 * r;
-                    if (m < R) Out[(int64_t)m * ldo + n] = acc[i][r];
+                    if (m < R) Out[(int64_t)m * ldo + n] = (E)acc[i][r];
                 }
         }
     }
 }
 
 
+// rowblock_update from FP32 S and Out (row lengths multiples of 4, columns up
+// to c_end, itself a multiple of 4): each wave owns 64 consecutive columns as
+// 4 MFMA blocks j with the columns {4 c + j}, so a lane reads and writes four
+// consecutive floats of a row; FP32 accumulation.  All BLOCK threads call it.
+template <int TR, int TK>
+__device__ void rowblock_update32(const double *__restrict__ Delta, bool trans, int R, int Kd,
+                                  const float *__restrict__ S, int64_t lds,
+                                  float *__restrict__ Out, int64_t ldo, int64_t c_begin,
+                                  int64_t c_end, float (*dl)[TR + 4]) {
+    static_assert(TR == 64 && TK == 64, "one 64 x 64 delta per tile");
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
+    for (int e = tid; e < TK * TR; e += BLOCK) {
+        const int k = e / TR, m = e % TR;
+        dl[k][m] = (m < R && k < Kd) ? (float)(trans ? Delta[k * TK + m] : Delta[m * TK + k])
+                                     : 0.f;
+    }
+    __syncthreads();
+    const int col = lane & 15, krow = lane >> 4;
+#pragma unroll 1
+    for (int64_t c0 = c_begin + wid * 64; c0 < c_end; c0 += 4 * 64) {
+        const int64_t n = c0 + 4 * col;              // this lane's four columns
+        const bool nv = n < c_end;
+        f32x4 acc[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = i * 16 + 4 * krow + r;
+                const f32x4 v = (nv && m < R)
+                                    ? *reinterpret_cast<const f32x4 *>(Out + (int64_t)m * ldo + n)
+                                    : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j][r] = v[j];
+            }
+#pragma unroll 2
+        for (int ks = 0; ks < TK / 4; ++ks) {
+            const int k = ks * 4 + krow;
+            const f32x4 bv = (nv && k < Kd)
+                                 ? *reinterpret_cast<const f32x4 *>(S + (int64_t)k * lds + n)
+                                 : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float av = dl[k][i * 16 + col];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = mfma_f32_16x16x4(av, bv[j], acc[i][j]);
+            }
+        }
+        if (nv) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int m = i * 16 + 4 * krow + r;
+                    if (m < R)
+                        *reinterpret_cast<f32x4 *>(Out + (int64_t)m * ldo + n) =
+                            f32x4{acc[i][0][r], acc[i][1][r], acc[i][2][r], acc[i][3][r]};
+                }
+        }
+    }
+}
+
 constexpr int UPD_CHUNKS = 4;   // 64-column chunks per update workgroup
 constexpr int UPD_MINB = 4;     // workgroups per CU the update kernels are built for
 
 // V[I, :] += dTheta[I, J] Sigma[J, :] for every changed tile of the wave.
+template <class E>
 __global__ __launch_bounds__(BLOCK, UPD_MINB) void theta_v_update_kernel(
-    const TileRect *__restrict__ rects, int64_t q, const double *__restrict__ Sigma,
-    const double *__restrict__ dT, const int *__restrict__ changed, double *__restrict__ V) {
+    const TileRect *__restrict__ rects, int64_t q, const E *__restrict__ Sigma,
+    const double *__restrict__ dT, const int *__restrict__ changed, E *__restrict__ V) {
     const int e = blockIdx.y;
     if (!changed[e]) return;
     const TileRect rc = rects[e];
@@ -414,8 +586,9 @@ __global__ __launch_bounds__(BLOCK, UPD_MINB) void theta_v_update_kernel(
     const int64_t c_begin = (int64_t)blockIdx.x * 64 * UPD_CHUNKS;
     const int64_t c_end = std::min<int64_t>(q, c_begin + 64 * UPD_CHUNKS);
     __shared__ double dl[TT][TT + 2];
-    rowblock_update<TT, TT>(dT + (int64_t)e * TT * TT, false, R, C, Sigma + (int64_t)rc.c0 * q,
-                            q, V + (int64_t)rc.r0 * q, q, c_begin, c_end, dl);
+    rowblock_update<TT, TT, E>(dT + (int64_t)e * TT * TT, false, R, C,
+                               Sigma + (int64_t)rc.c0 * q, q, V + (int64_t)rc.r0 * q, q, c_begin,
+                               c_end, dl);
 }
 
 // ----------------------------------------------------------------- Lambda ---
@@ -447,7 +620,8 @@ __global__ __launch_bounds__(BLOCK) void lambda_gs_kernel(
     const double *__restrict__ partial, int64_t q, const double *__restrict__ Sigma,
     const double *__restrict__ Psi, const double *__restrict__ GL,
     const double *__restrict__ Lam, double lamL, double *__restrict__ D,
-    double *__restrict__ dD, int *__restrict__ changed, unsigned long long *__restrict__ ctr) {
+    double *__restrict__ dD, int *__restrict__ changed, unsigned long long *__restrict__ ctr,
+    int esz) {
     static_assert(T == 64, "the Lambda tile is one wavefront wide");
     const int e = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
@@ -478,7 +652,7 @@ __global__ __launch_bounds__(BLOCK) void lambda_gs_kernel(
         const int64_t RC = (int64_t)R * C;
         atomicAdd(ctr + 0, 1ull);
         // snapshot: slabs SP[:, I], U[:, J], U[:, I], Psi[:, J]
-        atomicAdd(ctr + 1, (unsigned long long)(8 * 2 * q * (R + C)));
+        atomicAdd(ctr + 1, (unsigned long long)(esz * 2 * q * (R + C)));
         atomicAdd(ctr + 2, (unsigned long long)(4 * RC * q));
         // Gauss-Seidel: six Sigma / Psi blocks, G and Lambda reads, D (both
         // triangles) and delta writes
@@ -486,7 +660,7 @@ __global__ __launch_bounds__(BLOCK) void lambda_gs_kernel(
         atomicAdd(ctr + 4, (unsigned long long)(16 * RC * C));
         // update: Sigma rows read, U rows read and written (both index sets
         // of an off-diagonal tile)
-        const int64_t ub = diag ? 8 * q * 3 * R : 8 * q * 3 * (R + C);
+        const int64_t ub = diag ? esz * q * 3 * R : esz * q * 3 * (R + C);
         atomicAdd(ctr + 5, (unsigned long long)ub);
         atomicAdd(ctr + 6, (unsigned long long)((diag ? 2 : 4) * RC * q));
     }
@@ -671,9 +845,10 @@ __global__ __launch_bounds__(BLOCK) void lambda_gs_kernel(
 
 // U[I, :] += dD Sigma[J, :] and U[J, :] += dD^T Sigma[I, :] (off-diagonal
 // tiles), or U[I, :] += dD_sym Sigma[I, :] (diagonal tiles).
+template <class E>
 __global__ __launch_bounds__(BLOCK, UPD_MINB) void lambda_u_update_kernel(
-    const TileRect *__restrict__ rects, int64_t q, const double *__restrict__ Sigma,
-    const double *__restrict__ dD, const int *__restrict__ changed, double *__restrict__ U) {
+    const TileRect *__restrict__ rects, int64_t q, const E *__restrict__ Sigma,
+    const double *__restrict__ dD, const int *__restrict__ changed, E *__restrict__ U) {
     const int e = blockIdx.y, half = blockIdx.z;
     if (!changed[e]) return;
     const TileRect rc = rects[e];
@@ -685,11 +860,49 @@ __global__ __launch_bounds__(BLOCK, UPD_MINB) void lambda_u_update_kernel(
     __shared__ double dl[T][T + 2];
     const double *dDe = dD + (int64_t)e * T * T;
     if (half == 0)
-        rowblock_update<T, T>(dDe, false, R, C, Sigma + (int64_t)rc.c0 * q, q,
-                              U + (int64_t)rc.r0 * q, q, c_begin, c_end, dl);
+        rowblock_update<T, T, E>(dDe, false, R, C, Sigma + (int64_t)rc.c0 * q, q,
+                                 U + (int64_t)rc.r0 * q, q, c_begin, c_end, dl);
     else
-        rowblock_update<T, T>(dDe, true, C, R, Sigma + (int64_t)rc.r0 * q, q,
-                              U + (int64_t)rc.c0 * q, q, c_begin, c_end, dl);
+        rowblock_update<T, T, E>(dDe, true, C, R, Sigma + (int64_t)rc.r0 * q, q,
+                                 U + (int64_t)rc.c0 * q, q, c_begin, c_end, dl);
+}
+
+// The updates on FP32 copies (row length ld): V32[I, :] += dTheta Sigma32[J, :];
+// U32 as lambda_u_update_kernel.  UPD32_COLS columns per workgroup.
+constexpr int UPD32_COLS = 1024;
+__global__ __launch_bounds__(BLOCK, UPD_MINB) void theta_v_update32_kernel(
+    const TileRect *__restrict__ rects, int64_t ld, const float *__restrict__ Sigma,
+    const double *__restrict__ dT, const int *__restrict__ changed, float *__restrict__ V) {
+    const int e = blockIdx.y;
+    if (!changed[e]) return;
+    const TileRect rc = rects[e];
+    const int R = rc.r1 - rc.r0, C = rc.c1 - rc.c0;
+    const int64_t c_begin = (int64_t)blockIdx.x * UPD32_COLS;
+    const int64_t c_end = std::min<int64_t>(ld, c_begin + UPD32_COLS);
+    __shared__ float dl[TT][TT + 4];
+    rowblock_update32<TT, TT>(dT + (int64_t)e * TT * TT, false, R, C, Sigma + (int64_t)rc.c0 * ld,
+                              ld, V + (int64_t)rc.r0 * ld, ld, c_begin, c_end, dl);
+}
+
+__global__ __launch_bounds__(BLOCK, UPD_MINB) void lambda_u_update32_kernel(
+    const TileRect *__restrict__ rects, int64_t ld, const float *__restrict__ Sigma,
+    const double *__restrict__ dD, const int *__restrict__ changed, float *__restrict__ U) {
+    const int e = blockIdx.y, half = blockIdx.z;
+    if (!changed[e]) return;
+    const TileRect rc = rects[e];
+    const bool diag = rc.r0 == rc.c0;
+    if (diag && half == 1) return;
+    const int R = rc.r1 - rc.r0, C = rc.c1 - rc.c0;
+    const int64_t c_begin = (int64_t)blockIdx.x * UPD32_COLS;
+    const int64_t c_end = std::min<int64_t>(ld, c_begin + UPD32_COLS);
+    __shared__ float dl[T][T + 4];
+    const double *dDe = dD + (int64_t)e * T * T;
+    if (half == 0)
+        rowblock_update32<T, T>(dDe, false, R, C, Sigma + (int64_t)rc.c0 * ld, ld,
+                                U + (int64_t)rc.r0 * ld, ld, c_begin, c_end, dl);
+    else
+        rowblock_update32<T, T>(dDe, true, C, R, Sigma + (int64_t)rc.r0 * ld, ld,
+                                U + (int64_t)rc.c0 * ld, ld, c_begin, c_end, dl);
 }
 
 // Parts of the K range per tile snapshot: enough wavefronts per launch
@@ -725,39 +938,70 @@ void lambda_activity(hipStream_t s, const TileRect *rects_dev, int nrect, int64_
 void theta_wave(hipStream_t s, const TileRect *rects_dev, const int *active, int nrect,
                 int64_t p, int64_t q, const double *Sxx, const double *Sxy, const double *Sigma,
                 double *V, const double *GT, double *Theta, double lamT, double *dT,
-                int *changed, const CdScratch &scr, const WaveProbe *probe) {
+                int *changed, const CdScratch &scr, const WaveProbe *probe,
+                const SweepF32 *f32) {
     if (nrect <= 0) return;
     constexpr int NB = snap_blocks_per_tile<TT>();
     const int S = snapshot_parts(nrect, NB, p);
-    SnapArgs<1> args{{Sxx}, {p}, {V}, {q}};
+    const bool lo = f32 && f32->on;
+    const unsigned nsb = (unsigned)snapshot_blocks((int64_t)nrect * S, NB);
     record(s, probe, 0);
-    snapshot_kernel<TT, 1><<<(unsigned)snapshot_blocks((int64_t)nrect * S, NB), WAVE, 0, s>>>(
-        rects_dev, active, S, nrect, p, args, scr.partial);
+    if (lo) {
+        SnapArgs<1, float> args{{f32->Sxx}, {f32->ldp}, {f32->V}, {f32->ldq}};
+        snapshot32_kernel<TT, 1><<<nsb, WAVE, 0, s>>>(rects_dev, active, S, nrect, p, args,
+                                                      scr.partial);
+    } else {
+        SnapArgs<1, double> args{{Sxx}, {p}, {V}, {q}};
+        snapshot_kernel<TT, 1, double><<<nsb, WAVE, 0, s>>>(rects_dev, active, S, nrect, p, args,
+                                                            scr.partial);
+    }
     CGGM_LAUNCH_CHECK();
     sum_snapshots<TT>(s, active, nrect, S, scr.partial);
     record(s, probe, 1);
     theta_gs_kernel<<<nrect, BLOCK, 0, s>>>(rects_dev, active, S, scr.partial, p, q, Sxx, Sxy,
                                             Sigma, GT, Theta, lamT, dT, changed,
-                                            probe ? probe->counters : nullptr);
+                                            probe ? probe->counters : nullptr,
+                                            lo ? (int)sizeof(float) : (int)sizeof(double));
     CGGM_LAUNCH_CHECK();
     record(s, probe, 2);
     const int64_t cols_per_wg = 64 * UPD_CHUNKS;
-    dim3 grid((unsigned)((q + cols_per_wg - 1) / cols_per_wg), (unsigned)nrect);
-    theta_v_update_kernel<<<grid, BLOCK, 0, s>>>(rects_dev, q, Sigma, dT, changed, V);
+    if (lo) {
+        dim3 grid((unsigned)((f32->ldq + UPD32_COLS - 1) / UPD32_COLS), (unsigned)nrect);
+        theta_v_update32_kernel<<<grid, BLOCK, 0, s>>>(rects_dev, f32->ldq, f32->Sigma, dT,
+                                                       changed, f32->V);
+    } else {
+        dim3 grid((unsigned)((q + cols_per_wg - 1) / cols_per_wg), (unsigned)nrect);
+        theta_v_update_kernel<double><<<grid, BLOCK, 0, s>>>(rects_dev, q, Sigma, dT, changed, V);
+    }
     CGGM_LAUNCH_CHECK();
     record(s, probe, 3);
 }
 
+// b snapshot: G + (SP U)[I, J] + ((Psi U)[J, I])^T
+//   = G + SP[:, I]^T U[:, J] + U[:, I]^T Psi[:, J]   (SP, Psi symmetric)
 int lambda_snapshot(hipStream_t s, const TileRect *rects_dev, const int *active, int nrect,
                     int64_t q, const double *SP, const double *U, const double *Psi,
                     const CdScratch &scr) {
     if (nrect <= 0) return 0;
     constexpr int NB = snap_blocks_per_tile<T>();
     const int S = snapshot_parts(nrect, NB, q);
-    // b snapshot: G + (SP U)[I, J] + ((Psi U)[J, I])^T
-    //   = G + SP[:, I]^T U[:, J] + U[:, I]^T Psi[:, J]   (SP, Psi symmetric)
-    SnapArgs<2> args{{SP, U}, {q, q}, {U, Psi}, {q, q}};
-    snapshot_kernel<T, 2><<<(unsigned)snapshot_blocks((int64_t)nrect * S, NB), WAVE, 0, s>>>(
+    SnapArgs<2, double> args{{SP, U}, {q, q}, {U, Psi}, {q, q}};
+    snapshot_kernel<T, 2, double>
+        <<<(unsigned)snapshot_blocks((int64_t)nrect * S, NB), WAVE, 0, s>>>(
+            rects_dev, active, S, nrect, q, args, scr.partial);
+    CGGM_LAUNCH_CHECK();
+    sum_snapshots<T>(s, active, nrect, S, scr.partial);
+    return S;
+}
+
+int lambda_snapshot(hipStream_t s, const TileRect *rects_dev, const int *active, int nrect,
+                    int64_t q, const float *SP, const float *U, const float *Psi, int64_t ld,
+                    const CdScratch &scr) {
+    if (nrect <= 0) return 0;
+    constexpr int NB = snap_blocks_per_tile<T>();
+    const int S = snapshot_parts(nrect, NB, q);
+    SnapArgs<2, float> args{{SP, U}, {ld, ld}, {U, Psi}, {ld, ld}};
+    snapshot32_kernel<T, 2><<<(unsigned)snapshot_blocks((int64_t)nrect * S, NB), WAVE, 0, s>>>(
         rects_dev, active, S, nrect, q, args, scr.partial);
     CGGM_LAUNCH_CHECK();
     sum_snapshots<T>(s, active, nrect, S, scr.partial);
@@ -768,10 +1012,10 @@ void lambda_gauss_seidel(hipStream_t s, const TileRect *rects_dev, const int *ac
                          int S, int64_t q, const double *Sigma, const double *Psi,
                          const double *GL, const double *Lam, double lamL, double *D,
                          double *dD, int *changed, const CdScratch &scr,
-                         unsigned long long *counters) {
+                         unsigned long long *counters, int esz) {
     if (nrect <= 0) return;
     lambda_gs_kernel<<<nrect, BLOCK, 0, s>>>(rects_dev, active, S, scr.partial, q, Sigma, Psi, GL,
-                                             Lam, lamL, D, dD, changed, counters);
+                                             Lam, lamL, D, dD, changed, counters, esz);
     CGGM_LAUNCH_CHECK();
 }
 
@@ -780,22 +1024,38 @@ void lambda_update(hipStream_t s, const TileRect *rects_dev, int nrect, int64_t 
     if (nrect <= 0) return;
     const int64_t cols_per_wg = 64 * UPD_CHUNKS;
     dim3 grid((unsigned)((q + cols_per_wg - 1) / cols_per_wg), (unsigned)nrect, 2);
-    lambda_u_update_kernel<<<grid, BLOCK, 0, s>>>(rects_dev, q, Sigma, dD, changed, U);
+    lambda_u_update_kernel<double><<<grid, BLOCK, 0, s>>>(rects_dev, q, Sigma, dD, changed, U);
+    CGGM_LAUNCH_CHECK();
+}
+
+void lambda_update(hipStream_t s, const TileRect *rects_dev, int nrect, int64_t ld,
+                   const float *Sigma, const double *dD, const int *changed, float *U) {
+    if (nrect <= 0) return;
+    dim3 grid((unsigned)((ld + UPD32_COLS - 1) / UPD32_COLS), (unsigned)nrect, 2);
+    lambda_u_update32_kernel<<<grid, BLOCK, 0, s>>>(rects_dev, ld, Sigma, dD, changed, U);
     CGGM_LAUNCH_CHECK();
 }
 
 void lambda_wave(hipStream_t s, const TileRect *rects_dev, const int *active, int nrect,
                  int64_t q, const double *Sigma, const double *Psi, const double *SP,
                  const double *GL, const double *Lam, double lamL, double *D, double *U,
-                 double *dD, int *changed, const CdScratch &scr, const WaveProbe *probe) {
+                 double *dD, int *changed, const CdScratch &scr, const WaveProbe *probe,
+                 const SweepF32 *f32) {
     if (nrect <= 0) return;
+    const bool lo = f32 && f32->on;
     record(s, probe, 0);
-    const int S = lambda_snapshot(s, rects_dev, active, nrect, q, SP, U, Psi, scr);
+    const int S = lo ? lambda_snapshot(s, rects_dev, active, nrect, q, f32->SP, f32->U,
+                                       f32->Psi, f32->ldq, scr)
+                     : lambda_snapshot(s, rects_dev, active, nrect, q, SP, U, Psi, scr);
     record(s, probe, 1);
     lambda_gauss_seidel(s, rects_dev, active, nrect, S, q, Sigma, Psi, GL, Lam, lamL, D, dD,
-                        changed, scr, probe ? probe->counters : nullptr);
+                        changed, scr, probe ? probe->counters : nullptr,
+                        lo ? (int)sizeof(float) : (int)sizeof(double));
     record(s, probe, 2);
-    lambda_update(s, rects_dev, nrect, q, Sigma, dD, changed, U);
+    if (lo)
+        lambda_update(s, rects_dev, nrect, f32->ldq, f32->Sigma, dD, changed, f32->U);
+    else
+        lambda_update(s, rects_dev, nrect, q, Sigma, dD, changed, U);
     record(s, probe, 3);
 }
 

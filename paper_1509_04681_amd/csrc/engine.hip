@@ -206,6 +206,9 @@ struct Work {
     TileRect *rects_theta, *rects_lambda;
     int max_tiles = 0;
     __bf16 *split_Th = nullptr, *split_Sig = nullptr;   // mixed mode: BF16 pieces
+    // mixed mode: FP32 copies of the operands the CD sweeps stream
+    float *SP32 = nullptr, *Psi32 = nullptr, *Sig32 = nullptr, *U32 = nullptr;
+    float *Sxx32 = nullptr, *V32 = nullptr;
 };
 
 constexpr int NSCAL = 64;
@@ -254,6 +257,13 @@ void layout(Arena &a, Work &w, int64_t n, int64_t p, int64_t q, int64_t ntheta_r
     if (mixed) {
         w.split_Th = a.take<__bf16>(3 * p * split3_stride(q));
         w.split_Sig = a.take<__bf16>(3 * q * split3_stride(q));
+        const int64_t lq = f32_ld(q), lp = f32_ld(p);
+        w.SP32 = a.take<float>(q * lq);
+        w.Psi32 = a.take<float>(q * lq);
+        w.Sig32 = a.take<float>(q * lq);
+        w.U32 = a.take<float>(q * lq);
+        w.Sxx32 = a.take<float>(p * lp);
+        w.V32 = a.take<float>(p * lq);
     }
 }
 
@@ -278,7 +288,8 @@ struct Ctx {
 };
 
 // V = Theta Sigma: FP64 MFMA, or in mixed mode from the BF16 pieces of Theta
-// and Sigma (Sigma symmetric: its rows are the columns the product needs).
+// and Sigma (Sigma symmetric: its rows are the columns the product needs) into
+// the FP32 V the mixed Theta sweep maintains.
 void theta_sigma(Ctx &c) {
     Work &w = c.w;
     if (!c.mixed) {
@@ -287,7 +298,31 @@ void theta_sigma(Ctx &c) {
     }
     split3(c.s, w.p, w.q, w.Th, w.q, w.split_Th);
     split3(c.s, w.q, w.q, w.Sig, w.q, w.split_Sig);
-    gemm_split3_nt(c.s, w.p, w.q, w.q, w.split_Th, w.split_Sig, w.V, w.q);
+    gemm_split3_nt(c.s, w.p, w.q, w.q, w.split_Th, w.split_Sig, w.V32, f32_ld(w.q));
+}
+
+// Operands of a sweep in the current precision.
+SweepF32 sweep_operands(const Ctx &c) {
+    SweepF32 f;
+    if (!c.mixed) return f;
+    const Work &w = c.w;
+    f.on = true;
+    f.ldq = f32_ld(w.q);
+    f.ldp = f32_ld(w.p);
+    f.SP = w.SP32;
+    f.Psi = w.Psi32;
+    f.Sigma = w.Sig32;
+    f.Sxx = w.Sxx32;
+    f.U = w.U32;
+    f.V = w.V32;
+    return f;
+}
+
+// Sigma of the current factor; in mixed mode also its FP32 copy.
+void refresh_sigma(Ctx &c) {
+    Work &w = c.w;
+    spd_inverse_from_cholesky(c.s, w.q, w.L, w.Wd, w.U, w.Sig);
+    if (c.mixed) to_f32(c.s, w.q, w.q, w.Sig, w.q, w.Sig32, f32_ld(w.q));
 }
 
 // Rounding allowance of an FP64 objective evaluation in the Armijo test and
@@ -323,6 +358,10 @@ void gradients(Ctx &c, const double *X) {
     assemble_lambda_gradient(c.s, w.q, w.Syy, w.Sig, w.Psi, w.GL, w.SP);
     scale_copy(c.s, w.p * w.q, 2.0, w.Sxy, w.GT);
     gemm(c.s, true, false, w.p, w.q, w.n, 2.0 * inv_n, X, w.p, w.R, w.q, 1.0, w.GT, w.q);
+    if (c.mixed) {
+        to_f32(c.s, w.q, w.q, w.SP, w.q, w.SP32, f32_ld(w.q));
+        to_f32(c.s, w.q, w.q, w.Psi, w.q, w.Psi32, f32_ld(w.q));
+    }
 }
 
 struct TopStats {
@@ -415,6 +454,7 @@ struct KernelTimer {
 
 void run_theta_sweep(Ctx &c, const Schedule &sch, KernelTimer *kt = nullptr) {
     Work &w = c.w;
+    const SweepF32 f32 = sweep_operands(c);
     theta_activity(c.s, w.rects_theta, (int)sch.rects.size(), w.q, w.GT, w.Th, c.lamT,
                    w.act_theta);
     for (int k = 0; k < sch.waves(); ++k) {
@@ -423,7 +463,7 @@ void run_theta_sweep(Ctx &c, const Schedule &sch, KernelTimer *kt = nullptr) {
         if (kt && kt->on()) pr = kt->probe();
         theta_wave(c.s, w.rects_theta + b, w.act_theta + b, e - b, w.p, w.q, w.Sxx, w.Sxy, w.Sig,
                    w.V, w.GT, w.Th, c.lamT, w.dT, w.changed, w.cd,
-                   (kt && kt->on()) ? &pr : nullptr);
+                   (kt && kt->on()) ? &pr : nullptr, &f32);
     }
 }
 
@@ -431,9 +471,13 @@ void run_theta_sweep(Ctx &c, const Schedule &sch, KernelTimer *kt = nullptr) {
 // on the first pass and carry over to further passes (pass > 0).
 void run_lambda_sweep(Ctx &c, const Schedule &sch, KernelTimer *kt = nullptr, int pass = 0) {
     Work &w = c.w;
+    const SweepF32 f32 = sweep_operands(c);
     if (pass == 0) {
         fill(c.s, w.q * w.q, 0.0, w.D);
-        fill(c.s, w.q * w.q, 0.0, w.U);
+        if (f32.on)
+            fill_f32(c.s, w.q * f32_ld(w.q), 0.0f, w.U32);
+        else
+            fill(c.s, w.q * w.q, 0.0, w.U);
         lambda_activity(c.s, w.rects_lambda, (int)sch.rects.size(), w.q, w.GL, w.Lam, c.lamL,
                         w.act_lambda);
     }
@@ -443,7 +487,7 @@ void run_lambda_sweep(Ctx &c, const Schedule &sch, KernelTimer *kt = nullptr, in
         if (kt && kt->on()) pr = kt->probe();
         lambda_wave(c.s, w.rects_lambda + b, w.act_lambda + b, e - b, w.q, w.Sig, w.Psi, w.SP,
                     w.GL, w.Lam, c.lamL, w.D, w.U, w.dD, w.changed, w.cd,
-                    (kt && kt->on()) ? &pr : nullptr);
+                    (kt && kt->on()) ? &pr : nullptr, &f32);
     }
 }
 
@@ -616,6 +660,10 @@ struct Solver::Impl {
         }
         t0 = std::chrono::steady_clock::now();
         statistics(c, X, Y);
+        if (mixed) {
+            to_f32(s, p, p, w.Sxx, p, w.Sxx32, f32_ld(p));
+            fill_f32(s, p * f32_ld(q), 0.0f, w.V32);   // the padding columns stay zero
+        }
         loaded = true;
     }
     void start() {
@@ -642,7 +690,7 @@ struct Solver::Impl {
         CGGM_HIP(hipMemcpyAsync(&hflag, w.flag, sizeof(int), hipMemcpyDeviceToHost, s));
         CGGM_HIP(hipStreamSynchronize(s));
         if (hflag) fail(CGGM_ENOTPD, "the warm-start Lambda is not positive definite");
-        spd_inverse_from_cholesky(s, q, w.L, w.Wd, w.U, w.Sig);
+        refresh_sigma(c);
         theta_products(c, X);
         started = true;
     }
@@ -833,7 +881,7 @@ SolveOutcome Solver::Impl::run(double lamL, double lamT, double tol) {
         f_after_ls = f_acc;
         last_alpha = alpha;
         last_trials = trials;
-        spd_inverse_from_cholesky(s, q, w.L, w.Wd, w.U, w.Sig);
+        refresh_sigma(c);
         CGGM_HIP(hipEventRecord(ev[4], s));
         have_phase = true;
 

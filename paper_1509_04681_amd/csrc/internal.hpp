@@ -118,6 +118,12 @@ void assemble_lambda_gradient(hipStream_t s, int64_t q, const double *Syy,
 // y = a x (count entries).
 void scale_copy(hipStream_t s, int64_t count, double a, const double *x, double *y);
 
+// y = (float)x elementwise (rows x cols, row lengths ldx and ldy >= cols; the
+// columns [cols, ldy) of y are set to zero); y = v.
+void to_f32(hipStream_t s, int64_t rows, int64_t cols, const double *x, int64_t ldx, float *y,
+            int64_t ldy);
+void fill_f32(hipStream_t s, int64_t count, float v, float *y);
+
 // Set a device int to a value (a kernel, so the stream may be graph-captured).
 void set_int(hipStream_t s, int *dst, int v);
 
@@ -140,6 +146,9 @@ void split3(hipStream_t s, int64_t rows, int64_t cols, const double *X, int64_t 
 // FP32 accumulation.
 void gemm_split3_nt(hipStream_t s, int64_t M, int64_t N, int64_t K, const __bf16 *Ap,
                     const __bf16 *Bp, double *C, int64_t ldc);
+// The same with an FP32 result (the FP32 accumulators stored as they are).
+void gemm_split3_nt(hipStream_t s, int64_t M, int64_t N, int64_t K, const __bf16 *Ap,
+                    const __bf16 *Bp, float *C, int64_t ldc);
 
 // ---------------------------------------------------------------- cd.hip ---
 struct TileRect {
@@ -166,6 +175,18 @@ struct CdScratch {
     double *partial = nullptr;
 };
 
+// FP32 copies of the operands the sweeps stream, used in the mixed mode: when
+// `on`, the snapshots and the maintained-product updates read (and for U, V
+// write) these instead of the FP64 arrays, converting to FP64 in registers;
+// the Gauss-Seidel stage still reads FP64 blocks and writes FP64 parameters.
+struct SweepF32 {
+    bool on = false;
+    int64_t ldq = 0, ldp = 0;   // row lengths: q and p rounded up to 4 (padding zero)
+    const float *SP = nullptr, *Psi = nullptr, *Sigma = nullptr, *Sxx = nullptr;  // q or p rows
+    float *U = nullptr, *V = nullptr;
+};
+inline int64_t f32_ld(int64_t cols) { return (cols + 3) / 4 * 4; }
+
 // Activity of every rect of a sweep (1 when the rect holds a coordinate with
 // |G| > lambda or a nonzero parameter), decided once at the start of the sweep.
 void theta_activity(hipStream_t s, const TileRect *rects_dev, int nrect, int64_t q,
@@ -180,22 +201,30 @@ void lambda_activity(hipStream_t s, const TileRect *rects_dev, int nrect, int64_
 void theta_wave(hipStream_t s, const TileRect *rects_dev, const int *active, int nrect,
                 int64_t p, int64_t q, const double *Sxx, const double *Sxy, const double *Sigma,
                 double *V, const double *GT, double *Theta, double lamT, double *dT,
-                int *changed, const CdScratch &scr, const WaveProbe *probe = nullptr);
+                int *changed, const CdScratch &scr, const WaveProbe *probe = nullptr,
+                const SweepF32 *f32 = nullptr);
 
 // The three stages of a Lambda wave (lambda_wave runs them in order).
 // lambda_snapshot returns the number of K parts the Gauss-Seidel stage must be
 // given.  Within one wave every snapshot must complete before any update
 // starts (the updates write rows of U that every snapshot reads).
+// The FP32 overloads take the operand copies of the mixed mode; `esz` is the
+// byte size of the streamed operands (for the traffic counters).
 int lambda_snapshot(hipStream_t s, const TileRect *rects_dev, const int *active, int nrect,
                     int64_t q, const double *SP, const double *U, const double *Psi,
+                    const CdScratch &scr);
+int lambda_snapshot(hipStream_t s, const TileRect *rects_dev, const int *active, int nrect,
+                    int64_t q, const float *SP, const float *U, const float *Psi, int64_t ld,
                     const CdScratch &scr);
 void lambda_gauss_seidel(hipStream_t s, const TileRect *rects_dev, const int *active, int nrect,
                          int S, int64_t q, const double *Sigma, const double *Psi,
                          const double *GL, const double *Lam, double lamL, double *D,
                          double *dD, int *changed, const CdScratch &scr,
-                         unsigned long long *counters);
+                         unsigned long long *counters, int esz = 8);
 void lambda_update(hipStream_t s, const TileRect *rects_dev, int nrect, int64_t q,
                    const double *Sigma, const double *dD, const int *changed, double *U);
+void lambda_update(hipStream_t s, const TileRect *rects_dev, int nrect, int64_t ld,
+                   const float *Sigma, const double *dD, const int *changed, float *U);
 
 // One wave of the Lambda direction sweep over upper-triangle rects with
 // pairwise-disjoint index sets: exact Gauss-Seidel inside each rect from a
@@ -204,6 +233,7 @@ void lambda_update(hipStream_t s, const TileRect *rects_dev, int nrect, int64_t 
 void lambda_wave(hipStream_t s, const TileRect *rects_dev, const int *active, int nrect,
                  int64_t q, const double *Sigma, const double *Psi, const double *SP,
                  const double *GL, const double *Lam, double lamL, double *D, double *U,
-                 double *dD, int *changed, const CdScratch &scr, const WaveProbe *probe = nullptr);
+                 double *dD, int *changed, const CdScratch &scr, const WaveProbe *probe = nullptr,
+                 const SweepF32 *f32 = nullptr);
 
 }  // namespace cggm

@@ -267,6 +267,19 @@ __global__ void scale_copy_kernel(int64_t count, double a, const double *x, doub
 
 __global__ void set_int_kernel(int *dst, int v) { *dst = v; }
 
+__global__ void to_f32_kernel(int64_t rows, int64_t cols, const double *__restrict__ x,
+                              int64_t ldx, float *__restrict__ y, int64_t ldy) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= rows * ldy) return;
+    const int64_t r = e / ldy, c = e % ldy;
+    y[e] = c < cols ? (float)x[r * ldx + c] : 0.f;
+}
+
+__global__ void fill_f32_kernel(int64_t count, float v, float *__restrict__ y) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < count) y[e] = v;
+}
+
 // ---------------------------------------------------------- reductions ------
 // Block-level sum of NV values; thread 0 of the block gets the totals.
 template <int NV>
@@ -557,6 +570,21 @@ void assemble_lambda_gradient(hipStream_t s, int64_t q, const double *Syy,
 
 void scale_copy(hipStream_t s, int64_t count, double a, const double *x, double *y) {
     scale_copy_kernel<<<blocks_for(count), BLOCK, 0, s>>>(count, a, x, y);
+    CGGM_LAUNCH_CHECK();
+}
+
+void to_f32(hipStream_t s, int64_t rows, int64_t cols, const double *x, int64_t ldx, float *y,
+            int64_t ldy) {
+    const int64_t count = rows * ldy;
+    if (count <= 0) return;
+    to_f32_kernel<<<(unsigned)((count + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(rows, cols, x, ldx, y,
+                                                                            ldy);
+    CGGM_LAUNCH_CHECK();
+}
+
+void fill_f32(hipStream_t s, int64_t count, float v, float *y) {
+    if (count <= 0) return;
+    fill_f32_kernel<<<(unsigned)((count + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(count, v, y);
     CGGM_LAUNCH_CHECK();
 }
 

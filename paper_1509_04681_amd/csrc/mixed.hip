@@ -57,11 +57,11 @@ struct MixSmem {
 // and B (N x Kp): 128 x 128 tiles, each of the 4 waves a 64 x 64 quarter as
 // 4 x 4 MFMA blocks with FP32 accumulators.  The next K step's planes are
 // loaded into registers while the current one is multiplied from LDS.
+template <class TC>
 __global__ __launch_bounds__(BLOCK) void gemm_split3_nt_kernel(int64_t M, int64_t N, int64_t Kp,
                                                                const __bf16 *__restrict__ Ap,
                                                                const __bf16 *__restrict__ Bp,
-                                                               double *__restrict__ C,
-                                                               int64_t ldc) {
+                                                               TC *__restrict__ C, int64_t ldc) {
     __shared__ MixSmem sm;
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
     const int64_t m0 = (int64_t)blockIdx.y * MT, n0 = (int64_t)blockIdx.x * MT;
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(BLOCK) void gemm_split3_nt_kernel(int64_t M, int64_
             for (int r = 0; r < 4; ++r) {
                 const int64_t row = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
                 const int64_t cc = n0 + wn + j * 16 + col;
-                if (row < M && cc < N) C[row * ldc + cc] = (double)acc[i][j][r];
+                if (row < M && cc < N) C[row * ldc + cc] = (TC)acc[i][j][r];
             }
 }
 
@@ -157,12 +157,23 @@ void split3(hipStream_t s, int64_t rows, int64_t cols, const double *X, int64_t 
     CGGM_LAUNCH_CHECK();
 }
 
-void gemm_split3_nt(hipStream_t s, int64_t M, int64_t N, int64_t K, const __bf16 *Ap,
-                    const __bf16 *Bp, double *C, int64_t ldc) {
+template <class TC>
+void gemm_split3_nt_t(hipStream_t s, int64_t M, int64_t N, int64_t K, const __bf16 *Ap,
+                      const __bf16 *Bp, TC *C, int64_t ldc) {
     if (M <= 0 || N <= 0) return;
     dim3 grid((unsigned)((N + MT - 1) / MT), (unsigned)((M + MT - 1) / MT));
-    gemm_split3_nt_kernel<<<grid, BLOCK, 0, s>>>(M, N, split3_stride(K), Ap, Bp, C, ldc);
+    gemm_split3_nt_kernel<TC><<<grid, BLOCK, 0, s>>>(M, N, split3_stride(K), Ap, Bp, C, ldc);
     CGGM_LAUNCH_CHECK();
+}
+
+void gemm_split3_nt(hipStream_t s, int64_t M, int64_t N, int64_t K, const __bf16 *Ap,
+                    const __bf16 *Bp, double *C, int64_t ldc) {
+    gemm_split3_nt_t<double>(s, M, N, K, Ap, Bp, C, ldc);
+}
+
+void gemm_split3_nt(hipStream_t s, int64_t M, int64_t N, int64_t K, const __bf16 *Ap,
+                    const __bf16 *Bp, float *C, int64_t ldc) {
+    gemm_split3_nt_t<float>(s, M, N, K, Ap, Bp, C, ldc);
 }
 
 }  // namespace cggm
