@@ -55,7 +55,8 @@ extern "C" {
 
 /* ---- arithmetic ---------------------------------------------------------
  * FP64: every step in FP64.
- * MIXED: while the subgradient is above 1e-4 of the stopping scale
+ * MIXED (problems with q >= options.mixed_min_q; smaller ones run in FP64):
+ *   while the subgradient is above 1e-4 of the stopping scale
  *   (||Lambda||_1 + ||Theta||_1), the coordinate-descent sweeps (Sec. 3.1,
  *   3.2) stream FP32 copies of Sigma, Psi, Sigma + Psi and Sxx and maintain
  *   U = D Sigma and V = Theta Sigma in FP32, with their products on the FP32
@@ -121,6 +122,15 @@ typedef struct {
                               per iteration (Sec. 3 makes one; default 4)     */
     int precision;         /* CGGM_PRECISION_FP64 (default) or
                               CGGM_PRECISION_MIXED                             */
+    int mixed_min_q;       /* CGGM_PRECISION_MIXED applies to problems with
+                              q >= this (default 4096; 0 = always); smaller
+                              ones run in FP64.  Below it the sweeps are bound
+                              by the latency of small launches and
+                              Gauss-Seidel chains, not by HBM, and the extra
+                              conversions and split products only cost time
+                              (at q = 2000 the mixed mode gained nothing; at
+                              q = 20000 it takes an outer iteration from
+                              6.9 s to 4.3 s on one MI355X)                   */
     size_t workspace_budget;   /* bytes of device workspace allowed (0 = any)  */
     const double *warm_Lambda; /* device q x q start (NULL = identity)         */
     const double *warm_Theta;  /* device p x q start (NULL = zero)             */
@@ -256,6 +266,7 @@ typedef struct {
     int precision;            /* CGGM_PRECISION_*                                 */
     int max_iter;             /* per path point; 0 = default                      */
     int lambda_passes;        /* 0 = default                                      */
+    int mixed_min_q;          /* as cggm_options.mixed_min_q; < 0 = default      */
     double *Lambda_out;       /* device npath x q x q, or NULL                    */
     double *Theta_out;        /* device npath x p x q, or NULL                    */
 } cggm_request;

@@ -58,7 +58,7 @@ class Options(ctypes.Structure):
                 ("ls_beta", ctypes.c_double), ("ls_sigma", ctypes.c_double),
                 ("stall_iters", ctypes.c_int), ("sweep", ctypes.c_int),
                 ("tile", ctypes.c_int), ("lambda_passes", ctypes.c_int),
-                ("precision", ctypes.c_int),
+                ("precision", ctypes.c_int), ("mixed_min_q", ctypes.c_int),
                 ("workspace_budget", ctypes.c_size_t),
                 ("warm_Lambda", _vp), ("warm_Theta", _vp),
                 ("trace", ctypes.POINTER(TraceEntry)), ("trace_cap", ctypes.c_int),
@@ -69,7 +69,8 @@ class Request(ctypes.Structure):
     _fields_ = [("X", _vp), ("Y", _vp), ("n", _i64), ("p", _i64), ("q", _i64),
                 ("npath", ctypes.c_int), ("lamL", _dp), ("lamT", _dp), ("tol", ctypes.c_double),
                 ("precision", ctypes.c_int), ("max_iter", ctypes.c_int),
-                ("lambda_passes", ctypes.c_int), ("Lambda_out", _vp), ("Theta_out", _vp)]
+                ("lambda_passes", ctypes.c_int), ("mixed_min_q", ctypes.c_int),
+                ("Lambda_out", _vp), ("Theta_out", _vp)]
 
 
 class RequestInfo(ctypes.Structure):
@@ -207,13 +208,16 @@ class SolveResult:
 
 
 def _options(lib, *, max_iter, max_ls, ls_beta, ls_sigma, stall_iters, sweep, tile,
-             lambda_passes, precision, workspace_budget, warm_Lambda, warm_Theta) -> Options:
+             lambda_passes, precision, workspace_budget, warm_Lambda, warm_Theta,
+             mixed_min_q=None) -> Options:
     opt = Options()
     lib.cggm_default_options(ctypes.byref(opt))
     opt.max_iter, opt.max_ls, opt.ls_beta, opt.ls_sigma = max_iter, max_ls, ls_beta, ls_sigma
     opt.stall_iters, opt.sweep, opt.tile = stall_iters, sweep, tile
     opt.lambda_passes = lambda_passes
     opt.precision = PRECISIONS[precision]
+    if mixed_min_q is not None:
+        opt.mixed_min_q = mixed_min_q
     opt.workspace_budget = workspace_budget
     if warm_Lambda is not None:
         opt.warm_Lambda = _dev(warm_Lambda, "warm_Lambda").value
@@ -257,7 +261,7 @@ def cggm_solve(X, Y, lam_Lambda: float, lam_Theta: float, tol: float = 1e-2, *,
                max_iter: int = 500, max_ls: int = 30, ls_beta: float = 0.5,
                ls_sigma: float = 1e-3, stall_iters: int = 3, sweep: int = CGGM_SWEEP_TILED,
                tile: int = 0, lambda_passes: int = 4, precision: str = "fp64",
-               workspace_budget: int = 0,
+               mixed_min_q: int | None = None, workspace_budget: int = 0,
                warm_Lambda=None, warm_Theta=None, trace_cap: int | None = None,
                keep_csr: bool = False, kernel_stats: bool = False,
                stream=None) -> SolveResult:
@@ -269,7 +273,7 @@ def cggm_solve(X, Y, lam_Lambda: float, lam_Theta: float, tol: float = 1e-2, *,
                    stall_iters=stall_iters, sweep=sweep, tile=tile,
                    lambda_passes=lambda_passes, precision=precision,
                    workspace_budget=workspace_budget, warm_Lambda=warm_Lambda,
-                   warm_Theta=warm_Theta)
+                   warm_Theta=warm_Theta, mixed_min_q=mixed_min_q)
     cap = (max_iter + 1) if trace_cap is None else trace_cap
     trace_buf = (TraceEntry * max(cap, 1))()
     opt.trace = ctypes.cast(trace_buf, ctypes.POINTER(TraceEntry)) if cap > 0 else None
@@ -300,7 +304,8 @@ def cggm_solve_path(X, Y, lam_Lambda, lam_Theta, tol: float = 1e-2, *,
                     max_iter: int = 500, max_ls: int = 30, ls_beta: float = 0.5,
                     ls_sigma: float = 1e-3, stall_iters: int = 3,
                     sweep: int = CGGM_SWEEP_TILED, tile: int = 0, lambda_passes: int = 4,
-                    precision: str = "fp64", workspace_budget: int = 0, warm_Lambda=None,
+                    precision: str = "fp64", mixed_min_q: int | None = None,
+                    workspace_budget: int = 0, warm_Lambda=None,
                     warm_Theta=None, trace_cap: int | None = None, keep_csr: bool = False,
                     stream=None) -> list:
     """Warm-started regularisation path: one SolveResult per (lam_Lambda[k], lam_Theta[k])."""
@@ -316,7 +321,7 @@ def cggm_solve_path(X, Y, lam_Lambda, lam_Theta, tol: float = 1e-2, *,
                    stall_iters=stall_iters, sweep=sweep, tile=tile,
                    lambda_passes=lambda_passes, precision=precision,
                    workspace_budget=workspace_budget, warm_Lambda=warm_Lambda,
-                   warm_Theta=warm_Theta)
+                   warm_Theta=warm_Theta, mixed_min_q=mixed_min_q)
     cap = npath * (max_iter + 1) if trace_cap is None else trace_cap
     trace_buf = (TraceEntry * max(cap, 1))()
     opt.trace = ctypes.cast(trace_buf, ctypes.POINTER(TraceEntry)) if cap > 0 else None
@@ -397,7 +402,7 @@ class Server:
 
     def submit(self, X, Y, lam_Lambda, lam_Theta, tol: float = 1e-2, *,
                precision: str = "fp64", max_iter: int = 0, lambda_passes: int = 0,
-               Lambda_out=None, Theta_out=None) -> int:
+               mixed_min_q: int | None = None, Lambda_out=None, Theta_out=None) -> int:
         n, p = X.shape
         q = Y.shape[1]
         lamL = np.ascontiguousarray(lam_Lambda, dtype=np.float64).ravel()
@@ -411,6 +416,7 @@ class Server:
         r.lamL, r.lamT = lamL.ctypes.data_as(_dp), lamT.ctypes.data_as(_dp)
         r.tol, r.precision = float(tol), PRECISIONS[precision]
         r.max_iter, r.lambda_passes = int(max_iter), int(lambda_passes)
+        r.mixed_min_q = -1 if mixed_min_q is None else int(mixed_min_q)
         for t, name, shape in ((Lambda_out, "Lambda_out", (npath, q, q)),
                                (Theta_out, "Theta_out", (npath, p, q))):
             if t is not None and tuple(t.shape) != shape:

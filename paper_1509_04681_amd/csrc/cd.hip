@@ -513,7 +513,9 @@ __device__ void rowblock_update(const double *__restrict__ Delta, bool trans, in
 // rowblock_update from FP32 S and Out (row lengths multiples of 4, columns up
 // to c_end, itself a multiple of 4): each wave owns 64 consecutive columns as
 // 4 MFMA blocks j with the columns {4 c + j}, so a lane reads and writes four
-// consecutive floats of a row; FP32 accumulation.  All BLOCK threads call it.
+// consecutive floats of a row; the S rows stream in groups of four k-steps
+// whose loads are all issued before their products; FP32 accumulation.  All
+// BLOCK threads call it.
 template <int TR, int TK>
 __device__ void rowblock_update32(const double *__restrict__ Delta, bool trans, int R, int Kd,
                                   const float *__restrict__ S, int64_t lds,
@@ -544,17 +546,25 @@ __device__ void rowblock_update32(const double *__restrict__ Delta, bool trans, 
 #pragma unroll
                 for (int j = 0; j < 4; ++j) acc[i][j][r] = v[j];
             }
-#pragma unroll 2
-        for (int ks = 0; ks < TK / 4; ++ks) {
-            const int k = ks * 4 + krow;
-            const f32x4 bv = (nv && k < Kd)
-                                 ? *reinterpret_cast<const f32x4 *>(S + (int64_t)k * lds + n)
-                                 : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+        for (int h = 0; h < TK / 4 / 4; ++h) {
+            f32x4 bvs[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float av = dl[k][i * 16 + col];
+            for (int u = 0; u < 4; ++u) {
+                const int k = (h * 4 + u) * 4 + krow;
+                bvs[u] = (nv && k < Kd) ? *reinterpret_cast<const f32x4 *>(S + (int64_t)k * lds + n)
+                                        : f32x4{0.f, 0.f, 0.f, 0.f};
+            }
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = mfma_f32_16x16x4(av, bv[j], acc[i][j]);
+            for (int u = 0; u < 4; ++u) {
+                const int k = (h * 4 + u) * 4 + krow;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float av = dl[k][i * 16 + col];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        acc[i][j] = mfma_f32_16x16x4(av, bvs[u][j], acc[i][j]);
+                }
             }
         }
         if (nv) {
@@ -868,9 +878,10 @@ __global__ __launch_bounds__(BLOCK, UPD_MINB) void lambda_u_update_kernel(
 }
 
 // The updates on FP32 copies (row length ld): V32[I, :] += dTheta Sigma32[J, :];
-// U32 as lambda_u_update_kernel.  UPD32_COLS columns per workgroup.
-constexpr int UPD32_COLS = 1024;
-__global__ __launch_bounds__(BLOCK, UPD_MINB) void theta_v_update32_kernel(
+// U32 as lambda_u_update_kernel.  UPD32_COLS columns per workgroup; built for
+// three workgroups per CU (the register budget of the four-k-step groups).
+constexpr int UPD32_COLS = 1024, UPD32_MINB = 3;
+__global__ __launch_bounds__(BLOCK, UPD32_MINB) void theta_v_update32_kernel(
     const TileRect *__restrict__ rects, int64_t ld, const float *__restrict__ Sigma,
     const double *__restrict__ dT, const int *__restrict__ changed, float *__restrict__ V) {
     const int e = blockIdx.y;
@@ -884,7 +895,7 @@ __global__ __launch_bounds__(BLOCK, UPD_MINB) void theta_v_update32_kernel(
                               ld, V + (int64_t)rc.r0 * ld, ld, c_begin, c_end, dl);
 }
 
-__global__ __launch_bounds__(BLOCK, UPD_MINB) void lambda_u_update32_kernel(
+__global__ __launch_bounds__(BLOCK, UPD32_MINB) void lambda_u_update32_kernel(
     const TileRect *__restrict__ rects, int64_t ld, const float *__restrict__ Sigma,
     const double *__restrict__ dD, const int *__restrict__ changed, float *__restrict__ U) {
     const int e = blockIdx.y, half = blockIdx.z;

@@ -215,7 +215,7 @@ constexpr int NSCAL = 64;
 
 // Layout of the workspace; with a.measure it only sizes it.
 void layout(Arena &a, Work &w, int64_t n, int64_t p, int64_t q, int64_t ntheta_rects,
-            int64_t nlambda_rects, int max_tiles, bool mixed = false) {
+            int64_t nlambda_rects, int max_tiles, bool mixed = false, bool f32 = false) {
     const int64_t qq = q * q, pq = p * q, nq = n * q;
     w.n = n, w.p = p, w.q = q;
     w.Sxx = a.take<double>(p * p);
@@ -257,6 +257,8 @@ void layout(Arena &a, Work &w, int64_t n, int64_t p, int64_t q, int64_t ntheta_r
     if (mixed) {
         w.split_Th = a.take<__bf16>(3 * p * split3_stride(q));
         w.split_Sig = a.take<__bf16>(3 * q * split3_stride(q));
+    }
+    if (f32) {
         const int64_t lq = f32_ld(q), lp = f32_ld(p);
         w.SP32 = a.take<float>(q * lq);
         w.Psi32 = a.take<float>(q * lq);
@@ -284,7 +286,8 @@ struct Ctx {
     hipStream_t s;
     Work &w;
     double lamL, lamT;
-    bool mixed = false;
+    bool mixed = false;   // split-BF16 V and FP32 sweep operands
+    bool f32() const { return mixed && w.Sig32 != nullptr; }
 };
 
 // V = Theta Sigma: FP64 MFMA, or in mixed mode from the BF16 pieces of Theta
@@ -298,13 +301,16 @@ void theta_sigma(Ctx &c) {
     }
     split3(c.s, w.p, w.q, w.Th, w.q, w.split_Th);
     split3(c.s, w.q, w.q, w.Sig, w.q, w.split_Sig);
-    gemm_split3_nt(c.s, w.p, w.q, w.q, w.split_Th, w.split_Sig, w.V32, f32_ld(w.q));
+    if (c.f32())
+        gemm_split3_nt(c.s, w.p, w.q, w.q, w.split_Th, w.split_Sig, w.V32, f32_ld(w.q));
+    else
+        gemm_split3_nt(c.s, w.p, w.q, w.q, w.split_Th, w.split_Sig, w.V, w.q);
 }
 
 // Operands of a sweep in the current precision.
 SweepF32 sweep_operands(const Ctx &c) {
     SweepF32 f;
-    if (!c.mixed) return f;
+    if (!c.f32()) return f;
     const Work &w = c.w;
     f.on = true;
     f.ldq = f32_ld(w.q);
@@ -322,7 +328,7 @@ SweepF32 sweep_operands(const Ctx &c) {
 void refresh_sigma(Ctx &c) {
     Work &w = c.w;
     spd_inverse_from_cholesky(c.s, w.q, w.L, w.Wd, w.U, w.Sig);
-    if (c.mixed) to_f32(c.s, w.q, w.q, w.Sig, w.q, w.Sig32, f32_ld(w.q));
+    if (c.f32()) to_f32(c.s, w.q, w.q, w.Sig, w.q, w.Sig32, f32_ld(w.q));
 }
 
 // Rounding allowance of an FP64 objective evaluation in the Armijo test and
@@ -358,7 +364,7 @@ void gradients(Ctx &c, const double *X) {
     assemble_lambda_gradient(c.s, w.q, w.Syy, w.Sig, w.Psi, w.GL, w.SP);
     scale_copy(c.s, w.p * w.q, 2.0, w.Sxy, w.GT);
     gemm(c.s, true, false, w.p, w.q, w.n, 2.0 * inv_n, X, w.p, w.R, w.q, 1.0, w.GT, w.q);
-    if (c.mixed) {
+    if (c.f32()) {
         to_f32(c.s, w.q, w.q, w.SP, w.q, w.SP32, f32_ld(w.q));
         to_f32(c.s, w.q, w.q, w.Psi, w.q, w.Psi32, f32_ld(w.q));
     }
@@ -561,7 +567,7 @@ cggm_options checked_options(const cggm_options *opt_in) {
     if (opt_in) opt = *opt_in;
     if (opt.max_iter < 0 || opt.max_ls < 1 || !(opt.ls_beta > 0.0 && opt.ls_beta < 1.0) ||
         !(opt.ls_sigma > 0.0 && opt.ls_sigma < 1.0) || opt.stall_iters < 0 ||
-        opt.lambda_passes < 1 ||
+        opt.lambda_passes < 1 || opt.mixed_min_q < 0 ||
         (opt.precision != CGGM_PRECISION_FP64 && opt.precision != CGGM_PRECISION_MIXED) ||
         (opt.sweep != CGGM_SWEEP_TILED && opt.sweep != CGGM_SWEEP_SEQUENTIAL))
         fail(CGGM_EINVAL, "invalid options");
@@ -590,7 +596,7 @@ struct Solver::Impl {
     Impl(int64_t n_, int64_t p_, int64_t q_, const cggm_options *o, hipStream_t st)
         : n(n_), p(p_), q(q_), opt(checked_options(o)), s(st) {
         check_sizes(n, p, q);
-        mixed = opt.precision == CGGM_PRECISION_MIXED;
+        mixed = opt.precision == CGGM_PRECISION_MIXED && q >= opt.mixed_min_q;
         seq = opt.sweep == CGGM_SWEEP_SEQUENTIAL;
         const auto [tileL, tileT] = tile_edges(opt.tile);
         th_sched = theta_schedule(p, q, tileT, seq);
@@ -615,7 +621,7 @@ struct Solver::Impl {
     }
     void lay(Arena &a) {
         layout(a, w, n, p, q, (int64_t)th_sched.rects.size(), (int64_t)la_sched.rects.size(),
-               max_tiles, mixed);
+               max_tiles, mixed, mixed);
     }
     double ms_since(std::chrono::steady_clock::time_point a) const {
         return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - a)
@@ -660,7 +666,7 @@ struct Solver::Impl {
         }
         t0 = std::chrono::steady_clock::now();
         statistics(c, X, Y);
-        if (mixed) {
+        if (c.f32()) {
             to_f32(s, p, p, w.Sxx, p, w.Sxx32, f32_ld(p));
             fill_f32(s, p * f32_ld(q), 0.0f, w.V32);   // the padding columns stay zero
         }
@@ -1151,6 +1157,7 @@ void cggm_default_options(cggm_options *opt) {
     opt->tile = 0;
     opt->lambda_passes = 4;
     opt->precision = CGGM_PRECISION_FP64;
+    opt->mixed_min_q = 4096;
 }
 
 size_t cggm_solve_workspace_bytes(int64_t n, int64_t p, int64_t q) {

@@ -163,6 +163,7 @@ Job *make_job(const cggm_request *req) {
     j->opt.precision = r.precision;
     if (r.max_iter > 0) j->opt.max_iter = r.max_iter;
     if (r.lambda_passes > 0) j->opt.lambda_passes = r.lambda_passes;
+    if (r.mixed_min_q >= 0) j->opt.mixed_min_q = r.mixed_min_q;
     j->footprint = round_up(solve_footprint(r.n, r.p, r.q, &j->opt));   // validates
     j->f.assign(r.npath, 0.0);
     j->iters.assign(r.npath, 0);

@@ -77,6 +77,10 @@ def test_argument_errors_without_device(lib):
     opt.lambda_passes = 0
     assert lib.cggm_solve(fake, fake, 4, 3, 2, 0.1, 0.1, 0.01, ctypes.byref(opt),
                           ctypes.byref(r), None) == m.CGGM_EINVAL
+    lib.cggm_default_options(ctypes.byref(opt))
+    opt.mixed_min_q = -1
+    assert lib.cggm_solve(fake, fake, 4, 3, 2, 0.1, 0.1, 0.01, ctypes.byref(opt),
+                          ctypes.byref(r), None) == m.CGGM_EINVAL
 
 
 def test_workspace_budget_is_checked_before_allocation(lib):
@@ -103,6 +107,7 @@ def test_default_options(lib):
     assert opt.sweep == m.CGGM_SWEEP_TILED
     assert opt.lambda_passes == 4
     assert opt.precision == m.CGGM_PRECISION_FP64
+    assert opt.mixed_min_q == 4096
 
 
 def test_path_and_workspace_arguments_without_device(lib):
@@ -124,7 +129,15 @@ def test_path_and_workspace_arguments_without_device(lib):
     # footprints: the mixed mode adds the BF16 planes; invalid options give 0
     fp64 = m.cggm_workspace_bytes(300, 200, 100)
     assert fp64 == m.cggm_solve_workspace_bytes(300, 200, 100)
-    assert m.cggm_workspace_bytes(300, 200, 100, "mixed") >= fp64 + 2 * 3 * (200 + 100) * 128
+    # the mixed mode's buffers (BF16 pieces, FP32 sweep copies) only from q = 4096 on
+    opt = m.Options()
+    lib.cggm_default_options(ctypes.byref(opt))
+    opt.precision = m.CGGM_PRECISION_MIXED
+    small = lib.cggm_workspace_bytes(300, 200, 100, ctypes.byref(opt))
+    assert small == fp64
+    opt.mixed_min_q = 0
+    forced = lib.cggm_workspace_bytes(300, 200, 100, ctypes.byref(opt))
+    assert forced - small >= 4 * (4 * 100 * 100 + 200 * 200 + 200 * 100)
     opt = m.Options()
     lib.cggm_default_options(ctypes.byref(opt))
     opt.lambda_passes = 0

@@ -338,16 +338,18 @@ def test_chain2k_converged_solve_is_certified(cg):
     assert np.all(np.linalg.eigvalsh(Lg) > 0)
 
 
+@pytest.mark.parametrize("mixed_min_q", [0, None], ids=["mixed", "default"])
 @pytest.mark.parametrize("name", ["chain40", "chain530"])
-def test_mixed_precision_reaches_the_oracle_optimum(cg, name):
-    """Mixed mode (V = Theta Sigma from split-BF16 products, everything that
-    decides the objective in FP64): the converged objective is within 1e-6 of
-    the oracle's f* and the supports {|x| > 1e-6} agree outside the
-    borderline band."""
+def test_mixed_precision_reaches_the_oracle_optimum(cg, name, mixed_min_q):
+    """Mixed mode (V = Theta Sigma from split-BF16 products and FP32 copies in
+    the CD sweeps; everything that decides the objective in FP64), forced on
+    these small problems with mixed_min_q = 0 (the default runs q < 4096 in
+    FP64): the converged objective is within 1e-6 of the oracle's f* and the
+    supports {|x| > 1e-6} agree outside the borderline band."""
     g0 = load_golden(name)
     pr = synth.workload(name)
     g = cg.cggm_solve(dev(pr.X), dev(pr.Y), pr.lam_Lambda, pr.lam_Theta, tol=0.0,
-                      max_iter=5000, precision="mixed")
+                      max_iter=5000, precision="mixed", mixed_min_q=mixed_min_q)
     Lg, Tg = g.Lambda.cpu().numpy(), g.Theta.cpu().numpy()
     sL, sT = np.abs(Lg) > SUPPORT_EPS, np.abs(Tg) > SUPPORT_EPS
     mL = int(np.sum((sL != g0["support_Lambda"]) & ~g0["borderline_Lambda"]))
@@ -359,13 +361,15 @@ def test_mixed_precision_reaches_the_oracle_optimum(cg, name):
     assert mL == 0 and mT == 0
 
 
-def test_mixed_precision_iterates_track_fp64(cg):
+@pytest.mark.parametrize("mixed_min_q", [0, None], ids=["mixed", "default"])
+def test_mixed_precision_iterates_track_fp64(cg, mixed_min_q):
     """The first iterations of a mixed solve stay close to the FP64 ones (the
-    split product only perturbs the Theta pass)."""
+    split product and the FP32 sweep operands only perturb the directions)."""
     pr = synth.workload("chain530")
     kw = dict(tol=0.0, max_iter=8, stall_iters=0)
     a = cg.cggm_solve(dev(pr.X), dev(pr.Y), pr.lam_Lambda, pr.lam_Theta, **kw)
-    b = cg.cggm_solve(dev(pr.X), dev(pr.Y), pr.lam_Lambda, pr.lam_Theta, precision="mixed", **kw)
+    b = cg.cggm_solve(dev(pr.X), dev(pr.Y), pr.lam_Lambda, pr.lam_Theta, precision="mixed",
+                      mixed_min_q=mixed_min_q, **kw)
     fa = np.array([t["f"] for t in a.trace])
     fb = np.array([t["f"] for t in b.trace])
     print("fp64 vs mixed relative differences:", np.abs(fa - fb) / np.abs(fa), flush=True)

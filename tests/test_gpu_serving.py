@@ -101,7 +101,7 @@ def serve(cg, reqs, slots, pool_bytes, precisions, max_bypass=8):
         tickets = []
         for (pr, lL, lT), (X, Y), (Lo, To), prec in zip(reqs, inputs, outs, precisions):
             tickets.append(srv.submit(X, Y, lL, lT, tol=1e-7, precision=prec, max_iter=400,
-                                      Lambda_out=Lo, Theta_out=To))
+                                      mixed_min_q=0, Lambda_out=Lo, Theta_out=To))
         for t in tickets:
             infos.append(srv.wait(t))
         st = srv.stats()
@@ -111,7 +111,7 @@ def serve(cg, reqs, slots, pool_bytes, precisions, max_bypass=8):
 def test_served_results_equal_results_alone(cg):
     import torch
     reqs = stream(10, 100, (60, 400), (60, 400), (200, 600))
-    prec = ["fp64", "mixed"] * 5
+    prec = ["fp64", "mixed"] * 5          # mixed forced at these sizes (mixed_min_q = 0)
     print("requests:", [r[0].name for r in reqs], flush=True)
     mix, infos, st = serve(cg, reqs, slots=4, pool_bytes=2 << 30, precisions=prec)
     print(f"mix stats {st}", flush=True)
@@ -129,7 +129,7 @@ def test_served_results_equal_results_alone(cg):
         # and the one-request server equals the path entry point
         if k < 3:
             path = cg.cggm_solve_path(dev(pr.X), dev(pr.Y), lL, lT, tol=1e-7, max_iter=400,
-                                      precision=prec[k])
+                                      precision=prec[k], mixed_min_q=0)
             assert [r.f for r in path] == info["f"]
             assert all(torch.equal(r.Lambda, mix[k][0][j]) for j, r in enumerate(path))
 
