@@ -513,9 +513,10 @@ __device__ void rowblock_update(const double *__restrict__ Delta, bool trans, in
 // rowblock_update from FP32 S and Out (row lengths multiples of 4, columns up
 // to c_end, itself a multiple of 4): each wave owns 64 consecutive columns as
 // 4 MFMA blocks j with the columns {4 c + j}, so a lane reads and writes four
-// consecutive floats of a row; the S rows stream in groups of four k-steps
-// whose loads are all issued before their products; FP32 accumulation.  All
-// BLOCK threads call it.
+// consecutive floats of a row; the S rows stream in groups of UPD32_GROUP
+// k-steps whose loads are all issued before their products; FP32
+// accumulation.  All BLOCK threads call it.
+constexpr int UPD32_GROUP = 8;
 template <int TR, int TK>
 __device__ void rowblock_update32(const double *__restrict__ Delta, bool trans, int R, int Kd,
                                   const float *__restrict__ S, int64_t lds,
@@ -547,17 +548,17 @@ __device__ void rowblock_update32(const double *__restrict__ Delta, bool trans, 
                 for (int j = 0; j < 4; ++j) acc[i][j][r] = v[j];
             }
 #pragma unroll 1
-        for (int h = 0; h < TK / 4 / 4; ++h) {
-            f32x4 bvs[4];
+        for (int h = 0; h < TK / 4 / UPD32_GROUP; ++h) {
+            f32x4 bvs[UPD32_GROUP];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int k = (h * 4 + u) * 4 + krow;
+            for (int u = 0; u < UPD32_GROUP; ++u) {
+                const int k = (h * UPD32_GROUP + u) * 4 + krow;
                 bvs[u] = (nv && k < Kd) ? *reinterpret_cast<const f32x4 *>(S + (int64_t)k * lds + n)
                                         : f32x4{0.f, 0.f, 0.f, 0.f};
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int k = (h * 4 + u) * 4 + krow;
+            for (int u = 0; u < UPD32_GROUP; ++u) {
+                const int k = (h * UPD32_GROUP + u) * 4 + krow;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const float av = dl[k][i * 16 + col];
@@ -879,7 +880,7 @@ __global__ __launch_bounds__(BLOCK, UPD_MINB) void lambda_u_update_kernel(
 
 // The updates on FP32 copies (row length ld): V32[I, :] += dTheta Sigma32[J, :];
 // U32 as lambda_u_update_kernel.  UPD32_COLS columns per workgroup; built for
-// three workgroups per CU (the register budget of the four-k-step groups).
+// three workgroups per CU (the register budget of the eight-k-step groups).
 constexpr int UPD32_COLS = 1024, UPD32_MINB = 3;
 __global__ __launch_bounds__(BLOCK, UPD32_MINB) void theta_v_update32_kernel(
     const TileRect *__restrict__ rects, int64_t ld, const float *__restrict__ Sigma,
