@@ -56,3 +56,33 @@ def test_samples_follow_the_model():
     np.testing.assert_allclose(B, -pr.Theta_true.toarray() @ Sig, atol=0.01)
     res = pr.Y - pr.X @ B
     np.testing.assert_allclose(res.T @ res / pr.n, Sig, atol=0.01)
+
+
+def test_stream_problems_and_penalty_path():
+    """Request-stream generator: shapes in range, both Lambda kinds, diagonally
+    dominant random-sparse Lambda of mean degree 4; the first point of the
+    penalty path is where the optimum has Theta = 0 and a diagonal Lambda
+    (checked with the oracle), later points move off it."""
+    import oracle
+    oracle.build()
+    kinds = set()
+    for seed in range(6):
+        pr = synth.stream_problem(seed, p_range=(20, 40), q_range=(15, 30), n_range=(60, 90))
+        assert 20 <= pr.p <= 40 and 15 <= pr.q <= 30 and 60 <= pr.n <= 90
+        L = pr.Lambda_true.toarray()
+        off = L - np.diag(np.diag(L))
+        assert np.all(np.diag(L) > np.abs(off).sum(axis=1))
+        kinds.add(pr.name.split("-")[0])
+    assert kinds == {"chain", "random"}
+    q = 400
+    A = synth.random_sparse_lambda(q, np.random.default_rng(1)).toarray()
+    assert (np.count_nonzero(A - np.diag(np.diag(A))) // 2) == 2 * q
+    pr = synth.stream_problem(11, p_range=(12, 12), q_range=(8, 8), n_range=(80, 80))
+    lL, lT = synth.penalty_path(pr.X, pr.Y, points=5, ratio=0.1)
+    assert np.all(np.diff(lL) < 0) and abs(lL[-1] / lL[0] - 0.1) < 1e-12
+    r0 = oracle.solve(pr.X, pr.Y, lL[0] * (1 + 1e-9), lT[0] * (1 + 1e-9), tol=0.0,
+                      max_iter=300, stall_iters=3)
+    assert np.abs(r0.Theta).max() == 0.0
+    assert np.abs(r0.Lambda - np.diag(np.diag(r0.Lambda))).max() == 0.0
+    r4 = oracle.solve(pr.X, pr.Y, lL[-1], lT[-1], tol=0.0, max_iter=300, stall_iters=3)
+    assert np.abs(r4.Theta).max() > 0.0
