@@ -744,19 +744,27 @@ SolveOutcome Solver::Impl::run(double lamL, double lamT, double tol) {
         CGGM_HIP(hipEventRecord(ev[1], s));
         top = read_top(c, true);
         kt_theta.collect();                       // the last Theta sweep is done
-        const double theta_guard = swept_mixed ? 1e-10 : F_ROUNDING;
-        if (t > 0 && top.f > f_after_ls + theta_guard * std::max(1.0, fabs(f_after_ls))) {
-            // Descent guard: the concurrent tiles of the Theta sweep raised f.
-            // Redo the sweep one tile per wave (exact block Gauss-Seidel).
+        // Descent guard: the Theta sweep must not raise f.  A sweep steered by
+        // the mixed-precision operands is redone as the same tiled sweep in
+        // FP64 (and the run stays in FP64); a tiled FP64 sweep that raised f
+        // (concurrent tiles) is redone one tile per wave (exact block
+        // Gauss-Seidel; at q = 20000 that takes about a minute).
+        while (t > 0) {
+            const double theta_guard = swept_mixed ? 1e-10 : F_ROUNDING;
+            if (!(top.f > f_after_ls + theta_guard * std::max(1.0, fabs(f_after_ls)))) break;
             CGGM_HIP(hipMemcpyAsync(w.Th, w.ThOld, sizeof(double) * pq, hipMemcpyDeviceToDevice,
                                     s));
+            const bool to_fp64 = swept_mixed;
+            c.mixed = false;
+            swept_mixed = false;
             theta_sigma(c);
-            run_theta_sweep(c, th_safe);
+            run_theta_sweep(c, to_fp64 ? th_sched : th_safe);
             ++last_fallbacks;
             theta_products(c, X);
             evaluate();
             CGGM_HIP(hipEventRecord(ev[1], s));
             top = read_top(c, true);
+            if (!to_fp64) break;
         }
         if (opt.trace && trace_len < opt.trace_cap) {
             cggm_trace_entry &te = opt.trace[trace_len++];
@@ -826,15 +834,21 @@ SolveOutcome Solver::Impl::run(double lamL, double lamT, double tol) {
         CGGM_HIP(hipStreamSynchronize(s));
         kt_lambda.collect();
         double delta = hd[0] + lamL * hd[1];
-        if (!(delta < 0.0) && !seq) {
-            // Descent guard: redo the direction one tile per wave.
+        // Descent guard: the direction must have delta < 0 (Armijo needs it).
+        // A direction from the mixed-precision operands is redone as the same
+        // tiled sweep in FP64 (and the run stays in FP64); a tiled FP64
+        // direction is redone one tile per wave.
+        while (!(delta < 0.0) && !seq) {
+            const bool to_fp64 = c.mixed;
+            c.mixed = false;
             for (int pass = 0; pass < opt.lambda_passes; ++pass)
-                run_lambda_sweep(c, la_safe, nullptr, pass);
+                run_lambda_sweep(c, to_fp64 ? la_sched : la_safe, nullptr, pass);
             ++last_fallbacks;
             reduce_direction(s, q, w.GL, w.Lam, w.D, w.partials, w.scal + S_DIR);
             CGGM_HIP(hipMemcpyAsync(hd, w.scal + S_DIR, sizeof(hd), hipMemcpyDeviceToHost, s));
             CGGM_HIP(hipStreamSynchronize(s));
             delta = hd[0] + lamL * hd[1];
+            if (!to_fp64) break;
         }
         CGGM_HIP(hipEventRecord(ev[3], s));
         double alpha = 0.0, f_acc = top.f;
