@@ -9,6 +9,7 @@
 #include <string>
 
 #include "cggm.h"
+#include "tile_rect.hpp"
 
 namespace cggm {
 
@@ -151,9 +152,6 @@ void gemm_split3_nt(hipStream_t s, int64_t M, int64_t N, int64_t K, const __bf16
                     const __bf16 *Bp, float *C, int64_t ldc);
 
 // ---------------------------------------------------------------- cd.hip ---
-struct TileRect {
-    int32_t r0, r1, c0, c1;   // rows [r0, r1), columns [c0, c1)
-};
 
 constexpr int LAMBDA_TILE = 64;   // tile edge of the Lambda CD tiles
 constexpr int THETA_TILE = 64;    // tile edge of the Theta CD tiles

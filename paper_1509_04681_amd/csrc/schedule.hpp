@@ -1,0 +1,102 @@
+// schedule.hpp -- wave schedules of the tiled coordinate-descent sweeps.
+// Plain host C++ (no HIP), so the schedules can be tested on their own.
+//
+// A sweep is a list of waves; the tiles of one wave run concurrently, so the
+// rows of the maintained product they update must be disjoint: a Theta tile
+// (I, J) updates V[I, :] and reads Sigma[J, :] (waves row- and
+// column-disjoint), a Lambda tile (I, J) updates U[I, :] and U[J, :] (the
+// index blocks of a wave pairwise disjoint).
+#pragma once
+
+#include <stdint.h>
+
+#include <algorithm>
+#include <utility>
+#include <vector>
+
+#include "tile_rect.hpp"
+
+namespace cggm {
+
+// Wave schedules of the coordinate-descent sweeps (host lists of rects with
+// offsets of each wave; uploaded once per solve).
+struct Schedule {
+    std::vector<TileRect> rects;
+    std::vector<int> wave_start;   // wave w = rects[wave_start[w], wave_start[w+1])
+    int max_wave = 0;
+    int waves() const { return (int)wave_start.size() - 1; }
+    void finish_wave() {
+        const int prev = wave_start.empty() ? 0 : wave_start.back();
+        max_wave = std::max(max_wave, (int)rects.size() - prev);
+        wave_start.push_back((int)rects.size());
+    }
+};
+
+inline TileRect rect(int64_t r0, int64_t r1, int64_t c0, int64_t c1) {
+    return TileRect{(int32_t)r0, (int32_t)r1, (int32_t)c0, (int32_t)c1};
+}
+
+// Theta: tile (I, J) belongs to wave (J - I) mod W, W = max(#row blocks,
+// #column blocks); each wave is row- and column-disjoint.
+inline Schedule theta_schedule(int64_t p, int64_t q, int tile, bool sequential) {
+    Schedule s;
+    s.wave_start.push_back(0);
+    if (sequential) {
+        for (int64_t i = 0; i < p; ++i)
+            for (int64_t j = 0; j < q; ++j) {
+                s.rects.push_back(rect(i, i + 1, j, j + 1));
+                s.finish_wave();
+            }
+        return s;
+    }
+    const int64_t P = (p + tile - 1) / tile, Q = (q + tile - 1) / tile, W = std::max(P, Q);
+    for (int64_t w = 0; w < W; ++w) {
+        for (int64_t I = 0; I < P; ++I) {
+            const int64_t J = (I + w) % W;
+            if (J >= Q) continue;
+            s.rects.push_back(rect(I * tile, std::min(p, (I + 1) * tile), J * tile,
+                                   std::min(q, (J + 1) * tile)));
+        }
+        s.finish_wave();
+    }
+    return s;
+}
+
+// Lambda: first the wave of all diagonal tiles, then the rounds of a
+// round-robin pairing of the column blocks (each block once per round).
+inline Schedule lambda_schedule(int64_t q, int tile, bool sequential) {
+    Schedule s;
+    s.wave_start.push_back(0);
+    if (sequential) {
+        for (int64_t i = 0; i < q; ++i)
+            for (int64_t j = i; j < q; ++j) {
+                s.rects.push_back(rect(i, i + 1, j, j + 1));
+                s.finish_wave();
+            }
+        return s;
+    }
+    const int64_t Q = (q + tile - 1) / tile;
+    auto blk = [&](int64_t I, int64_t J) {
+        return rect(I * tile, std::min(q, (I + 1) * tile), J * tile, std::min(q, (J + 1) * tile));
+    };
+    for (int64_t I = 0; I < Q; ++I) s.rects.push_back(blk(I, I));
+    s.finish_wave();
+    const int64_t n = Q + (Q & 1);             // even number of slots (one bye if Q odd)
+    for (int64_t r = 0; r + 1 < n; ++r) {
+        std::vector<std::pair<int64_t, int64_t>> pairs;
+        pairs.push_back({r, n - 1});
+        for (int64_t k = 1; k < n / 2; ++k)
+            pairs.push_back({(r + k) % (n - 1), (r - k + (n - 1)) % (n - 1)});
+        bool any = false;
+        for (auto [a, b] : pairs) {
+            if (a >= Q || b >= Q) continue;     // bye
+            const int64_t I = std::min(a, b), J = std::max(a, b);
+            s.rects.push_back(blk(I, J));
+            any = true;
+        }
+        if (any) s.finish_wave();
+    }
+    return s;
+}
+
+}  // namespace cggm
