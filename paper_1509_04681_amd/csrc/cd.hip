@@ -71,8 +71,8 @@ __global__ __launch_bounds__(BLOCK) void tile_activity_kernel(const TileRect *__
 // ----------------------------------------------------------------- snapshot --
 // Operand pairs of the snapshot products: out[m][n] += sum_k A[k][r0 + m] B[k][c0 + n]
 // (A, B symmetric or stored so that the tile's rows/columns are column slabs).
-// The operands are FP64, or FP32 copies in the mixed mode (converted to FP64
-// in registers; the products accumulate in FP64).
+// E = double for snapshot_kernel (FP64 matrix cores, FP64 accumulation) and
+// E = float for snapshot32_kernel (the FP32 copies of the mixed mode).
 template <int NPAIR, class E>
 struct SnapArgs {
     const E *A[NPAIR];
@@ -453,8 +453,8 @@ __global__ __launch_bounds__(BLOCK) void theta_gs_kernel(
 // every 64-column chunk, loads its S operands straight from global memory (one
 // 128-byte row segment per k-step) and read-modify-writes Out from the MFMA
 // accumulators.  All BLOCK threads call it.
-// S and Out are FP64, or FP32 copies in the mixed mode (the products
-// accumulate in FP64 either way).
+// Instantiated with E = double; the mixed mode's FP32 rows use
+// rowblock_update32.
 template <int TR, int TK, class E>
 __device__ void rowblock_update(const double *__restrict__ Delta, bool trans, int R, int Kd,
                                 const E *__restrict__ S, int64_t lds,

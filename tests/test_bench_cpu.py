@@ -1,6 +1,5 @@
 """Host logic of bench.py: the roofline entry, the traffic summary lookup and
 the extrapolated optimum of the full-size time-to-tolerance leg."""
-import hashlib
 import os
 import sys
 
@@ -39,10 +38,22 @@ def test_traffic_summary_matches_the_current_source():
             key, v = line[5:].split("-->")[0].strip().split("=", 1)
             vals[key.strip()] = v.strip()
     src = os.path.join(ROOT, "paper_1509_04681_amd", "csrc", "cd.hip")
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    digest = bench.code_digest(src)
     got = bench.measured_traffic(vals["kernel"])
-    if vals["cd_hip_sha256"] == digest:
+    if vals["cd_hip_code_sha256"] == digest:
         assert got == float(vals["bytes_per_launch"])
     else:
         assert got is None
     assert bench.measured_traffic("no_such_kernel") is None
+
+
+def test_code_digest_ignores_comments_and_whitespace_only(tmp_path):
+    import bench
+    a = tmp_path / "a.hip"
+    b = tmp_path / "b.hip"
+    c = tmp_path / "c.hip"
+    a.write_text('int f(int x) {  // one\n  return x + 1; /* two */ }\nconst char *s = "// kept";\n')
+    b.write_text('// header\nint f(int x) {\n    return x + 1;\n}\nconst char *s = "// kept";\n')
+    c.write_text('int f(int x) { return x + 2; }\nconst char *s = "// kept";\n')
+    assert bench.code_digest(str(a)) == bench.code_digest(str(b))
+    assert bench.code_digest(str(a)) != bench.code_digest(str(c))
