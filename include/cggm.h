@@ -159,12 +159,18 @@ typedef struct cggm_result cggm_result;   /* opaque, owns device CSR arrays */
  *   1. factors Lambda = L L^T, forms Sigma = Lambda^{-1}, log det Lambda,
  *      R = X Theta Sigma, Psi = R^T R / n and the gradients of Eq. (3),
  *   2. screens the active sets |grad| > lambda or param != 0 (Sec. 2.2),
- *   3. finds the generalized Newton direction D of Eq. (6) by one
- *      coordinate-descent pass over S_Lambda, maintaining U = D Sigma,
+ *   3. finds the generalized Newton direction D of Eq. (6) by
+ *      options.lambda_passes coordinate-descent passes over S_Lambda (the
+ *      paper makes one), maintaining U = D Sigma,
  *   4. takes the Armijo step Lambda + alpha D that keeps Lambda positive
  *      definite (Algorithm 1, line search),
  *   5. minimises Eq. (7) over Theta by one coordinate-descent pass over
  *      S_Theta, maintaining V = Theta Sigma (Sec. 3.2).
+ * The passes run as waves of 64 x 64 tiles whose maintained-product rows are
+ * disjoint (exact Gauss-Seidel inside a tile, concurrent across the tiles of
+ * a wave), or one coordinate at a time with CGGM_SWEEP_SEQUENTIAL; a
+ * direction with no descent, or a Theta pass that raises f, is redone (in
+ * FP64 after a mixed-precision pass, else one tile per wave).
  * It stops when ||grad^S||_1 < tol (||Lambda||_1 + ||Theta||_1) (the paper's
  * stopping rule of Sec. 5.1 with 0.01 replaced by tol), when the iterate stops
  * moving (stall_iters), or after max_iter iterations (CGGM_MAXITER).

@@ -2,8 +2,9 @@
 // coordinate descent solver (McCarter & Kim, AISTATS 2016, Algorithm 1).
 //
 // Control stays on the host; every arithmetic step runs in the kernels of
-// la.hip and cd.hip on the caller's stream.  The host reads back only scalars:
-// the top-of-iteration statistics, the line-search quantities of each trial.
+// la.hip, cd.hip and mixed.hip on the caller's stream.  The host reads back
+// only scalars: the top-of-iteration statistics, the direction's decrease and
+// the line-search quantities of each trial.
 #include <math.h>
 #include <string.h>
 
