@@ -74,8 +74,9 @@ extern "C" {
 typedef struct {
     int iter;
     int ls_trials;        /* Cholesky trials in the line search                 */
-    int sweep_fallbacks;  /* sweeps redone tile-sequentially by the descent guard */
-    int _pad;
+    int sweep_fallbacks;  /* sweeps redone by the descent guards               */
+    int sweep_split;      /* waves run as 2^(x & 255) (Lambda) and 2^(x >> 8)
+                             (Theta) sub-waves in this iteration              */
     double f;             /* objective at the top of the iteration (FP64)       */
     double subgrad_l1;    /* l1 norm of the minimum-norm subgradient            */
     double l1;            /* ||Lambda||_1 + ||Theta||_1                          */
@@ -168,9 +169,12 @@ typedef struct cggm_result cggm_result;   /* opaque, owns device CSR arrays */
  *      S_Theta, maintaining V = Theta Sigma (Sec. 3.2).
  * The passes run as waves of 64 x 64 tiles whose maintained-product rows are
  * disjoint (exact Gauss-Seidel inside a tile, concurrent across the tiles of
- * a wave), or one coordinate at a time with CGGM_SWEEP_SEQUENTIAL; a
- * direction with no descent, or a Theta pass that raises f, is redone (in
- * FP64 after a mixed-precision pass, else one tile per wave).
+ * a wave), or one coordinate at a time with CGGM_SWEEP_SEQUENTIAL.  A
+ * direction with no descent, or a Theta pass that raises f, is redone: in
+ * FP64 after a mixed-precision pass, else with each wave split into twice as
+ * many sub-waves (up to 64), else one tile per wave; a Lambda step shrunk
+ * below 1/8 by the line search also doubles the split, three full steps in
+ * a row halve it.
  * It stops when ||grad^S||_1 < tol (||Lambda||_1 + ||Theta||_1) (the paper's
  * stopping rule of Sec. 5.1 with 0.01 replaced by tol), when the iterate stops
  * moving (stall_iters), or after max_iter iterations (CGGM_MAXITER).

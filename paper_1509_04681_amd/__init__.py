@@ -34,7 +34,7 @@ _vp = ctypes.c_void_p
 
 class TraceEntry(ctypes.Structure):
     _fields_ = [("iter", ctypes.c_int), ("ls_trials", ctypes.c_int),
-                ("sweep_fallbacks", ctypes.c_int), ("_pad", ctypes.c_int),
+                ("sweep_fallbacks", ctypes.c_int), ("sweep_split", ctypes.c_int),
                 ("f", ctypes.c_double), ("subgrad_l1", ctypes.c_double),
                 ("l1", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("m_Lambda", ctypes.c_int64), ("m_Theta", ctypes.c_int64),

@@ -503,6 +503,10 @@ struct Solver::Impl {
     bool mixed, seq;
     hipStream_t s;
     Schedule th_sched, la_sched, th_safe, la_safe;   // *_safe: one tile per wave
+    // th_sched / la_sched with every wave split into 2^level sub-waves
+    // (level 1 .. MAX_SPLIT_LEVEL), built on first use.
+    static constexpr int MAX_SPLIT_LEVEL = 6;
+    std::vector<std::unique_ptr<Schedule>> th_split, la_split;
     int max_tiles = 1;
     size_t bytes = 0;
     DeviceBuffer own;
@@ -543,6 +547,13 @@ struct Solver::Impl {
     void lay(Arena &a) {
         layout(a, w, n, p, q, (int64_t)th_sched.rects.size(), (int64_t)la_sched.rects.size(),
                max_tiles, mixed, mixed);
+    }
+    const Schedule &split_sched(std::vector<std::unique_ptr<Schedule>> &cache,
+                                const Schedule &base, int level) {
+        if (level == 0 || seq) return base;
+        if ((int)cache.size() <= level) cache.resize(level + 1);
+        if (!cache[level]) cache[level] = std::make_unique<Schedule>(split_waves(base, 1 << level));
+        return *cache[level];
     }
     double ms_since(std::chrono::steady_clock::time_point a) const {
         return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - a)
@@ -643,6 +654,16 @@ SolveOutcome Solver::Impl::run(double lamL, double lamT, double tol) {
     bool swept_mixed = c.mixed;
     const int64_t qq = q * q, pq = p * q;
 
+    // Concurrency of the tiled sweeps: each wave runs as 2^level sub-waves
+    // whose tiles see the updates of the earlier sub-waves (Jacobi across the
+    // tiles of one sub-wave, exact Gauss-Seidel inside a tile).  With many
+    // strongly coupled tiles per wave the concurrent (Jacobi) part can give a
+    // poor or even divergent direction, so a direction without descent, a
+    // Theta sweep that raised f, or a Lambda step the line search had to
+    // shrink below SMALL_STEP raises the level; three full steps (three
+    // Theta sweeps that pass the guard) in a row lower it again.
+    constexpr double SMALL_STEP = 0.125;
+    int la_level = 0, th_level = 0, la_good = 0, th_good = 0;
     int status = CGGM_MAXITER, stalled = 0, t = 0, ls_fail_streak = 0;
     double sg_best = INFINITY, f_prev = INFINITY, f_after_ls = INFINITY;
     bool have_phase = false;
@@ -666,27 +687,40 @@ SolveOutcome Solver::Impl::run(double lamL, double lamT, double tol) {
         top = read_top(c, true);
         kt_theta.collect();                       // the last Theta sweep is done
         // Descent guard: the Theta sweep must not raise f.  A sweep steered by
-        // the mixed-precision operands is redone as the same tiled sweep in
-        // FP64 (and the run stays in FP64); a tiled FP64 sweep that raised f
-        // (concurrent tiles) is redone one tile per wave (exact block
-        // Gauss-Seidel; at q = 20000 that takes about a minute).
-        while (t > 0) {
+        // the mixed-precision operands is redone in FP64 at the same level (and
+        // the run stays in FP64); a tiled FP64 sweep that raised f is redone
+        // with its waves split further, and past MAX_SPLIT_LEVEL one tile per
+        // wave (exact block Gauss-Seidel; at q = 20000 about a minute).
+        bool th_fired = false;
+        while (t > 0 && !seq) {
             const double theta_guard = swept_mixed ? 1e-10 : F_ROUNDING;
             if (!(top.f > f_after_ls + theta_guard * std::max(1.0, fabs(f_after_ls)))) break;
+            th_fired = true;
             CGGM_HIP(hipMemcpyAsync(w.Th, w.ThOld, sizeof(double) * pq, hipMemcpyDeviceToDevice,
                                     s));
-            const bool to_fp64 = swept_mixed;
+            const Schedule *sch = &th_safe;
+            if (swept_mixed) {
+                sch = &split_sched(th_split, th_sched, th_level);
+            } else if (th_level < MAX_SPLIT_LEVEL) {
+                ++th_level;
+                sch = &split_sched(th_split, th_sched, th_level);
+            }
             c.mixed = false;
             swept_mixed = false;
             theta_sigma(c);
-            run_theta_sweep(c, to_fp64 ? th_sched : th_safe);
+            run_theta_sweep(c, *sch);
             ++last_fallbacks;
             theta_products(c, X);
             evaluate();
             CGGM_HIP(hipEventRecord(ev[1], s));
             top = read_top(c, true);
-            if (!to_fp64) break;
+            if (sch == &th_safe) break;
         }
+        if (t > 0 && !th_fired && th_level > 0 && ++th_good >= 3) {
+            --th_level;
+            th_good = 0;
+        }
+        if (th_fired) th_good = 0;
         if (opt.trace && trace_len < opt.trace_cap) {
             cggm_trace_entry &te = opt.trace[trace_len++];
             memset(&te, 0, sizeof(te));
@@ -698,6 +732,7 @@ SolveOutcome Solver::Impl::run(double lamL, double lamT, double tol) {
             te.m_Theta = top.mT;
             te.nnz_Lambda = top.nnzL;
             te.nnz_Theta = top.nnzT;
+            te.sweep_split = la_level | (th_level << 8);
             te.t_end_ms = ms_since(t0);
             float ms = 0.f;
             CGGM_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
@@ -742,7 +777,7 @@ SolveOutcome Solver::Impl::run(double lamL, double lamT, double tol) {
         // ---- Lambda: Newton direction by CD passes, Armijo line search -----
         CGGM_HIP(hipEventRecord(ev[2], s));
         for (int pass = 0; pass < opt.lambda_passes; ++pass) {
-            run_lambda_sweep(c, la_sched, &kt_lambda, pass);
+            run_lambda_sweep(c, split_sched(la_split, la_sched, la_level), &kt_lambda, pass);
             if (pass + 1 < opt.lambda_passes && kt_lambda.on()) {
                 // recycle the timing events of this pass
                 CGGM_HIP(hipStreamSynchronize(s));
@@ -756,20 +791,28 @@ SolveOutcome Solver::Impl::run(double lamL, double lamT, double tol) {
         kt_lambda.collect();
         double delta = hd[0] + lamL * hd[1];
         // Descent guard: the direction must have delta < 0 (Armijo needs it).
-        // A direction from the mixed-precision operands is redone as the same
-        // tiled sweep in FP64 (and the run stays in FP64); a tiled FP64
-        // direction is redone one tile per wave.
+        // A direction from the mixed-precision operands is redone in FP64 at
+        // the same level (and the run stays in FP64); a tiled FP64 direction
+        // is redone with its waves split further, and past MAX_SPLIT_LEVEL one
+        // tile per wave.
         while (!(delta < 0.0) && !seq) {
-            const bool to_fp64 = c.mixed;
+            const Schedule *sch = &la_safe;
+            if (c.mixed) {
+                sch = &split_sched(la_split, la_sched, la_level);
+            } else if (la_level < MAX_SPLIT_LEVEL) {
+                ++la_level;
+                la_good = 0;
+                sch = &split_sched(la_split, la_sched, la_level);
+            }
             c.mixed = false;
             for (int pass = 0; pass < opt.lambda_passes; ++pass)
-                run_lambda_sweep(c, to_fp64 ? la_sched : la_safe, nullptr, pass);
+                run_lambda_sweep(c, *sch, nullptr, pass);
             ++last_fallbacks;
             reduce_direction(s, q, w.GL, w.Lam, w.D, w.partials, w.scal + S_DIR);
             CGGM_HIP(hipMemcpyAsync(hd, w.scal + S_DIR, sizeof(hd), hipMemcpyDeviceToHost, s));
             CGGM_HIP(hipStreamSynchronize(s));
             delta = hd[0] + lamL * hd[1];
-            if (!to_fp64) break;
+            if (sch == &la_safe) break;
         }
         CGGM_HIP(hipEventRecord(ev[3], s));
         double alpha = 0.0, f_acc = top.f;
@@ -819,6 +862,15 @@ SolveOutcome Solver::Impl::run(double lamL, double lamT, double tol) {
                 break;
             }
         }
+        if (!seq && accepted) {
+            if (alpha < SMALL_STEP && la_level < MAX_SPLIT_LEVEL) {
+                ++la_level;
+                la_good = 0;
+            } else if (alpha == 1.0 && la_level > 0 && ++la_good >= 3) {
+                --la_level;
+                la_good = 0;
+            }
+        }
         f_after_ls = f_acc;
         last_alpha = alpha;
         last_trials = trials;
@@ -830,7 +882,7 @@ SolveOutcome Solver::Impl::run(double lamL, double lamT, double tol) {
         CGGM_HIP(hipMemcpyAsync(w.ThOld, w.Th, sizeof(double) * pq, hipMemcpyDeviceToDevice, s));
         swept_mixed = c.mixed;
         theta_sigma(c);                                              // V = Theta Sigma
-        run_theta_sweep(c, th_sched, &kt_theta);
+        run_theta_sweep(c, split_sched(th_split, th_sched, th_level), &kt_theta);
         theta_products(c, X);
     }
     SolveOutcome o;

@@ -99,4 +99,25 @@ inline Schedule lambda_schedule(int64_t q, int tile, bool sequential) {
     return s;
 }
 
+// The schedule with every wave split into min(parts, wave size) consecutive
+// sub-waves of near-equal size: the same rects in the same order (so the
+// device copy of the rects serves both), fewer tiles running concurrently.
+inline Schedule split_waves(const Schedule &src, int parts) {
+    Schedule s;
+    s.rects = src.rects;
+    s.wave_start.push_back(0);
+    for (int w = 0; w < src.waves(); ++w) {
+        const int b = src.wave_start[w], m = src.wave_start[w + 1] - b;
+        const int k = std::max(1, std::min(parts, m));
+        for (int i = 1; i <= k; ++i) {
+            const int end = b + (int)((int64_t)m * i / k);
+            if (end > s.wave_start.back()) {
+                s.max_wave = std::max(s.max_wave, end - s.wave_start.back());
+                s.wave_start.push_back(end);
+            }
+        }
+    }
+    return s;
+}
+
 }  // namespace cggm

@@ -17,7 +17,7 @@ printf("info size %zu\n", sizeof(cggm_request_info));
 S(submitted)S(completed)S(rejected)S(max_running)S(pool_bytes)S(peak_bytes_in_use)
 printf("stats size %zu\n", sizeof(cggm_server_stats));
 #define T(f) printf("trace %s %zu\n", #f, offsetof(cggm_trace_entry, f));
-T(iter)T(ls_trials)T(sweep_fallbacks)T(f)T(subgrad_l1)T(l1)T(alpha)T(m_Lambda)T(m_Theta)
+T(iter)T(ls_trials)T(sweep_fallbacks)T(sweep_split)T(f)T(subgrad_l1)T(l1)T(alpha)T(m_Lambda)T(m_Theta)
 T(nnz_Lambda)T(nnz_Theta)T(t_end_ms)T(ms_gradient)T(ms_lambda_cd)T(ms_line_search)T(ms_theta_cd)
 printf("trace size %zu\n", sizeof(cggm_trace_entry));
 #define K(f) printf("kstats %s %zu\n", #f, offsetof(cggm_kernel_stats, f));

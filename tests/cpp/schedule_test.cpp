@@ -102,6 +102,33 @@ static void sequential(int64_t p, int64_t q) {
         for (int64_t j = i; j < q; ++j, ++k) CHECK(l.rects[k].r0 == i && l.rects[k].c0 == j);
 }
 
+static void split(int64_t q, int parts) {
+    const Schedule s = lambda_schedule(q, 64, false);
+    const Schedule t = split_waves(s, parts);
+    check_waves(t);
+    CHECK(t.rects.size() == s.rects.size());
+    for (size_t k = 0; k < s.rects.size(); ++k)                 // same rects, same order
+        CHECK(t.rects[k].r0 == s.rects[k].r0 && t.rects[k].c0 == s.rects[k].c0);
+    // every original wave boundary is kept and each wave becomes
+    // min(parts, size) sub-waves of near-equal size
+    std::set<int> starts(t.wave_start.begin(), t.wave_start.end());
+    int expect = 0;
+    for (int w = 0; w < s.waves(); ++w) {
+        CHECK(starts.count(s.wave_start[w]) && starts.count(s.wave_start[w + 1]));
+        const int m = s.wave_start[w + 1] - s.wave_start[w];
+        expect += std::min(parts, m);
+        int lo = m, hi = 0, cnt = 0;
+        for (int x = 0; x < t.waves(); ++x)
+            if (t.wave_start[x] >= s.wave_start[w] && t.wave_start[x + 1] <= s.wave_start[w + 1]) {
+                const int sz = t.wave_start[x + 1] - t.wave_start[x];
+                lo = std::min(lo, sz), hi = std::max(hi, sz), ++cnt;
+            }
+        CHECK(cnt == std::min(parts, m) && hi - lo <= 1);
+    }
+    CHECK(t.waves() == expect);
+    if (parts == 1) CHECK(t.wave_start == s.wave_start);
+}
+
 int main() {
     const int64_t sizes[] = {1, 2, 63, 64, 65, 127, 128, 130, 515, 640, 1000};
     for (int64_t p : sizes)
@@ -111,6 +138,8 @@ int main() {
     for (int64_t q : sizes) lambda(q, 64);
     for (int64_t q : {64 * 7, 64 * 8 + 5, 20000}) lambda(q, 64);
     lambda(515, 32);
+    for (int parts : {1, 2, 3, 4, 64, 1000})
+        for (int64_t q : {64, 130, 640, 1000, 20000}) split(q, parts);
     sequential(5, 7);
     sequential(1, 1);
     printf("schedule: %d checks passed\n", checks);
