@@ -442,17 +442,34 @@ def _prox_grad(X, Y, lamL, lamT, iters=20000, tol=1e-13):
     return L, T, hist[-1]
 
 
-@pytest.mark.parametrize("seed,p,q", [(50, 3, 4), (51, 5, 3), (52, 6, 6)])
-def test_agrees_with_proximal_gradient(oracle_lib, seed, p, q):
-    X, Y = random_problem(p, q, 30, seed=seed)
+# The last three draws have fewer samples than inputs and outputs together
+# (n < p + q; two of them n < p), the regime of
+# the larger benchmark workloads: there the objective is nearly flat along
+# some directions, the oracle's coordinate descent takes thousands of
+# iterations, and the proximal-gradient solver stops at a KKT residual near
+# 1e-8 with parameters ~1e-7 from the optimum while its objective agrees to
+# 1e-13.  The oracle is held to the tighter KKT bound itself.
+@pytest.mark.parametrize("seed,p,q,n", [(50, 3, 4, 30), (51, 5, 3, 30), (52, 6, 6, 30),
+                                        (53, 9, 4, 7), (54, 8, 6, 10), (55, 12, 3, 9)])
+def test_agrees_with_proximal_gradient(oracle_lib, seed, p, q, n):
+    X, Y = random_problem(p, q, n, seed=seed)
     lamL, lamT = 0.06, 0.09
-    r = oracle_lib.solve(X, Y, lamL, lamT, tol=1e-14, max_iter=5000, stall_iters=5)
-    L, T, f = _prox_grad(X, Y, lamL, lamT)
+    flat = n < p + q
+    r = oracle_lib.solve(X, Y, lamL, lamT, tol=1e-14, max_iter=200000, stall_iters=5)
+    assert r.status in (oracle_lib.ORC_OK, oracle_lib.ORC_STALLED)
+    GL, GT = _numpy_gradient(X, Y, r.Lambda, r.Theta)
+    assert max(_kkt_violation(GL, r.Lambda, lamL), _kkt_violation(GT, r.Theta, lamT)) < 1e-9
+    L, T, f = _prox_grad(X, Y, lamL, lamT, iters=200000, tol=1e-15 if flat else 1e-13)
     GL, GT = _numpy_gradient(X, Y, L, T)
-    assert max(_kkt_violation(GL, L, lamL), _kkt_violation(GT, T, lamT)) < 1e-9
+    assert max(_kkt_violation(GL, L, lamL), _kkt_violation(GT, T, lamT)) < (
+        1e-7 if flat else 1e-9)
     assert r.f == pytest.approx(f, rel=1e-12)
-    np.testing.assert_allclose(r.Lambda, L, atol=1e-8)
-    np.testing.assert_allclose(r.Theta, T, atol=1e-8)
+    atol = 1e-5 if flat else 1e-8
+    np.testing.assert_allclose(r.Lambda, L, atol=atol)
+    np.testing.assert_allclose(r.Theta, T, atol=atol)
+    for a, b in ((r.Lambda, L), (r.Theta, T)):     # supports outside [1e-7, 1e-5]
+        clear = (np.abs(a) < 1e-7) | (np.abs(a) > 1e-5)
+        assert np.array_equal((np.abs(a) > 1e-6)[clear], (np.abs(b) > 1e-6)[clear])
 
 
 # ----------------------------------------------------------------------------

@@ -1,11 +1,12 @@
 """Property tests of the oracle over randomly drawn small problems
-(hypothesis): on every problem the objective never increases and Lambda stays
-symmetric positive definite; on well-posed ones (n >= 2 (p + q)) the KKT
-conditions of Eq. (1) hold at the solve's end, with gradients recomputed in
-numpy from their definition (Eq. (3)).  With n < p or n < q and a small
-penalty, coordinate descent can reach the rounding floor of f (the stall
-rule) while the iterate is still 1e-7..1e-4 away from the KKT point, so the
-KKT bound is not asserted there.  CPU only."""
+(hypothesis): on every problem the objective never increases, Lambda stays
+symmetric positive definite, the solve ends at the rounding floor of f (the
+stall rule) or at the stopping rule and never at the iteration cap, and the
+KKT conditions of Eq. (1) hold at its end, with gradients recomputed in
+numpy from their definition (Eq. (3)).  Draws with n < p + q (the regime of
+the larger parity workloads) converge slowly -- thousands of iterations --
+but to the same KKT point, so the cap is set high and the bound holds on
+every draw.  CPU only."""
 import numpy as np
 import pytest
 from hypothesis import HealthCheck, given, settings
@@ -44,14 +45,13 @@ def kkt_violation(G, P, lam):
 def test_random_problems_converge_to_kkt(orc, p, q, n, density, lam, ratio, seed):
     pr = synth.chain_problem(p=p, q=q, n=n, density=density, lam=lam, seed=seed,
                              lam_Theta=lam * ratio)
-    r = orc.solve(pr.X, pr.Y, pr.lam_Lambda, pr.lam_Theta, tol=0.0, max_iter=3000,
+    r = orc.solve(pr.X, pr.Y, pr.lam_Lambda, pr.lam_Theta, tol=0.0, max_iter=200000,
                   stall_iters=3)
+    assert r.status in (orc.ORC_OK, orc.ORC_STALLED), (r.status, r.iters)
     f = r.trace["f"][np.isfinite(r.trace["f"])]
     assert np.all(np.diff(f) <= 1e-12 * np.abs(f[1:]) + 1e-300)
     assert np.array_equal(r.Lambda, r.Lambda.T)
     assert np.linalg.eigvalsh(r.Lambda).min() > 0
-    if n < 2 * (p + q):
-        return
     GL, GT = numpy_gradient(pr.X, pr.Y, r.Lambda, r.Theta)
     scale = max(1.0, np.abs(GL).max(), np.abs(GT).max())
     assert kkt_violation(GL, r.Lambda, pr.lam_Lambda) < 1e-7 * scale
