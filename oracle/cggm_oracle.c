@@ -26,11 +26,13 @@
  *     1e-14 max(1, |f|) for the rounding error of f itself.
  *   - Screening uses strict '>' against lambda and an exact-zero test.
  */
+#define _DEFAULT_SOURCE   /* posix_memalign, madvise */
 #include "cggm_oracle.h"
 
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#include <sys/mman.h>
 
 #define IDX(i, j, ld) ((size_t)(i) * (size_t)(ld) + (size_t)(j))
 
@@ -40,10 +42,22 @@
 /* Products below this many multiply-adds run on one thread. */
 #define OMP_MIN_WORK 4000000LL
 
+/* Zeroed array.  Large ones are backed by 2 MiB pages where the kernel
+ * allows it: the coordinate sweeps walk columns of row-major matrices, and
+ * with 4 KiB pages nearly every such access misses the TLB. */
 static double *zalloc(size_t count) {
-    double *p = (double *)calloc(count ? count : 1, sizeof(double));
-    if (!p) abort();
-    return p;
+    const size_t bytes = (count ? count : 1) * sizeof(double), huge = (size_t)2 << 20;
+    if (bytes < 2 * huge) {
+        double *p = (double *)calloc(count ? count : 1, sizeof(double));
+        if (!p) abort();
+        return p;
+    }
+    void *p = NULL;
+    const size_t rounded = (bytes + huge - 1) / huge * huge;
+    if (posix_memalign(&p, huge, rounded) != 0) abort();
+    (void)madvise(p, rounded, MADV_HUGEPAGE);
+    memset(p, 0, bytes);
+    return (double *)p;
 }
 
 /* C = A B (A m x k, B k x nc), skipping zero entries of A. */
@@ -348,28 +362,33 @@ void orc_theta_sweep(int64_t p, int64_t q, const double *Sxx, const double *Sxy,
     /* Coordinate descent directly on the quadratic of Eq. (7):
      * along Theta_ij the change of g is mu b + 1/2 a mu^2 with
      * b = 2 Sxy_ij + 2 (Sxx Theta Sigma)_ij and a = 2 Sxx_ii Sigma_jj.
-     * V = Theta Sigma is maintained (row i gains mu Sigma_j.). */
-    double *V = zalloc((size_t)(p * q));
+     * V = Theta Sigma is maintained (row i gains mu Sigma_j.), stored
+     * transposed (Vt[j][k] = V[k][j]) so that the column of V read by every
+     * coordinate is a contiguous row of Vt. */
+    double *V = zalloc((size_t)(p * q)), *Vt = zalloc((size_t)(p * q));
     matmul(p, q, q, Theta, Sigma, V);
+    for (int64_t k = 0; k < p; ++k)
+        for (int64_t j = 0; j < q; ++j) Vt[IDX(j, k, p)] = V[IDX(k, j, q)];
+    free(V);
     for (int64_t i = 0; i < p; ++i) {
         for (int64_t j = 0; j < q; ++j) {
             if (!actT[IDX(i, j, q)]) continue;
             double a = 2.0 * Sxx[IDX(i, i, p)] * Sigma[IDX(j, j, q)];
             if (!(a > 0.0)) continue;
+            const double *Si = Sxx + IDX(i, 0, p), *Vcol_j = Vt + IDX(j, 0, p);
             double sv = 0.0;
-            for (int64_t k = 0; k < p; ++k) sv += Sxx[IDX(i, k, p)] * V[IDX(k, j, q)];
+            for (int64_t k = 0; k < p; ++k) sv += Si[k] * Vcol_j[k];
             double b = 2.0 * Sxy[IDX(i, j, q)] + 2.0 * sv;
             double c = Theta[IDX(i, j, q)];
             double z = soft_threshold(c - b / a, lamT / a);
             double mu = z - c;
             if (mu == 0.0) continue;
             Theta[IDX(i, j, q)] = z;
-            double *Vi = V + IDX(i, 0, q);
             const double *Sj = Sigma + IDX(j, 0, q);
-            for (int64_t k = 0; k < q; ++k) Vi[k] += mu * Sj[k];
+            for (int64_t k = 0; k < q; ++k) Vt[IDX(k, i, p)] += mu * Sj[k];
         }
     }
-    free(V);
+    free(Vt);
 }
 
 /* l1 norm of the minimum-norm subgradient of f (stopping rule, Sec. 5.1). */
