@@ -40,6 +40,10 @@ extern "C" {
 /* ---- status codes ---------------------------------------------------- */
 #define CGGM_OK 0
 #define CGGM_MAXITER 1        /* warning: iteration cap reached, result valid   */
+#define CGGM_STALLED 2        /* warning: stopped because neither f nor the
+                                 subgradient improved for options.stall_iters
+                                 iterations (the rounding floor of f) before the
+                                 stopping rule was met; result valid           */
 #define CGGM_EINVAL (-1)      /* bad size, NULL pointer, non-finite value       */
 #define CGGM_ENOTPD (-2)      /* Lambda (given or warm start) not pos. definite */
 #define CGGM_ELINESEARCH (-3) /* no Armijo step found (last iterate returned)   */
@@ -91,6 +95,8 @@ typedef struct {
     double ms_lambda_cd;  /* Lambda coordinate-descent sweep                     */
     double ms_line_search;/* line search incl. the accepted factor's inverse    */
     double ms_theta_cd;   /* V = Theta Sigma and the Theta sweep                 */
+    double delta;         /* tr(G_Lambda D) + lamL (|Lambda + D|_1 - |Lambda|_1)
+                             of the direction the line search took              */
 } cggm_trace_entry;
 
 /* Launch statistics of the coordinate-descent sweeps, filled when
@@ -139,6 +145,16 @@ typedef struct {
     int trace_cap;
     int trace_len;             /* out: records written                          */
     cggm_kernel_stats *kstats; /* out: CD sweep kernel statistics, or NULL       */
+    int theta_passes;      /* CD passes of the Theta step over S_Theta per
+                              iteration (Sec. 3.2 makes one; default 1); the
+                              passes share Sigma and the active set          */
+    int split_level;       /* tiled sweeps: each wave starts as 2^split_level
+                              sub-waves run one after another (0..6, default
+                              0: whole waves)                                 */
+    int split_adapt;       /* 1 (default): the descent guards and the step
+                              size move the level (see cggm_solve); 0: the
+                              level stays at split_level and a failing sweep
+                              is redone with one tile per wave               */
 } cggm_options;
 
 /* Fill `opt` with the defaults above. */
@@ -170,14 +186,16 @@ typedef struct cggm_result cggm_result;   /* opaque, owns device CSR arrays */
  * The passes run as waves of 64 x 64 tiles whose maintained-product rows are
  * disjoint (exact Gauss-Seidel inside a tile, concurrent across the tiles of
  * a wave), or one coordinate at a time with CGGM_SWEEP_SEQUENTIAL.  A
- * direction with no descent, or a Theta pass that raises f, is redone: in
- * FP64 after a mixed-precision pass, else with each wave split into twice as
- * many sub-waves (up to 64), else one tile per wave; a Lambda step shrunk
- * below 1/8 by the line search also doubles the split, three full steps in
- * a row halve it.
+ * direction with no descent or for which the line search finds no Armijo
+ * step, or a Theta pass that raises f, is redone: in FP64 after a
+ * mixed-precision pass, else with each wave split into twice as many
+ * sub-waves (up to 64), else one tile per wave; a Lambda step shrunk below
+ * 1/8 by the line search also doubles the split, three full steps in a row
+ * (any step below 1 restarts the count) halve it.
  * It stops when ||grad^S||_1 < tol (||Lambda||_1 + ||Theta||_1) (the paper's
- * stopping rule of Sec. 5.1 with 0.01 replaced by tol), when the iterate stops
- * moving (stall_iters), or after max_iter iterations (CGGM_MAXITER).
+ * stopping rule of Sec. 5.1 with 0.01 replaced by tol; CGGM_OK), when the
+ * iterate stops moving (stall_iters; CGGM_STALLED), or after max_iter
+ * iterations (CGGM_MAXITER).
  *
  * X: n x p, Y: n x q (device).  lamL, lamT >= 0.  On success *out receives a
  * result handle (free with cggm_result_free).  The call is blocking: it
@@ -204,7 +222,8 @@ int cggm_solve(const double *X, const double *Y, int64_t n, int64_t p, int64_t q
  * out: host array of npath handles, all filled unless the return value is an
  * error other than CGGM_ELINESEARCH (then none are).  Returns the first
  * negative status of a point, else CGGM_MAXITER if a point reached the cap,
- * else CGGM_OK; each point's own status is in cggm_result_info.  Trace records
+ * else CGGM_STALLED if a point stalled, else CGGM_OK; each point's own status
+ * is in cggm_result_info.  Trace records
  * of all points are appended in order (iter restarts at 0 for each point).
  */
 int cggm_solve_path(const double *X, const double *Y, int64_t n, int64_t p, int64_t q,

@@ -21,7 +21,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcggm.so")
 
-CGGM_OK, CGGM_MAXITER = 0, 1
+CGGM_OK, CGGM_MAXITER, CGGM_STALLED = 0, 1, 2
 CGGM_PRECISION_FP64, CGGM_PRECISION_MIXED = 0, 1
 CGGM_EINVAL, CGGM_ENOTPD, CGGM_ELINESEARCH, CGGM_ENOMEM, CGGM_EHIP = -1, -2, -3, -4, -5
 CGGM_ECAPACITY = -6
@@ -41,7 +41,7 @@ class TraceEntry(ctypes.Structure):
                 ("nnz_Lambda", ctypes.c_int64), ("nnz_Theta", ctypes.c_int64),
                 ("t_end_ms", ctypes.c_double), ("ms_gradient", ctypes.c_double),
                 ("ms_lambda_cd", ctypes.c_double), ("ms_line_search", ctypes.c_double),
-                ("ms_theta_cd", ctypes.c_double)]
+                ("ms_theta_cd", ctypes.c_double), ("delta", ctypes.c_double)]
 
 
 class KernelStats(ctypes.Structure):
@@ -62,7 +62,9 @@ class Options(ctypes.Structure):
                 ("workspace_budget", ctypes.c_size_t),
                 ("warm_Lambda", _vp), ("warm_Theta", _vp),
                 ("trace", ctypes.POINTER(TraceEntry)), ("trace_cap", ctypes.c_int),
-                ("trace_len", ctypes.c_int), ("kstats", ctypes.POINTER(KernelStats))]
+                ("trace_len", ctypes.c_int), ("kstats", ctypes.POINTER(KernelStats)),
+                ("theta_passes", ctypes.c_int), ("split_level", ctypes.c_int),
+                ("split_adapt", ctypes.c_int)]
 
 
 class Request(ctypes.Structure):
@@ -209,12 +211,13 @@ class SolveResult:
 
 def _options(lib, *, max_iter, max_ls, ls_beta, ls_sigma, stall_iters, sweep, tile,
              lambda_passes, precision, workspace_budget, warm_Lambda, warm_Theta,
-             mixed_min_q=None) -> Options:
+             mixed_min_q=None, theta_passes=1, split_level=0, split_adapt=True) -> Options:
     opt = Options()
     lib.cggm_default_options(ctypes.byref(opt))
     opt.max_iter, opt.max_ls, opt.ls_beta, opt.ls_sigma = max_iter, max_ls, ls_beta, ls_sigma
     opt.stall_iters, opt.sweep, opt.tile = stall_iters, sweep, tile
-    opt.lambda_passes = lambda_passes
+    opt.lambda_passes, opt.theta_passes = lambda_passes, theta_passes
+    opt.split_level, opt.split_adapt = split_level, int(bool(split_adapt))
     opt.precision = PRECISIONS[precision]
     if mixed_min_q is not None:
         opt.mixed_min_q = mixed_min_q
@@ -264,6 +267,7 @@ def cggm_solve(X, Y, lam_Lambda: float, lam_Theta: float, tol: float = 1e-2, *,
                mixed_min_q: int | None = None, workspace_budget: int = 0,
                warm_Lambda=None, warm_Theta=None, trace_cap: int | None = None,
                keep_csr: bool = False, kernel_stats: bool = False,
+               theta_passes: int = 1, split_level: int = 0, split_adapt: bool = True,
                stream=None) -> SolveResult:
     """Alternating Newton CD (Algorithm 1) on device X (n x p) and Y (n x q), float64."""
     lib = load()
@@ -273,7 +277,9 @@ def cggm_solve(X, Y, lam_Lambda: float, lam_Theta: float, tol: float = 1e-2, *,
                    stall_iters=stall_iters, sweep=sweep, tile=tile,
                    lambda_passes=lambda_passes, precision=precision,
                    workspace_budget=workspace_budget, warm_Lambda=warm_Lambda,
-                   warm_Theta=warm_Theta, mixed_min_q=mixed_min_q)
+                   warm_Theta=warm_Theta, mixed_min_q=mixed_min_q,
+                   theta_passes=theta_passes, split_level=split_level,
+                   split_adapt=split_adapt)
     cap = (max_iter + 1) if trace_cap is None else trace_cap
     trace_buf = (TraceEntry * max(cap, 1))()
     opt.trace = ctypes.cast(trace_buf, ctypes.POINTER(TraceEntry)) if cap > 0 else None
@@ -307,6 +313,7 @@ def cggm_solve_path(X, Y, lam_Lambda, lam_Theta, tol: float = 1e-2, *,
                     precision: str = "fp64", mixed_min_q: int | None = None,
                     workspace_budget: int = 0, warm_Lambda=None,
                     warm_Theta=None, trace_cap: int | None = None, keep_csr: bool = False,
+                    theta_passes: int = 1, split_level: int = 0, split_adapt: bool = True,
                     stream=None) -> list:
     """Warm-started regularisation path: one SolveResult per (lam_Lambda[k], lam_Theta[k])."""
     lib = load()
@@ -321,7 +328,9 @@ def cggm_solve_path(X, Y, lam_Lambda, lam_Theta, tol: float = 1e-2, *,
                    stall_iters=stall_iters, sweep=sweep, tile=tile,
                    lambda_passes=lambda_passes, precision=precision,
                    workspace_budget=workspace_budget, warm_Lambda=warm_Lambda,
-                   warm_Theta=warm_Theta, mixed_min_q=mixed_min_q)
+                   warm_Theta=warm_Theta, mixed_min_q=mixed_min_q,
+                   theta_passes=theta_passes, split_level=split_level,
+                   split_adapt=split_adapt)
     cap = npath * (max_iter + 1) if trace_cap is None else trace_cap
     trace_buf = (TraceEntry * max(cap, 1))()
     opt.trace = ctypes.cast(trace_buf, ctypes.POINTER(TraceEntry)) if cap > 0 else None

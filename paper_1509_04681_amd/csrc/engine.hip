@@ -379,11 +379,14 @@ struct KernelTimer {
     }
 };
 
-void run_theta_sweep(Ctx &c, const Schedule &sch, KernelTimer *kt = nullptr) {
+// One CD pass over S_Theta; the activity of the tiles is taken on the first
+// pass (pass == 0) from the top-of-iteration gradient, further passes reuse it.
+void run_theta_sweep(Ctx &c, const Schedule &sch, KernelTimer *kt = nullptr, int pass = 0) {
     Work &w = c.w;
     const SweepF32 f32 = sweep_operands(c);
-    theta_activity(c.s, w.rects_theta, (int)sch.rects.size(), w.q, w.GT, w.Th, c.lamT,
-                   w.act_theta);
+    if (pass == 0)
+        theta_activity(c.s, w.rects_theta, (int)sch.rects.size(), w.q, w.GT, w.Th, c.lamT,
+                       w.act_theta);
     for (int k = 0; k < sch.waves(); ++k) {
         const int b = sch.wave_start[k], e = sch.wave_start[k + 1];
         WaveProbe pr;
@@ -488,7 +491,8 @@ cggm_options checked_options(const cggm_options *opt_in) {
     if (opt_in) opt = *opt_in;
     if (opt.max_iter < 0 || opt.max_ls < 1 || !(opt.ls_beta > 0.0 && opt.ls_beta < 1.0) ||
         !(opt.ls_sigma > 0.0 && opt.ls_sigma < 1.0) || opt.stall_iters < 0 ||
-        opt.lambda_passes < 1 || opt.mixed_min_q < 0 ||
+        opt.lambda_passes < 1 || opt.mixed_min_q < 0 || opt.theta_passes < 1 ||
+        opt.split_level < 0 || opt.split_level > 6 ||
         (opt.precision != CGGM_PRECISION_FP64 && opt.precision != CGGM_PRECISION_MIXED) ||
         (opt.sweep != CGGM_SWEEP_TILED && opt.sweep != CGGM_SWEEP_SEQUENTIAL))
         fail(CGGM_EINVAL, "invalid options");
@@ -658,18 +662,22 @@ SolveOutcome Solver::Impl::run(double lamL, double lamT, double tol) {
     // whose tiles see the updates of the earlier sub-waves (Jacobi across the
     // tiles of one sub-wave, exact Gauss-Seidel inside a tile).  With many
     // strongly coupled tiles per wave the concurrent (Jacobi) part can give a
-    // poor or even divergent direction, so a direction without descent, a
-    // Theta sweep that raised f, or a Lambda step the line search had to
-    // shrink below SMALL_STEP raises the level; three full steps (three
-    // Theta sweeps that pass the guard) in a row lower it again.
+    // poor or even divergent direction, so a direction without descent or
+    // without an Armijo step, a Theta sweep that raised f, or a Lambda step
+    // the line search had to shrink below SMALL_STEP raises the level; three
+    // full steps (three Theta sweeps that pass the guard) in a row lower it
+    // again.  The levels start at options.split_level; with
+    // options.split_adapt == 0 they stay there and a failing sweep goes
+    // straight to one tile per wave.
     constexpr double SMALL_STEP = 0.125;
-    int la_level = 0, th_level = 0, la_good = 0, th_good = 0;
+    const bool adapt = opt.split_adapt != 0;
+    int la_level = seq ? 0 : opt.split_level, th_level = la_level, la_good = 0, th_good = 0;
     int status = CGGM_MAXITER, stalled = 0, t = 0, ls_fail_streak = 0;
     double sg_best = INFINITY, f_prev = INFINITY, f_after_ls = INFINITY;
     bool have_phase = false;
     const int trace_first = trace_len;
     int last_trials = 0, last_fallbacks = 0;
-    double last_alpha = 0.0;
+    double last_alpha = 0.0, last_delta = 0.0;
     TopStats top{};
     for (t = 0;; ++t) {
         CGGM_HIP(hipEventRecord(ev[0], s));
@@ -701,14 +709,14 @@ SolveOutcome Solver::Impl::run(double lamL, double lamT, double tol) {
             const Schedule *sch = &th_safe;
             if (swept_mixed) {
                 sch = &split_sched(th_split, th_sched, th_level);
-            } else if (th_level < MAX_SPLIT_LEVEL) {
+            } else if (adapt && th_level < MAX_SPLIT_LEVEL) {
                 ++th_level;
                 sch = &split_sched(th_split, th_sched, th_level);
             }
             c.mixed = false;
             swept_mixed = false;
             theta_sigma(c);
-            run_theta_sweep(c, *sch);
+            for (int pass = 0; pass < opt.theta_passes; ++pass) run_theta_sweep(c, *sch, nullptr, pass);
             ++last_fallbacks;
             theta_products(c, X);
             evaluate();
@@ -716,7 +724,7 @@ SolveOutcome Solver::Impl::run(double lamL, double lamT, double tol) {
             top = read_top(c, true);
             if (sch == &th_safe) break;
         }
-        if (t > 0 && !th_fired && th_level > 0 && ++th_good >= 3) {
+        if (adapt && t > 0 && !th_fired && th_level > 0 && ++th_good >= 3) {
             --th_level;
             th_good = 0;
         }
@@ -740,6 +748,7 @@ SolveOutcome Solver::Impl::run(double lamL, double lamT, double tol) {
             if (t > 0 && trace_len - trace_first >= 2) {
                 cggm_trace_entry &pv = opt.trace[trace_len - 2];
                 pv.alpha = last_alpha;
+                pv.delta = last_delta;
                 pv.ls_trials = last_trials;
                 pv.sweep_fallbacks = last_fallbacks;
                 if (have_phase) {
@@ -763,7 +772,7 @@ SolveOutcome Solver::Impl::run(double lamL, double lamT, double tol) {
                                      (top.f >= f_prev - 1e-15 * fabs(f_prev));
             stalled = no_progress ? stalled + 1 : 0;
             if (stalled >= opt.stall_iters) {
-                status = CGGM_OK;
+                status = CGGM_STALLED;
                 break;
             }
         }
@@ -776,49 +785,30 @@ SolveOutcome Solver::Impl::run(double lamL, double lamT, double tol) {
 
         // ---- Lambda: Newton direction by CD passes, Armijo line search -----
         CGGM_HIP(hipEventRecord(ev[2], s));
-        for (int pass = 0; pass < opt.lambda_passes; ++pass) {
-            run_lambda_sweep(c, split_sched(la_split, la_sched, la_level), &kt_lambda, pass);
-            if (pass + 1 < opt.lambda_passes && kt_lambda.on()) {
-                // recycle the timing events of this pass
-                CGGM_HIP(hipStreamSynchronize(s));
-                kt_lambda.collect();
+        // The direction: lambda_passes CD passes over S_Lambda at schedule
+        // `sch`; returns delta = tr(G D) + lamL (|Lambda + D|_1 - |Lambda|_1).
+        auto direction = [&](const Schedule &sch, KernelTimer *kt) {
+            for (int pass = 0; pass < opt.lambda_passes; ++pass) {
+                run_lambda_sweep(c, sch, kt, pass);
+                if (kt && pass + 1 < opt.lambda_passes && kt->on()) {
+                    // recycle the timing events of this pass
+                    CGGM_HIP(hipStreamSynchronize(s));
+                    kt->collect();
+                }
             }
-        }
-        reduce_direction(s, q, w.GL, w.Lam, w.D, w.partials, w.scal + S_DIR);
-        double hd[2];
-        CGGM_HIP(hipMemcpyAsync(hd, w.scal + S_DIR, sizeof(hd), hipMemcpyDeviceToHost, s));
-        CGGM_HIP(hipStreamSynchronize(s));
-        kt_lambda.collect();
-        double delta = hd[0] + lamL * hd[1];
-        // Descent guard: the direction must have delta < 0 (Armijo needs it).
-        // A direction from the mixed-precision operands is redone in FP64 at
-        // the same level (and the run stays in FP64); a tiled FP64 direction
-        // is redone with its waves split further, and past MAX_SPLIT_LEVEL one
-        // tile per wave.
-        while (!(delta < 0.0) && !seq) {
-            const Schedule *sch = &la_safe;
-            if (c.mixed) {
-                sch = &split_sched(la_split, la_sched, la_level);
-            } else if (la_level < MAX_SPLIT_LEVEL) {
-                ++la_level;
-                la_good = 0;
-                sch = &split_sched(la_split, la_sched, la_level);
-            }
-            c.mixed = false;
-            for (int pass = 0; pass < opt.lambda_passes; ++pass)
-                run_lambda_sweep(c, *sch, nullptr, pass);
-            ++last_fallbacks;
             reduce_direction(s, q, w.GL, w.Lam, w.D, w.partials, w.scal + S_DIR);
+            double hd[2];
             CGGM_HIP(hipMemcpyAsync(hd, w.scal + S_DIR, sizeof(hd), hipMemcpyDeviceToHost, s));
             CGGM_HIP(hipStreamSynchronize(s));
-            delta = hd[0] + lamL * hd[1];
-            if (sch == &la_safe) break;
-        }
-        CGGM_HIP(hipEventRecord(ev[3], s));
+            if (kt) kt->collect();
+            return hd[0] + lamL * hd[1];
+        };
+        // Armijo rule along D (Algorithm 1): the first alpha = 1, beta, ... with
+        // Lambda + alpha D positive definite (Cholesky) and f decreased by at
+        // least ls_sigma alpha delta; the trial's factor is kept for the swap.
         double alpha = 0.0, f_acc = top.f;
         int trials = 0;
-        bool accepted = false;
-        if (delta < 0.0) {
+        auto line_search = [&](double delta) {
             transpose(s, w.n, q, w.A, w.At);            // A^T, q x n
             double a = 1.0;
             for (int k = 0; k < opt.max_ls; ++k, a *= opt.ls_beta) {
@@ -846,10 +836,36 @@ SolveOutcome Solver::Impl::run(double lamL, double lamT, double tol) {
                               F_ROUNDING * std::max(1.0, fabs(top.f))) {
                     alpha = a;
                     f_acc = fa;
-                    accepted = true;
-                    break;
+                    return true;
                 }
             }
+            return false;
+        };
+        // Descent guard: a direction without descent (delta >= 0), or one for
+        // which no Armijo step was found, is redone: a direction from the
+        // mixed-precision operands in FP64 at the same level (the run then
+        // stays in FP64), a tiled FP64 direction with its waves split further,
+        // and past MAX_SPLIT_LEVEL (or at a fixed level) with one tile per
+        // wave, whose outcome stands.
+        const Schedule *la_sch = &split_sched(la_split, la_sched, la_level);
+        double delta = direction(*la_sch, &kt_lambda);
+        bool accepted = false;
+        for (;;) {
+            CGGM_HIP(hipEventRecord(ev[3], s));
+            if (delta < 0.0) accepted = line_search(delta);
+            if (accepted || seq || la_sch == &la_safe) break;
+            if (c.mixed) {
+                // same schedule, FP64 operands
+            } else if (adapt && la_level < MAX_SPLIT_LEVEL) {
+                ++la_level;
+                la_good = 0;
+                la_sch = &split_sched(la_split, la_sched, la_level);
+            } else {
+                la_sch = &la_safe;
+            }
+            c.mixed = false;
+            delta = direction(*la_sch, nullptr);
+            ++last_fallbacks;
         }
         if (accepted) {
             std::swap(w.Lam, w.LamT);
@@ -862,15 +878,18 @@ SolveOutcome Solver::Impl::run(double lamL, double lamT, double tol) {
                 break;
             }
         }
-        if (!seq && accepted) {
+        if (!seq && adapt && accepted) {
             if (alpha < SMALL_STEP && la_level < MAX_SPLIT_LEVEL) {
                 ++la_level;
                 la_good = 0;
-            } else if (alpha == 1.0 && la_level > 0 && ++la_good >= 3) {
+            } else if (alpha < 1.0) {
+                la_good = 0;
+            } else if (la_level > 0 && ++la_good >= 3) {
                 --la_level;
                 la_good = 0;
             }
         }
+        last_delta = delta;
         f_after_ls = f_acc;
         last_alpha = alpha;
         last_trials = trials;
@@ -882,7 +901,8 @@ SolveOutcome Solver::Impl::run(double lamL, double lamT, double tol) {
         CGGM_HIP(hipMemcpyAsync(w.ThOld, w.Th, sizeof(double) * pq, hipMemcpyDeviceToDevice, s));
         swept_mixed = c.mixed;
         theta_sigma(c);                                              // V = Theta Sigma
-        run_theta_sweep(c, split_sched(th_split, th_sched, th_level), &kt_theta);
+        for (int pass = 0; pass < opt.theta_passes; ++pass)
+            run_theta_sweep(c, split_sched(th_split, th_sched, th_level), &kt_theta, pass);
         theta_products(c, X);
     }
     SolveOutcome o;
@@ -965,6 +985,7 @@ std::string last_error_text() { return g_last_error; }
 int combine_status(int acc, int s) {
     if (acc < 0) return acc;
     if (s < 0) return s;
+    if (acc == CGGM_MAXITER || s == CGGM_MAXITER) return CGGM_MAXITER;
     return std::max(acc, s);
 }
 
@@ -1145,6 +1166,9 @@ void cggm_default_options(cggm_options *opt) {
     opt->lambda_passes = 4;
     opt->precision = CGGM_PRECISION_FP64;
     opt->mixed_min_q = 4096;
+    opt->theta_passes = 1;
+    opt->split_level = 0;
+    opt->split_adapt = 1;
 }
 
 size_t cggm_solve_workspace_bytes(int64_t n, int64_t p, int64_t q) {
@@ -1244,6 +1268,7 @@ const char *cggm_status_string(int status) {
     switch (status) {
         case CGGM_OK: return "ok";
         case CGGM_MAXITER: return "iteration cap reached";
+        case CGGM_STALLED: return "stopped at the rounding floor before the stopping rule";
         case CGGM_EINVAL: return "invalid argument";
         case CGGM_ENOTPD: return "Lambda is not positive definite";
         case CGGM_ELINESEARCH: return "line search found no Armijo step";

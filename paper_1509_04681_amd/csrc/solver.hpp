@@ -16,7 +16,7 @@
 namespace cggm {
 
 struct SolveOutcome {
-    int status = CGGM_OK;   // CGGM_OK, CGGM_MAXITER or CGGM_ELINESEARCH
+    int status = CGGM_OK;   // CGGM_OK, CGGM_MAXITER, CGGM_STALLED or CGGM_ELINESEARCH
     int iters = 0;          // outer iterations of this run
     double f = 0.0;         // objective at the returned iterate
 };
@@ -60,7 +60,8 @@ void set_last_error(const std::string &msg);
 std::string last_error_text();
 
 // Worst status over the points of a path: the first error, else CGGM_MAXITER
-// if any point reached the cap, else CGGM_OK.
+// if any point reached the cap, else CGGM_STALLED if any point stopped at the
+// rounding floor, else CGGM_OK.
 int combine_status(int acc, int s);
 
 // Runs f, turning exceptions into status codes and the thread's last error.

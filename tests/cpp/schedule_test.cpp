@@ -6,6 +6,7 @@
 
 #include <map>
 #include <set>
+#include <string>
 #include <utility>
 
 #include "schedule.hpp"
@@ -129,7 +130,24 @@ static void split(int64_t q, int parts) {
     if (parts == 1) CHECK(t.wave_start == s.wave_start);
 }
 
-int main() {
+// "dump q tile parts": print the Lambda schedule of a q x q problem with the
+// given tile edge, every wave split into `parts` sub-waves, one sub-wave per
+// line as "r0 r1 c0 c1" groups (read by the CPU emulation of the tiled
+// direction in tests/test_split_emulation_cpu.py).
+static int dump(int64_t q, int tile, int parts) {
+    const Schedule s = split_waves(lambda_schedule(q, tile, false), parts);
+    for (int w = 0; w < s.waves(); ++w) {
+        for (int k = s.wave_start[w]; k < s.wave_start[w + 1]; ++k)
+            printf("%s%d %d %d %d", k > s.wave_start[w] ? " " : "", s.rects[k].r0,
+                   s.rects[k].r1, s.rects[k].c0, s.rects[k].c1);
+        printf("\n");
+    }
+    return 0;
+}
+
+int main(int argc, char **argv) {
+    if (argc == 5 && std::string(argv[1]) == "dump")
+        return dump(atoll(argv[2]), atoi(argv[3]), atoi(argv[4]));
     const int64_t sizes[] = {1, 2, 63, 64, 65, 127, 128, 130, 515, 640, 1000};
     for (int64_t p : sizes)
         for (int64_t q : sizes) theta(p, q, 64);

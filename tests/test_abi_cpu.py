@@ -108,6 +108,8 @@ def test_default_options(lib):
     assert opt.lambda_passes == 4
     assert opt.precision == m.CGGM_PRECISION_FP64
     assert opt.mixed_min_q == 4096
+    assert (opt.theta_passes, opt.split_level, opt.split_adapt) == (1, 0, 1)
+    assert m.cggm_status_string(m.CGGM_STALLED).startswith("stopped at the rounding floor")
 
 
 def test_path_and_workspace_arguments_without_device(lib):
@@ -138,10 +140,12 @@ def test_path_and_workspace_arguments_without_device(lib):
     opt.mixed_min_q = 0
     forced = lib.cggm_workspace_bytes(300, 200, 100, ctypes.byref(opt))
     assert forced - small >= 4 * (4 * 100 * 100 + 200 * 200 + 200 * 100)
-    opt = m.Options()
-    lib.cggm_default_options(ctypes.byref(opt))
-    opt.lambda_passes = 0
-    assert lib.cggm_workspace_bytes(300, 200, 100, ctypes.byref(opt)) == 0
+    for field, value in (("lambda_passes", 0), ("theta_passes", 0), ("split_level", -1),
+                         ("split_level", 7)):
+        opt = m.Options()
+        lib.cggm_default_options(ctypes.byref(opt))
+        setattr(opt, field, value)
+        assert lib.cggm_workspace_bytes(300, 200, 100, ctypes.byref(opt)) == 0, (field, value)
     assert lib.cggm_workspace_bytes(0, 200, 100, None) == 0
 
 

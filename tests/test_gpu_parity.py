@@ -98,6 +98,36 @@ def test_objective_matches_oracle(cg, orc, p, q, n):
     assert f == pytest.approx(fo, rel=1e-12)
 
 
+def dense_spd_point(p, q, rng):
+    """A dense symmetric positive definite Lambda (every entry of its Cholesky
+    factor nonzero, so every trailing update multiplies nonzeros) and a 30%
+    dense Theta."""
+    A = rng.standard_normal((q, q))
+    Lam = A @ A.T / q + 0.5 * np.eye(q)
+    return (Lam + Lam.T) / 2, synth.dense_theta(p, q, 0.3, rng)
+
+
+# (600, 700, 300) reaches the 128 x 128 MFMA GEMM (M, N, K >= 256 in the
+# products and the trailing updates) and three 256-wide outer panels of the
+# blocked Cholesky; (333, 515, 257) has ragged edges on every level.
+@pytest.mark.parametrize("p,q,n", [(600, 700, 300), (333, 515, 257)])
+def test_dense_point_gradient_objective_match_oracle(cg, orc, p, q, n):
+    rng = np.random.default_rng(p + 7 * q)
+    X, Y = random_problem(p, q, n, seed=p + q + 1)
+    Lam, Theta = dense_spd_point(p, q, rng)
+    assert np.count_nonzero(np.linalg.cholesky(Lam)) == q * (q + 1) // 2
+    S = orc.stats(X, Y)
+    GL, GT = cg.cggm_gradient(dev(X), dev(Y), dev(Lam), dev(Theta))
+    GLo, GTo, _, _ = orc.gradient(S, Lam, Theta)
+    f = cg.cggm_objective(dev(X), dev(Y), dev(Lam), dev(Theta), 0.07, 0.03)
+    fo = orc.objective(S, Lam, Theta, 0.07, 0.03)
+    print(f"dense point p={p} q={q} n={n}: rel err GL {rel_err(GL.cpu(), GLo):.2e} "
+          f"GT {rel_err(GT.cpu(), GTo):.2e} f {abs(f - fo) / abs(fo):.2e}", flush=True)
+    assert rel_err(GL.cpu().numpy(), GLo) < 1e-12
+    assert rel_err(GT.cpu().numpy(), GTo) < 1e-12
+    assert f == pytest.approx(fo, rel=1e-12)
+
+
 def test_objective_rejects_non_pd(cg):
     X, Y = random_problem(4, 3, 10, seed=1)
     Lam = np.eye(3)
@@ -283,6 +313,38 @@ def test_csr_output_matches_dense(cg):
     assert np.array_equal(L, g.Lambda.cpu().numpy())
     assert np.array_equal(T, g.Theta.cpu().numpy())
     assert g.nnz_Lambda == np.count_nonzero(L) and g.nnz_Theta == np.count_nonzero(T)
+
+
+def test_csr_output_matches_oracle_chain40(cg, orc):
+    """The CSR arrays of a converged solve against the oracle's optimum of the
+    40 x 40 chain workload (tests/golden/chain40.json and the oracle's values):
+    row pointers count each row's nonzeros, columns ascend within a row, the
+    entries above 1e-6 are the stored supports and their values agree with the
+    oracle's."""
+    gold = load_golden("chain40")
+    pr = synth.workload("chain40")
+    g = cg.cggm_solve(dev(pr.X), dev(pr.Y), pr.lam_Lambda, pr.lam_Theta, tol=0.0,
+                      max_iter=5000, keep_csr=True)
+    o = orc.solve(pr.X, pr.Y, pr.lam_Lambda, pr.lam_Theta, tol=0.0, max_iter=20000,
+                  stall_iters=3)
+    assert o.f == gold["f_star"]
+    q, p = pr.q, pr.p
+    for (rowptr, col, val), rows, sup, border, ref in (
+            (g.csr[0], q, gold["support_Lambda"], gold["borderline_Lambda"], o.Lambda),
+            (g.csr[1], p, gold["support_Theta"], gold["borderline_Theta"], o.Theta)):
+        assert rowptr[0] == 0 and np.all(np.diff(rowptr) >= 0) and rowptr[-1] == len(col)
+        dense = np.zeros((rows, q))
+        for r in range(rows):
+            c = col[rowptr[r]:rowptr[r + 1]]
+            assert np.all(np.diff(c) > 0) and np.all((c >= 0) & (c < q))
+            assert np.all(val[rowptr[r]:rowptr[r + 1]] != 0)
+            dense[r, c] = val[rowptr[r]:rowptr[r + 1]]
+        big = np.abs(dense) > SUPPORT_EPS
+        assert ((big == sup) | border).all()
+        np.testing.assert_allclose(dense, ref, atol=1e-7)
+    L = np.zeros((q, q))
+    L[np.repeat(np.arange(q), np.diff(g.csr[0][0])), g.csr[0][1]] = g.csr[0][2]
+    assert np.array_equal(L, L.T)                 # full symmetric storage
 
 
 def test_error_paths_on_device(cg):
