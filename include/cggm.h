@@ -14,8 +14,10 @@
  * l1 norms elementwise over all entries (diagonal and both triangles).
  *
  * Conventions for every entry point:
- *   - All matrices are dense, row-major, contiguous, float64, in DEVICE memory
- *     of the current HIP device, unless a parameter says "host".
+ *   - All matrices are dense, row-major, contiguous, in DEVICE memory of the
+ *     current HIP device, unless a parameter says "host"; float64, except the
+ *     inputs X and Y, whose element type is the `dtype` argument (CGGM_F64 or
+ *     CGGM_F32).
  *   - `stream` is a hipStream_t (NULL = the default stream).  All device work
  *     is ordered on it.  Entry points that return host scalars synchronise it.
  *   - Input pointers are only read during the call and never retained.
@@ -50,6 +52,13 @@ extern "C" {
 #define CGGM_ENOMEM (-4)      /* workspace over budget or hipMalloc failed      */
 #define CGGM_EHIP (-5)        /* a HIP runtime call failed                      */
 #define CGGM_ECAPACITY (-6)   /* request larger than a server's device pool     */
+
+/* ---- element type of the inputs X and Y --------------------------------
+ * CGGM_F32 inputs are widened exactly to FP64 copies in the workspace (8 (np + nq)
+ * more bytes); every computation runs as for CGGM_F64 inputs holding the same
+ * values.  The parameters Lambda and Theta are always FP64. */
+#define CGGM_F64 0
+#define CGGM_F32 1
 
 /* ---- coordinate-descent sweep schedules ------------------------------ */
 #define CGGM_SWEEP_TILED 0      /* conflict-free parallel tile waves (default)   */
@@ -161,7 +170,8 @@ typedef struct {
 void cggm_default_options(cggm_options *opt);
 
 /* Device bytes cggm_solve would allocate for this shape with default options
- * (the footprint the workspace_budget option is compared against). */
+ * and FP64 inputs (the footprint the workspace_budget option is compared
+ * against; FP32 inputs add 8 (n p + n q) bytes, rounded up to 256 per array). */
 size_t cggm_solve_workspace_bytes(int64_t n, int64_t p, int64_t q);
 
 /* The same for the given options (NULL = defaults; the mixed mode needs more);
@@ -197,7 +207,8 @@ typedef struct cggm_result cggm_result;   /* opaque, owns device CSR arrays */
  * iterate stops moving (stall_iters; CGGM_STALLED), or after max_iter
  * iterations (CGGM_MAXITER).
  *
- * X: n x p, Y: n x q (device).  lamL, lamT >= 0.  On success *out receives a
+ * X: n x p, Y: n x q (device) of element type dtype (CGGM_F64 or CGGM_F32).
+ * lamL, lamT >= 0.  On success *out receives a
  * result handle (free with cggm_result_free).  The call is blocking: it
  * synchronises `stream` to take the line-search and stopping decisions.
  * Errors: CGGM_EINVAL (n, p, q < 1, NULL pointers, negative or non-finite
@@ -206,7 +217,7 @@ typedef struct cggm_result cggm_result;   /* opaque, owns device CSR arrays */
  * CGGM_EHIP.  CGGM_ELINESEARCH is returned with a valid result when no step
  * satisfying the Armijo rule exists for a descent direction.
  */
-int cggm_solve(const double *X, const double *Y, int64_t n, int64_t p, int64_t q,
+int cggm_solve(const void *X, const void *Y, int64_t n, int64_t p, int64_t q, int dtype,
                double lamL, double lamT, double tol, cggm_options *opt,
                cggm_result **out, void *stream);
 
@@ -226,7 +237,7 @@ int cggm_solve(const double *X, const double *Y, int64_t n, int64_t p, int64_t q
  * is in cggm_result_info.  Trace records
  * of all points are appended in order (iter restarts at 0 for each point).
  */
-int cggm_solve_path(const double *X, const double *Y, int64_t n, int64_t p, int64_t q,
+int cggm_solve_path(const void *X, const void *Y, int64_t n, int64_t p, int64_t q, int dtype,
                     int npath, const double *lamL, const double *lamT, double tol,
                     cggm_options *opt, cggm_result **out, void *stream);
 
@@ -253,7 +264,7 @@ void cggm_result_free(cggm_result *res);
  * symmetric) and Theta (p x q); *f_out is a host double.  Returns CGGM_ENOTPD
  * when Lambda is not positive definite (f is +infinity there).
  */
-int cggm_objective(const double *X, const double *Y, int64_t n, int64_t p, int64_t q,
+int cggm_objective(const void *X, const void *Y, int64_t n, int64_t p, int64_t q, int dtype,
                    const double *Lambda, const double *Theta, double lamL, double lamT,
                    double *f_out, void *stream);
 
@@ -263,7 +274,7 @@ int cggm_objective(const double *X, const double *Y, int64_t n, int64_t p, int64
  *   G_Theta  = 2 Sxy + 2 Sxx Theta Sigma   (p x q)
  * written to caller device buffers.  CGGM_ENOTPD if Lambda is not PD.
  */
-int cggm_gradient(const double *X, const double *Y, int64_t n, int64_t p, int64_t q,
+int cggm_gradient(const void *X, const void *Y, int64_t n, int64_t p, int64_t q, int dtype,
                   const double *Lambda, const double *Theta, double *G_Lambda,
                   double *G_Theta, void *stream);
 
@@ -285,8 +296,9 @@ int cggm_gradient(const double *X, const double *Y, int64_t n, int64_t p, int64_
 typedef struct cggm_server cggm_server;
 
 typedef struct {
-    const double *X, *Y;      /* device, n x p and n x q; valid until the request
-                                 completes (cggm_server_wait returned)           */
+    const void *X, *Y;        /* device, n x p and n x q of element type dtype;
+                                 valid until the request completes
+                                 (cggm_server_wait returned)                     */
     int64_t n, p, q;
     int npath;                /* >= 1 penalty pairs                               */
     const double *lamL;       /* host, npath values (copied at submit)            */
@@ -298,6 +310,7 @@ typedef struct {
     int mixed_min_q;          /* as cggm_options.mixed_min_q; < 0 = default      */
     double *Lambda_out;       /* device npath x q x q, or NULL                    */
     double *Theta_out;        /* device npath x p x q, or NULL                    */
+    int dtype;                /* CGGM_F64 (0) or CGGM_F32                          */
 } cggm_request;
 
 typedef struct {

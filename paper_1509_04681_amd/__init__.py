@@ -26,6 +26,7 @@ CGGM_PRECISION_FP64, CGGM_PRECISION_MIXED = 0, 1
 CGGM_EINVAL, CGGM_ENOTPD, CGGM_ELINESEARCH, CGGM_ENOMEM, CGGM_EHIP = -1, -2, -3, -4, -5
 CGGM_ECAPACITY = -6
 CGGM_SWEEP_TILED, CGGM_SWEEP_SEQUENTIAL = 0, 1
+CGGM_F64, CGGM_F32 = 0, 1
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _i64 = ctypes.c_int64
@@ -72,7 +73,7 @@ class Request(ctypes.Structure):
                 ("npath", ctypes.c_int), ("lamL", _dp), ("lamT", _dp), ("tol", ctypes.c_double),
                 ("precision", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("lambda_passes", ctypes.c_int), ("mixed_min_q", ctypes.c_int),
-                ("Lambda_out", _vp), ("Theta_out", _vp)]
+                ("Lambda_out", _vp), ("Theta_out", _vp), ("dtype", ctypes.c_int)]
 
 
 class RequestInfo(ctypes.Structure):
@@ -118,12 +119,14 @@ def load() -> ctypes.CDLL:
     lib.cggm_default_options.restype = None
     lib.cggm_solve_workspace_bytes.argtypes = [_i64, _i64, _i64]
     lib.cggm_solve_workspace_bytes.restype = ctypes.c_size_t
-    lib.cggm_solve.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_double, ctypes.c_double,
+    lib.cggm_solve.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_int, ctypes.c_double,
+                               ctypes.c_double,
                                ctypes.c_double, ctypes.POINTER(Options), ctypes.POINTER(_vp), _vp]
     lib.cggm_solve.restype = ctypes.c_int
     lib.cggm_workspace_bytes.argtypes = [_i64, _i64, _i64, ctypes.POINTER(Options)]
     lib.cggm_workspace_bytes.restype = ctypes.c_size_t
-    lib.cggm_solve_path.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_int, _dp, _dp,
+    lib.cggm_solve_path.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_int, ctypes.c_int, _dp,
+                                    _dp,
                                     ctypes.c_double, ctypes.POINTER(Options), ctypes.POINTER(_vp),
                                     _vp]
     lib.cggm_solve_path.restype = ctypes.c_int
@@ -149,10 +152,11 @@ def load() -> ctypes.CDLL:
     lib.cggm_result_dense.restype = ctypes.c_int
     lib.cggm_result_free.argtypes = [_vp]
     lib.cggm_result_free.restype = None
-    lib.cggm_objective.argtypes = [_vp, _vp, _i64, _i64, _i64, _vp, _vp, ctypes.c_double,
-                                   ctypes.c_double, _dp, _vp]
+    lib.cggm_objective.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_int, _vp, _vp,
+                                   ctypes.c_double, ctypes.c_double, _dp, _vp]
     lib.cggm_objective.restype = ctypes.c_int
-    lib.cggm_gradient.argtypes = [_vp, _vp, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _vp]
+    lib.cggm_gradient.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_int, _vp, _vp, _vp, _vp,
+                                  _vp]
     lib.cggm_gradient.restype = ctypes.c_int
     lib.cggm_status_string.argtypes = [ctypes.c_int]
     lib.cggm_status_string.restype = ctypes.c_char_p
@@ -183,6 +187,21 @@ def _dev(t, name):
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous (row-major)")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _inputs(X, Y):
+    """Device pointers of X and Y and their element type (both float64 or both
+    float32)."""
+    import torch
+    for t, name in ((X, "X"), (Y, "Y")):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{name} must be a torch tensor on a GPU device")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous (row-major)")
+    types = {torch.float64: CGGM_F64, torch.float32: CGGM_F32}
+    if X.dtype not in types or X.dtype != Y.dtype:
+        raise TypeError("X and Y must both be float64 or both float32")
+    return ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(Y.data_ptr()), types[X.dtype]
 
 
 def _stream(stream):
@@ -288,7 +307,8 @@ def cggm_solve(X, Y, lam_Lambda: float, lam_Theta: float, tol: float = 1e-2, *,
     if ks is not None:
         opt.kstats = ctypes.pointer(ks)
     res = ctypes.c_void_p()
-    code = lib.cggm_solve(_dev(X, "X"), _dev(Y, "Y"), n, p, q, float(lam_Lambda),
+    Xp, Yp, dtype = _inputs(X, Y)
+    code = lib.cggm_solve(Xp, Yp, n, p, q, dtype, float(lam_Lambda),
                           float(lam_Theta), float(tol), ctypes.byref(opt), ctypes.byref(res),
                           _stream(stream))
     if not (code == CGGM_ELINESEARCH and res.value):    # that status still returns a result
@@ -336,7 +356,8 @@ def cggm_solve_path(X, Y, lam_Lambda, lam_Theta, tol: float = 1e-2, *,
     opt.trace = ctypes.cast(trace_buf, ctypes.POINTER(TraceEntry)) if cap > 0 else None
     opt.trace_cap = cap
     res = (ctypes.c_void_p * npath)()
-    code = lib.cggm_solve_path(_dev(X, "X"), _dev(Y, "Y"), n, p, q, npath,
+    Xp, Yp, dtype = _inputs(X, Y)
+    code = lib.cggm_solve_path(Xp, Yp, n, p, q, dtype, npath,
                                lamL.ctypes.data_as(_dp), lamT.ctypes.data_as(_dp), float(tol),
                                ctypes.byref(opt), res, _stream(stream))
     if not (code == CGGM_ELINESEARCH and res[0]):
@@ -360,7 +381,8 @@ def cggm_objective(X, Y, Lambda, Theta, lam_Lambda: float, lam_Theta: float,
     n, p = X.shape
     q = Y.shape[1]
     f = ctypes.c_double()
-    _check(lib.cggm_objective(_dev(X, "X"), _dev(Y, "Y"), n, p, q, _dev(Lambda, "Lambda"),
+    Xp, Yp, dtype = _inputs(X, Y)
+    _check(lib.cggm_objective(Xp, Yp, n, p, q, dtype, _dev(Lambda, "Lambda"),
                               _dev(Theta, "Theta"), float(lam_Lambda), float(lam_Theta),
                               ctypes.byref(f), _stream(stream)))
     return f.value
@@ -374,7 +396,8 @@ def cggm_gradient(X, Y, Lambda, Theta, stream=None):
     q = Y.shape[1]
     GL = torch.empty((q, q), dtype=torch.float64, device=X.device)
     GT = torch.empty((p, q), dtype=torch.float64, device=X.device)
-    _check(lib.cggm_gradient(_dev(X, "X"), _dev(Y, "Y"), n, p, q, _dev(Lambda, "Lambda"),
+    Xp, Yp, dtype = _inputs(X, Y)
+    _check(lib.cggm_gradient(Xp, Yp, n, p, q, dtype, _dev(Lambda, "Lambda"),
                              _dev(Theta, "Theta"), _dev(GL, "G_Lambda"), _dev(GT, "G_Theta"),
                              _stream(stream)))
     return GL, GT
@@ -420,7 +443,8 @@ class Server:
             raise ValueError("lam_Lambda and lam_Theta must have the same length")
         npath = lamL.size
         r = Request()
-        r.X, r.Y = _dev(X, "X").value, _dev(Y, "Y").value
+        Xp, Yp, r.dtype = _inputs(X, Y)
+        r.X, r.Y = Xp.value, Yp.value
         r.n, r.p, r.q, r.npath = n, p, q, npath
         r.lamL, r.lamT = lamL.ctypes.data_as(_dp), lamT.ctypes.data_as(_dp)
         r.tol, r.precision = float(tol), PRECISIONS[precision]

@@ -31,6 +31,11 @@ __global__ void fill_kernel(int64_t count, double v, double *x) {
     if (e < count) x[e] = v;
 }
 
+__global__ void widen_kernel(int64_t count, const float *a, double *b) {   // b = (double)a
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < count) b[e] = (double)a[e];
+}
+
 __global__ void add_kernel(int64_t count, const double *a, double *b) {   // b += a
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e < count) b[e] += a[e];
@@ -89,6 +94,23 @@ void fill(hipStream_t s, int64_t count, double v, double *x) {
     CGGM_LAUNCH_CHECK();
 }
 
+void check_dtype(int dtype) {
+    if (dtype != CGGM_F64 && dtype != CGGM_F32) fail(CGGM_EINVAL, "dtype must be CGGM_F64 or CGGM_F32");
+}
+
+// X and Y as FP64 device arrays: the caller's when dtype is CGGM_F64, else
+// the exact FP64 widening of the caller's FP32 arrays into X64 / Y64.
+std::pair<const double *, const double *> fp64_inputs(hipStream_t s, int dtype, int64_t n,
+                                                      int64_t p, int64_t q, const void *X,
+                                                      const void *Y, double *X64, double *Y64) {
+    if (dtype == CGGM_F64) return {(const double *)X, (const double *)Y};
+    widen_kernel<<<nblk(n * p), BLOCK, 0, s>>>(n * p, (const float *)X, X64);
+    CGGM_LAUNCH_CHECK();
+    widen_kernel<<<nblk(n * q), BLOCK, 0, s>>>(n * q, (const float *)Y, Y64);
+    CGGM_LAUNCH_CHECK();
+    return {X64, Y64};
+}
+
 // ----------------------------------------------------------- device arena ----
 struct Arena {
     char *base = nullptr;
@@ -130,13 +152,15 @@ struct Work {
     // mixed mode: FP32 copies of the operands the CD sweeps stream
     float *SP32 = nullptr, *Psi32 = nullptr, *Sig32 = nullptr, *U32 = nullptr;
     float *Sxx32 = nullptr, *V32 = nullptr;
+    double *X64 = nullptr, *Y64 = nullptr;          // FP64 copies of FP32 inputs
 };
 
 constexpr int NSCAL = 64;
 
 // Layout of the workspace; with a.measure it only sizes it.
 void layout(Arena &a, Work &w, int64_t n, int64_t p, int64_t q, int64_t ntheta_rects,
-            int64_t nlambda_rects, int max_tiles, bool mixed = false, bool f32 = false) {
+            int64_t nlambda_rects, int max_tiles, bool mixed = false, bool f32 = false,
+            bool f32_inputs = false) {
     const int64_t qq = q * q, pq = p * q, nq = n * q;
     w.n = n, w.p = p, w.q = q;
     w.Sxx = a.take<double>(p * p);
@@ -187,6 +211,10 @@ void layout(Arena &a, Work &w, int64_t n, int64_t p, int64_t q, int64_t ntheta_r
         w.U32 = a.take<float>(q * lq);
         w.Sxx32 = a.take<float>(p * lp);
         w.V32 = a.take<float>(p * lq);
+    }
+    if (f32_inputs) {
+        w.X64 = a.take<double>(n * p);
+        w.Y64 = a.take<double>(n * q);
     }
 }
 
@@ -503,6 +531,7 @@ cggm_options checked_options(const cggm_options *opt_in) {
 
 struct Solver::Impl {
     int64_t n, p, q;
+    int dtype;
     cggm_options opt;
     bool mixed, seq;
     hipStream_t s;
@@ -522,9 +551,10 @@ struct Solver::Impl {
     int trace_len = 0;
     bool loaded = false, started = false;
 
-    Impl(int64_t n_, int64_t p_, int64_t q_, const cggm_options *o, hipStream_t st)
-        : n(n_), p(p_), q(q_), opt(checked_options(o)), s(st) {
+    Impl(int64_t n_, int64_t p_, int64_t q_, const cggm_options *o, hipStream_t st, int dt)
+        : n(n_), p(p_), q(q_), dtype(dt), opt(checked_options(o)), s(st) {
         check_sizes(n, p, q);
+        check_dtype(dtype);
         mixed = opt.precision == CGGM_PRECISION_MIXED && q >= opt.mixed_min_q;
         seq = opt.sweep == CGGM_SWEEP_SEQUENTIAL;
         const auto [tileL, tileT] = tile_edges(opt.tile);
@@ -550,7 +580,7 @@ struct Solver::Impl {
     }
     void lay(Arena &a) {
         layout(a, w, n, p, q, (int64_t)th_sched.rects.size(), (int64_t)la_sched.rects.size(),
-               max_tiles, mixed, mixed);
+               max_tiles, mixed, mixed, dtype == CGGM_F32);
     }
     const Schedule &split_sched(std::vector<std::unique_ptr<Schedule>> &cache,
                                 const Schedule &base, int level) {
@@ -590,8 +620,9 @@ struct Solver::Impl {
         }
         bind(own.p);
     }
-    void load(const double *X_, const double *Y) {
-        if (!X_ || !Y) fail(CGGM_EINVAL, "NULL pointer argument");
+    void load(const void *X_in, const void *Y_in) {
+        if (!X_in || !Y_in) fail(CGGM_EINVAL, "NULL pointer argument");
+        const auto [X_, Y] = fp64_inputs(s, dtype, n, p, q, X_in, Y_in, w.X64, w.Y64);
         X = X_;
         Ctx c{s, w, 0.0, 0.0, mixed};
         check_finite(c, X, Y);                 // synchronises the stream
@@ -912,13 +943,14 @@ SolveOutcome Solver::Impl::run(double lamL, double lamT, double tol) {
     return o;
 }
 
-Solver::Solver(int64_t n, int64_t p, int64_t q, const cggm_options *opt, hipStream_t s)
-    : impl_(new Impl(n, p, q, opt, s)) {}
+Solver::Solver(int64_t n, int64_t p, int64_t q, const cggm_options *opt, hipStream_t s,
+               int dtype)
+    : impl_(new Impl(n, p, q, opt, s, dtype)) {}
 Solver::~Solver() = default;
 size_t Solver::footprint() const { return impl_->bytes; }
 void Solver::allocate() { impl_->allocate(); }
 void Solver::bind(void *base) { impl_->bind(base); }
-void Solver::load(const double *X, const double *Y) { impl_->load(X, Y); }
+void Solver::load(const void *X, const void *Y) { impl_->load(X, Y); }
 void Solver::start() { impl_->start(); }
 SolveOutcome Solver::run(double lamL, double lamT, double tol) {
     return impl_->run(lamL, lamT, tol);
@@ -974,8 +1006,8 @@ void Solver::finish_kernel_stats() {
     }
 }
 
-size_t solve_footprint(int64_t n, int64_t p, int64_t q, const cggm_options *opt) {
-    Solver sv(n, p, q, opt, nullptr);
+size_t solve_footprint(int64_t n, int64_t p, int64_t q, const cggm_options *opt, int dtype) {
+    Solver sv(n, p, q, opt, nullptr, dtype);
     return sv.footprint();
 }
 
@@ -991,14 +1023,15 @@ int combine_status(int acc, int s) {
 
 namespace {
 
-int solve_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q, double lamL,
-               double lamT, double tol, cggm_options *opt_in, cggm_result **out,
+int solve_impl(const void *X, const void *Y, int64_t n, int64_t p, int64_t q, int dtype,
+               double lamL, double lamT, double tol, cggm_options *opt_in, cggm_result **out,
                hipStream_t s) {
     if (!X || !Y || !out) fail(CGGM_EINVAL, "NULL pointer argument");
     check_sizes(n, p, q);
+    check_dtype(dtype);
     check_lambda(lamL, lamT);
     if (!(tol >= 0.0) || !isfinite(tol)) fail(CGGM_EINVAL, "tol must be finite and >= 0");
-    Solver sv(n, p, q, opt_in, s);
+    Solver sv(n, p, q, opt_in, s, dtype);
     sv.allocate();
     sv.load(X, Y);
     sv.start();
@@ -1009,15 +1042,16 @@ int solve_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q
     return o.status;
 }
 
-int solve_path_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q,
+int solve_path_impl(const void *X, const void *Y, int64_t n, int64_t p, int64_t q, int dtype,
                     int npath, const double *lamL, const double *lamT, double tol,
                     cggm_options *opt_in, cggm_result **out, hipStream_t s) {
     if (!X || !Y || !out || !lamL || !lamT) fail(CGGM_EINVAL, "NULL pointer argument");
     if (npath < 1) fail(CGGM_EINVAL, "npath must be >= 1");
     check_sizes(n, p, q);
+    check_dtype(dtype);
     for (int k = 0; k < npath; ++k) check_lambda(lamL[k], lamT[k]);
     if (!(tol >= 0.0) || !isfinite(tol)) fail(CGGM_EINVAL, "tol must be finite and >= 0");
-    Solver sv(n, p, q, opt_in, s);
+    Solver sv(n, p, q, opt_in, s, dtype);
     sv.allocate();
     sv.load(X, Y);
     sv.start();
@@ -1039,43 +1073,38 @@ int solve_path_impl(const double *X, const double *Y, int64_t n, int64_t p, int6
 struct EvalWork {
     double *A, *R, *At, *L, *Wd, *Sig, *Psi, *Work, *YL, *partials, *scal;
     int *flag;
+    double *X64 = nullptr, *Y64 = nullptr;   // FP64 copies of FP32 inputs
 };
 
-void eval_layout(Arena &a, EvalWork &e, int64_t n, int64_t p, int64_t q, bool gradient) {
+// The objective uses A, At, L, Wd, YL and the reduction scratch; the gradient
+// A, R, L, Wd, Sig, Psi, Work and the reduction scratch.
+void eval_layout(Arena &a, EvalWork &e, int64_t n, int64_t p, int64_t q, bool gradient,
+                 int dtype) {
     e.A = a.take<double>(n * q);
-    e.R = a.take<double>(n * q);
-    e.At = a.take<double>(n * q);
+    e.R = gradient ? a.take<double>(n * q) : nullptr;
+    e.At = gradient ? nullptr : a.take<double>(n * q);
     e.L = a.take<double>(q * q);
     e.Wd = a.take<double>(diag_inv_count(q));
     e.Sig = gradient ? a.take<double>(q * q) : nullptr;
     e.Psi = gradient ? a.take<double>(q * q) : nullptr;
-    e.Work = a.take<double>(q * q);
-    e.YL = a.take<double>(n * q);
+    e.Work = gradient ? a.take<double>(q * q) : nullptr;
+    e.YL = gradient ? nullptr : a.take<double>(n * q);
     e.partials = a.take<double>(REDUCE_BLOCKS * 8);
     e.scal = a.take<double>(NSCAL);
     e.flag = a.take<int>(4);
+    if (dtype == CGGM_F32) {
+        e.X64 = a.take<double>(n * p);
+        e.Y64 = a.take<double>(n * q);
+    }
 }
 
-int objective_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q,
-                   const double *Lam, const double *Th, double lamL, double lamT, double *f_out,
-                   hipStream_t s) {
-    if (!X || !Y || !Lam || !Th || !f_out) fail(CGGM_EINVAL, "NULL pointer argument");
-    check_sizes(n, p, q);
-    check_lambda(lamL, lamT);
-    Arena sizer;
-    sizer.measure = true;
-    EvalWork e;
-    eval_layout(sizer, e, n, p, q, false);
-    DeviceBuffer buf;
-    if (hipMalloc(&buf.p, sizer.used) != hipSuccess) {
-        (void)hipGetLastError();
-        fail(CGGM_ENOMEM, "hipMalloc failed");
-    }
-    Arena arena;
-    arena.base = (char *)buf.p;
-    eval_layout(arena, e, n, p, q, false);
-    // f = -log det L + tr(Syy Lam) + 2 <Sxy, Theta> + |L^{-1} (X Theta)^T|_F^2 / n + penalties
-    // with tr(Syy Lam) = <Y, Y Lam> / n and <Sxy, Theta> = <Y, X Theta> / n.
+// f of Eq. (1) at dense (Lam, Th) with the evaluation workspace `e` (laid out
+// for the objective); Lam must be positive definite (else CGGM_ENOTPD).
+// f = -log det L + tr(Syy Lam) + 2 <Sxy, Theta> + |L^{-1} (X Theta)^T|_F^2 / n
+//     + penalties, with tr(Syy Lam) = <Y, Y Lam> / n, <Sxy, Theta> = <Y, X Theta> / n.
+double objective_core(const double *X, const double *Y, int64_t n, int64_t p, int64_t q,
+                      const double *Lam, const double *Th, double lamL, double lamT,
+                      const EvalWork &e, hipStream_t s) {
     gemm(s, false, false, n, q, p, 1.0, X, p, Th, q, 0.0, e.A, q);
     CGGM_HIP(hipMemcpyAsync(e.L, Lam, sizeof(double) * q * q, hipMemcpyDeviceToDevice, s));
     set_int(s, e.flag, 0);
@@ -1097,19 +1126,26 @@ int objective_impl(const double *X, const double *Y, int64_t n, int64_t p, int64
     CGGM_HIP(hipStreamSynchronize(s));
     if (hf || h[1] != 0.0) fail(CGGM_ENOTPD, "Lambda is not positive definite");
     const double inv_n = 1.0 / (double)n;
-    *f_out = -h[0] + h[3] * inv_n + 2.0 * h[4] * inv_n + h[2] * inv_n + lamL * h[6] +
-             lamT * h[11];
-    return CGGM_OK;
+    return -h[0] + h[3] * inv_n + 2.0 * h[4] * inv_n + h[2] * inv_n + lamL * h[6] + lamT * h[11];
 }
 
-int gradient_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_t q,
-                  const double *Lam, const double *Th, double *GL, double *GT, hipStream_t s) {
-    if (!X || !Y || !Lam || !Th || !GL || !GT) fail(CGGM_EINVAL, "NULL pointer argument");
+void check_objective_args(const void *X, const void *Y, int64_t n, int64_t p, int64_t q,
+                          int dtype, const double *Lam, const double *Th, double lamL,
+                          double lamT, double *f_out) {
+    if (!X || !Y || !Lam || !Th || !f_out) fail(CGGM_EINVAL, "NULL pointer argument");
     check_sizes(n, p, q);
+    check_dtype(dtype);
+    check_lambda(lamL, lamT);
+}
+
+int objective_impl(const void *X, const void *Y, int64_t n, int64_t p, int64_t q, int dtype,
+                   const double *Lam, const double *Th, double lamL, double lamT, double *f_out,
+                   hipStream_t s) {
+    check_objective_args(X, Y, n, p, q, dtype, Lam, Th, lamL, lamT, f_out);
     Arena sizer;
     sizer.measure = true;
     EvalWork e;
-    eval_layout(sizer, e, n, p, q, true);
+    eval_layout(sizer, e, n, p, q, false, dtype);
     DeviceBuffer buf;
     if (hipMalloc(&buf.p, sizer.used) != hipSuccess) {
         (void)hipGetLastError();
@@ -1117,7 +1153,31 @@ int gradient_impl(const double *X, const double *Y, int64_t n, int64_t p, int64_
     }
     Arena arena;
     arena.base = (char *)buf.p;
-    eval_layout(arena, e, n, p, q, true);
+    eval_layout(arena, e, n, p, q, false, dtype);
+    const auto [X64, Y64] = fp64_inputs(s, dtype, n, p, q, X, Y, e.X64, e.Y64);
+    *f_out = objective_core(X64, Y64, n, p, q, Lam, Th, lamL, lamT, e, s);
+    return CGGM_OK;
+}
+
+int gradient_impl(const void *X_in, const void *Y_in, int64_t n, int64_t p, int64_t q,
+                  int dtype, const double *Lam, const double *Th, double *GL, double *GT,
+                  hipStream_t s) {
+    if (!X_in || !Y_in || !Lam || !Th || !GL || !GT) fail(CGGM_EINVAL, "NULL pointer argument");
+    check_sizes(n, p, q);
+    check_dtype(dtype);
+    Arena sizer;
+    sizer.measure = true;
+    EvalWork e;
+    eval_layout(sizer, e, n, p, q, true, dtype);
+    DeviceBuffer buf;
+    if (hipMalloc(&buf.p, sizer.used) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(CGGM_ENOMEM, "hipMalloc failed");
+    }
+    Arena arena;
+    arena.base = (char *)buf.p;
+    eval_layout(arena, e, n, p, q, true, dtype);
+    const auto [X, Y] = fp64_inputs(s, dtype, n, p, q, X_in, Y_in, e.X64, e.Y64);
     const double inv_n = 1.0 / (double)n;
     CGGM_HIP(hipMemcpyAsync(e.L, Lam, sizeof(double) * q * q, hipMemcpyDeviceToDevice, s));
     set_int(s, e.flag, 0);
@@ -1178,24 +1238,25 @@ size_t cggm_solve_workspace_bytes(int64_t n, int64_t p, int64_t q) {
 size_t cggm_workspace_bytes(int64_t n, int64_t p, int64_t q, const cggm_options *opt) {
     size_t bytes = 0;
     const int st = guarded([&] {
-        bytes = solve_footprint(n, p, q, opt);
+        bytes = solve_footprint(n, p, q, opt, CGGM_F64);
         return CGGM_OK;
     });
     return st == CGGM_OK ? bytes : 0;
 }
 
-int cggm_solve(const double *X, const double *Y, int64_t n, int64_t p, int64_t q, double lamL,
-               double lamT, double tol, cggm_options *opt, cggm_result **out, void *stream) {
+int cggm_solve(const void *X, const void *Y, int64_t n, int64_t p, int64_t q, int dtype,
+               double lamL, double lamT, double tol, cggm_options *opt, cggm_result **out,
+               void *stream) {
     return guarded([&] {
-        return solve_impl(X, Y, n, p, q, lamL, lamT, tol, opt, out, (hipStream_t)stream);
+        return solve_impl(X, Y, n, p, q, dtype, lamL, lamT, tol, opt, out, (hipStream_t)stream);
     });
 }
 
-int cggm_solve_path(const double *X, const double *Y, int64_t n, int64_t p, int64_t q,
+int cggm_solve_path(const void *X, const void *Y, int64_t n, int64_t p, int64_t q, int dtype,
                     int npath, const double *lamL, const double *lamT, double tol,
                     cggm_options *opt, cggm_result **out, void *stream) {
     return guarded([&] {
-        return solve_path_impl(X, Y, n, p, q, npath, lamL, lamT, tol, opt, out,
+        return solve_path_impl(X, Y, n, p, q, dtype, npath, lamL, lamT, tol, opt, out,
                                (hipStream_t)stream);
     });
 }
@@ -1246,20 +1307,20 @@ int cggm_result_dense(const cggm_result *res, double *Lambda, double *Theta, int
 
 void cggm_result_free(cggm_result *res) { delete reinterpret_cast<ResultImpl *>(res); }
 
-int cggm_objective(const double *X, const double *Y, int64_t n, int64_t p, int64_t q,
+int cggm_objective(const void *X, const void *Y, int64_t n, int64_t p, int64_t q, int dtype,
                    const double *Lambda, const double *Theta, double lamL, double lamT,
                    double *f_out, void *stream) {
     return guarded([&] {
-        return objective_impl(X, Y, n, p, q, Lambda, Theta, lamL, lamT, f_out,
+        return objective_impl(X, Y, n, p, q, dtype, Lambda, Theta, lamL, lamT, f_out,
                               (hipStream_t)stream);
     });
 }
 
-int cggm_gradient(const double *X, const double *Y, int64_t n, int64_t p, int64_t q,
+int cggm_gradient(const void *X, const void *Y, int64_t n, int64_t p, int64_t q, int dtype,
                   const double *Lambda, const double *Theta, double *G_Lambda, double *G_Theta,
                   void *stream) {
     return guarded([&] {
-        return gradient_impl(X, Y, n, p, q, Lambda, Theta, G_Lambda, G_Theta,
+        return gradient_impl(X, Y, n, p, q, dtype, Lambda, Theta, G_Lambda, G_Theta,
                              (hipStream_t)stream);
     });
 }

@@ -71,7 +71,7 @@ struct Server {
         const cggm_request &r = j.req;
         int iters_total = 0;
         j.status = guarded([&] {
-            Solver sv(r.n, r.p, r.q, &j.opt, s);
+            Solver sv(r.n, r.p, r.q, &j.opt, s, r.dtype);
             if (round_up(sv.footprint()) != j.footprint)
                 fail(CGGM_EHIP, "workspace size changed between submit and admission");
             sv.bind((char *)base + j.offset);
@@ -164,7 +164,7 @@ Job *make_job(const cggm_request *req) {
     if (r.max_iter > 0) j->opt.max_iter = r.max_iter;
     if (r.lambda_passes > 0) j->opt.lambda_passes = r.lambda_passes;
     if (r.mixed_min_q >= 0) j->opt.mixed_min_q = r.mixed_min_q;
-    j->footprint = round_up(solve_footprint(r.n, r.p, r.q, &j->opt));   // validates
+    j->footprint = round_up(solve_footprint(r.n, r.p, r.q, &j->opt, r.dtype));   // validates
     j->f.assign(r.npath, 0.0);
     j->iters.assign(r.npath, 0);
     return j.release();

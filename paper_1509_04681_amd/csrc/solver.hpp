@@ -29,7 +29,10 @@ struct SolveOutcome {
 // with that stream idle.
 class Solver {
   public:
-    Solver(int64_t n, int64_t p, int64_t q, const cggm_options *opt, hipStream_t s);
+    // dtype: CGGM_F64 or CGGM_F32 inputs X, Y (FP32 ones are widened to FP64
+    // copies in the workspace at load()).
+    Solver(int64_t n, int64_t p, int64_t q, const cggm_options *opt, hipStream_t s,
+           int dtype = CGGM_F64);
     ~Solver();
     Solver(const Solver &) = delete;
     Solver &operator=(const Solver &) = delete;
@@ -37,7 +40,7 @@ class Solver {
     size_t footprint() const;            // device bytes of the workspace
     void allocate();                     // hipMalloc the workspace (budget checked)
     void bind(void *base);               // use caller memory of footprint() bytes
-    void load(const double *X, const double *Y);   // finite check, statistics
+    void load(const void *X, const void *Y);       // finite check, statistics
     void start();                        // Lambda = I / warm start, Theta = 0 / warm start
     SolveOutcome run(double lamL, double lamT, double tol);
     // Current Lambda (q x q) and Theta (p x q) into device buffers (NULL skips).
@@ -53,7 +56,8 @@ class Solver {
 };
 
 // Workspace bytes of a solve of this shape with these options (NULL = defaults).
-size_t solve_footprint(int64_t n, int64_t p, int64_t q, const cggm_options *opt);
+size_t solve_footprint(int64_t n, int64_t p, int64_t q, const cggm_options *opt,
+                       int dtype = CGGM_F64);
 
 // Thread-local message of the last failing C-ABI call.
 void set_last_error(const std::string &msg);

@@ -40,7 +40,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 def test_status_strings(lib):
     import paper_1509_04681_amd as m
-    for code in (0, 1, -1, -2, -3, -4, -5, -6):
+    for code in (0, 1, 2, -1, -2, -3, -4, -5, -6):
         assert m.cggm_status_string(code) != "unknown status"
     assert m.cggm_status_string(42) == "unknown status"
 
@@ -49,37 +49,43 @@ def test_argument_errors_without_device(lib):
     import paper_1509_04681_amd as m
     r = ctypes.c_void_p()
     fake = ctypes.c_void_p(64)          # never dereferenced: validation fails first
-    assert lib.cggm_solve(None, fake, 4, 3, 2, 0.1, 0.1, 0.01, None, ctypes.byref(r), None) \
+    assert lib.cggm_solve(None, fake, 4, 3, 2, 0, 0.1, 0.1, 0.01, None, ctypes.byref(r), None) \
         == m.CGGM_EINVAL
-    assert lib.cggm_solve(fake, fake, 0, 3, 2, 0.1, 0.1, 0.01, None, ctypes.byref(r), None) \
+    assert lib.cggm_solve(fake, fake, 0, 3, 2, 0, 0.1, 0.1, 0.01, None, ctypes.byref(r), None) \
         == m.CGGM_EINVAL
-    assert lib.cggm_solve(fake, fake, 4, 3, 2, -0.1, 0.1, 0.01, None, ctypes.byref(r), None) \
+    assert lib.cggm_solve(fake, fake, 4, 3, 2, 0, -0.1, 0.1, 0.01, None, ctypes.byref(r), None) \
         == m.CGGM_EINVAL
-    assert lib.cggm_solve(fake, fake, 4, 3, 2, 0.1, float("nan"), 0.01, None, ctypes.byref(r),
+    assert lib.cggm_solve(fake, fake, 4, 3, 2, 0, 0.1, float("nan"), 0.01, None, ctypes.byref(r),
                           None) == m.CGGM_EINVAL
-    assert lib.cggm_solve(fake, fake, 4, 3, 2, 0.1, 0.1, -1.0, None, ctypes.byref(r), None) \
+    assert lib.cggm_solve(fake, fake, 4, 3, 2, 0, 0.1, 0.1, -1.0, None, ctypes.byref(r), None) \
         == m.CGGM_EINVAL
     assert b"tol" in lib.cggm_last_error()
+    assert lib.cggm_solve(fake, fake, 4, 3, 2, 2, 0.1, 0.1, 0.01, None, ctypes.byref(r),
+                          None) == m.CGGM_EINVAL            # dtype neither F64 nor F32
+    assert b"dtype" in lib.cggm_last_error()
+    f = ctypes.c_double()
+    assert lib.cggm_objective(fake, fake, 4, 3, 2, 5, fake, fake, 0.1, 0.1, ctypes.byref(f),
+                              None) == m.CGGM_EINVAL
     opt = m.Options()
     lib.cggm_default_options(ctypes.byref(opt))
     opt.ls_beta = 1.5
-    assert lib.cggm_solve(fake, fake, 4, 3, 2, 0.1, 0.1, 0.01, ctypes.byref(opt),
+    assert lib.cggm_solve(fake, fake, 4, 3, 2, 0, 0.1, 0.1, 0.01, ctypes.byref(opt),
                           ctypes.byref(r), None) == m.CGGM_EINVAL
     lib.cggm_default_options(ctypes.byref(opt))
     opt.tile = 65
-    assert lib.cggm_solve(fake, fake, 4, 3, 2, 0.1, 0.1, 0.01, ctypes.byref(opt),
+    assert lib.cggm_solve(fake, fake, 4, 3, 2, 0, 0.1, 0.1, 0.01, ctypes.byref(opt),
                           ctypes.byref(r), None) == m.CGGM_EINVAL
     lib.cggm_default_options(ctypes.byref(opt))
     opt.precision = 2
-    assert lib.cggm_solve(fake, fake, 4, 3, 2, 0.1, 0.1, 0.01, ctypes.byref(opt),
+    assert lib.cggm_solve(fake, fake, 4, 3, 2, 0, 0.1, 0.1, 0.01, ctypes.byref(opt),
                           ctypes.byref(r), None) == m.CGGM_EINVAL
     lib.cggm_default_options(ctypes.byref(opt))
     opt.lambda_passes = 0
-    assert lib.cggm_solve(fake, fake, 4, 3, 2, 0.1, 0.1, 0.01, ctypes.byref(opt),
+    assert lib.cggm_solve(fake, fake, 4, 3, 2, 0, 0.1, 0.1, 0.01, ctypes.byref(opt),
                           ctypes.byref(r), None) == m.CGGM_EINVAL
     lib.cggm_default_options(ctypes.byref(opt))
     opt.mixed_min_q = -1
-    assert lib.cggm_solve(fake, fake, 4, 3, 2, 0.1, 0.1, 0.01, ctypes.byref(opt),
+    assert lib.cggm_solve(fake, fake, 4, 3, 2, 0, 0.1, 0.1, 0.01, ctypes.byref(opt),
                           ctypes.byref(r), None) == m.CGGM_EINVAL
 
 
@@ -92,7 +98,7 @@ def test_workspace_budget_is_checked_before_allocation(lib):
     opt.workspace_budget = need - 1
     r = ctypes.c_void_p()
     fake = ctypes.c_void_p(64)
-    assert lib.cggm_solve(fake, fake, 50, 40, 30, 0.1, 0.1, 0.01, ctypes.byref(opt),
+    assert lib.cggm_solve(fake, fake, 50, 40, 30, 0, 0.1, 0.1, 0.01, ctypes.byref(opt),
                           ctypes.byref(r), None) == m.CGGM_ENOMEM
     # footprint at the 20000 x 20000 workload fits one 288 GB device
     assert m.cggm_solve_workspace_bytes(1000, 20000, 20000) < 100e9
@@ -120,13 +126,13 @@ def test_path_and_workspace_arguments_without_device(lib):
     out = (ctypes.c_void_p * 3)()
     dp = ctypes.POINTER(ctypes.c_double)
     L = ctypes.cast(lam, dp)
-    assert lib.cggm_solve_path(fake, fake, 4, 3, 2, 0, L, L, 0.01, None, out, None) \
+    assert lib.cggm_solve_path(fake, fake, 4, 3, 2, 0, 0, L, L, 0.01, None, out, None) \
         == m.CGGM_EINVAL
-    assert lib.cggm_solve_path(fake, fake, 4, 3, 2, 3, None, L, 0.01, None, out, None) \
+    assert lib.cggm_solve_path(fake, fake, 4, 3, 2, 0, 3, None, L, 0.01, None, out, None) \
         == m.CGGM_EINVAL
-    assert lib.cggm_solve_path(fake, fake, 4, 3, 2, 3, L, ctypes.cast(bad, dp), 0.01, None, out,
+    assert lib.cggm_solve_path(fake, fake, 4, 3, 2, 0, 3, L, ctypes.cast(bad, dp), 0.01, None, out,
                                None) == m.CGGM_EINVAL
-    assert lib.cggm_solve_path(fake, fake, 4, 3, 2, 3, L, L, 0.01, None, None, None) \
+    assert lib.cggm_solve_path(fake, fake, 4, 3, 2, 0, 3, L, L, 0.01, None, None, None) \
         == m.CGGM_EINVAL
     # footprints: the mixed mode adds the BF16 planes; invalid options give 0
     fp64 = m.cggm_workspace_bytes(300, 200, 100)

@@ -347,6 +347,31 @@ def test_csr_output_matches_oracle_chain40(cg, orc):
     assert np.array_equal(L, L.T)                 # full symmetric storage
 
 
+def test_fp32_inputs_equal_their_fp64_widening(cg):
+    """dtype CGGM_F32: X and Y are widened exactly to FP64 in the workspace, so
+    every result is bit for bit the one of the FP64 arrays holding the same
+    values."""
+    import torch
+    pr = synth.chain_problem(p=150, q=130, n=90, density=0.05, lam=0.08, seed=21)
+    X32 = torch.from_numpy(pr.X.astype(np.float32)).to("cuda:0")
+    Y32 = torch.from_numpy(pr.Y.astype(np.float32)).to("cuda:0")
+    X64, Y64 = X32.double(), Y32.double()
+    a = cg.cggm_solve(X32, Y32, pr.lam_Lambda, pr.lam_Theta, tol=1e-6, max_iter=300)
+    b = cg.cggm_solve(X64, Y64, pr.lam_Lambda, pr.lam_Theta, tol=1e-6, max_iter=300)
+    assert a.f == b.f and a.iters == b.iters
+    assert torch.equal(a.Lambda, b.Lambda) and torch.equal(a.Theta, b.Theta)
+    pa = cg.cggm_solve_path(X32, Y32, [0.3, 0.1], [0.3, 0.1], tol=1e-6)
+    pb = cg.cggm_solve_path(X64, Y64, [0.3, 0.1], [0.3, 0.1], tol=1e-6)
+    assert [r.f for r in pa] == [r.f for r in pb]
+    GLa, GTa = cg.cggm_gradient(X32, Y32, a.Lambda, a.Theta)
+    GLb, GTb = cg.cggm_gradient(X64, Y64, a.Lambda, a.Theta)
+    assert torch.equal(GLa, GLb) and torch.equal(GTa, GTb)
+    fa = cg.cggm_objective(X32, Y32, a.Lambda, a.Theta, 0.1, 0.1)
+    assert fa == cg.cggm_objective(X64, Y64, a.Lambda, a.Theta, 0.1, 0.1)
+    with pytest.raises(TypeError):
+        cg.cggm_solve(X32, Y64, 0.1, 0.1)
+
+
 def test_error_paths_on_device(cg):
     X, Y = random_problem(6, 5, 20, seed=15)
     Xbad = X.copy()
