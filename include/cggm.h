@@ -27,7 +27,8 @@
  *   - No entry point throws.  The solve entry points allocate their device
  *     workspace per call with hipMalloc and free it before returning; the
  *     request server allocates one device pool when it is created and carves
- *     every request's workspace out of it.
+ *     every request's workspace out of it; cggm_objective_noalloc uses a
+ *     static device array and allocates nothing.
  */
 #ifndef CGGM_H
 #define CGGM_H
@@ -51,7 +52,8 @@ extern "C" {
 #define CGGM_ELINESEARCH (-3) /* no Armijo step found (last iterate returned)   */
 #define CGGM_ENOMEM (-4)      /* workspace over budget or hipMalloc failed      */
 #define CGGM_EHIP (-5)        /* a HIP runtime call failed                      */
-#define CGGM_ECAPACITY (-6)   /* request larger than a server's device pool     */
+#define CGGM_ECAPACITY (-6)   /* problem larger than a server's device pool or
+                                 the static scratch of cggm_objective_noalloc  */
 
 /* ---- element type of the inputs X and Y --------------------------------
  * CGGM_F32 inputs are widened exactly to FP64 copies in the workspace (8 (np + nq)
@@ -267,6 +269,30 @@ void cggm_result_free(cggm_result *res);
 int cggm_objective(const void *X, const void *Y, int64_t n, int64_t p, int64_t q, int dtype,
                    const double *Lambda, const double *Theta, double lamL, double lamT,
                    double *f_out, void *stream);
+
+/*
+ * Allocation-free form of cggm_objective, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, result and errors as
+ * cggm_objective; it calls no hipMalloc, hipFree or allocating library
+ * routine.  Its workspace -- three n x q arrays (X Theta, its transpose,
+ * Y Lambda), the Cholesky factor (q x q), the inverted 64 x 64 diagonal
+ * blocks (64 ceil(q / 64) x 64), about 5 KB of reduction scratch and, for
+ * CGGM_F32 inputs, the FP64 copies of X and Y, 8-byte words, each array
+ * rounded up to 256 bytes -- comes from a static device
+ * array of CGGM_NOALLOC_SCRATCH_BYTES (64 MiB) that every device the library
+ * runs on holds until the process ends.  A shape whose workspace exceeds it
+ * returns CGGM_ECAPACITY before any device work: q = n = 1000 (31 MiB),
+ * q = 1500 with n = 1000 (52 MiB) and q = 2000 with n = 500 (54 MiB) fit,
+ * q = 2000 with n = 1000 (77 MiB) does not.  All calls on one device
+ * share that device's array: calls that overlap on one device (from several
+ * host threads, or on several streams) race and must be serialised by the
+ * caller.  The call synchronises `stream` to read f back.
+ */
+#define CGGM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int cggm_objective_noalloc(const void *X, const void *Y, int64_t n, int64_t p, int64_t q,
+                           int dtype, const double *Lambda, const double *Theta, double lamL,
+                           double lamT, double *f_out, void *stream);
 
 /*
  * Gradient of the smooth part g at (Lambda, Theta), Eq. (3):

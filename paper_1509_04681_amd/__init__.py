@@ -6,7 +6,8 @@ memory and the stream.  There is no CPU fallback: importing works without the
 library, but every call raises if ``libcggm.so`` is missing.
 
 Entry points mirror ``include/cggm.h``: :func:`cggm_solve`,
-:func:`cggm_solve_path`, :func:`cggm_objective`, :func:`cggm_gradient`, the
+:func:`cggm_solve_path`, :func:`cggm_objective`,
+:func:`cggm_objective_noalloc`, :func:`cggm_gradient`, the
 request server :class:`Server` (``cggm_server_*``), plus
 ``cggm_status_string`` and the workspace-size queries.
 """
@@ -155,6 +156,9 @@ def load() -> ctypes.CDLL:
     lib.cggm_objective.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_int, _vp, _vp,
                                    ctypes.c_double, ctypes.c_double, _dp, _vp]
     lib.cggm_objective.restype = ctypes.c_int
+    lib.cggm_objective_noalloc.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_int, _vp, _vp,
+                                           ctypes.c_double, ctypes.c_double, _dp, _vp]
+    lib.cggm_objective_noalloc.restype = ctypes.c_int
     lib.cggm_gradient.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_int, _vp, _vp, _vp, _vp,
                                   _vp]
     lib.cggm_gradient.restype = ctypes.c_int
@@ -385,6 +389,23 @@ def cggm_objective(X, Y, Lambda, Theta, lam_Lambda: float, lam_Theta: float,
     _check(lib.cggm_objective(Xp, Yp, n, p, q, dtype, _dev(Lambda, "Lambda"),
                               _dev(Theta, "Theta"), float(lam_Lambda), float(lam_Theta),
                               ctypes.byref(f), _stream(stream)))
+    return f.value
+
+
+def cggm_objective_noalloc(X, Y, Lambda, Theta, lam_Lambda: float, lam_Theta: float,
+                           stream=None) -> float:
+    """cggm_objective from the library's static device scratch (no device
+    allocation); raises CggmError(CGGM_ECAPACITY) for shapes whose workspace
+    exceeds it."""
+    lib = load()
+    n, p = X.shape
+    q = Y.shape[1]
+    f = ctypes.c_double()
+    Xp, Yp, dtype = _inputs(X, Y)
+    _check(lib.cggm_objective_noalloc(Xp, Yp, n, p, q, dtype,
+                                      _dev(Lambda, "Lambda"), _dev(Theta, "Theta"),
+                                      float(lam_Lambda), float(lam_Theta), ctypes.byref(f),
+                                      _stream(stream)))
     return f.value
 
 

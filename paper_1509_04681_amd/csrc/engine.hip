@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <chrono>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -19,6 +20,11 @@
 #include "internal.hpp"
 #include "schedule.hpp"
 #include "solver.hpp"
+
+// Workspace of cggm_objective_noalloc (file scope, one copy per device, held
+// until the process ends).  Host code uses only its per-device address from
+// hipGetSymbolAddress, never the name itself.
+static __device__ __align__(256) char scratch[CGGM_NOALLOC_SCRATCH_BYTES];
 
 namespace cggm {
 namespace {
@@ -1159,6 +1165,49 @@ int objective_impl(const void *X, const void *Y, int64_t n, int64_t p, int64_t q
     return CGGM_OK;
 }
 
+// Device address of the allocation-free entry point's scratch array on the
+// current device, looked up once per device (with that device current) and
+// kept: each device holds its own copy of the array at its own address, and
+// the array's name in host code is only a host-side stand-in.
+std::mutex g_scratch_mu;
+std::vector<void *> g_scratch_addr;
+
+void *scratch_on_current_device() {
+    int dev = 0;
+    CGGM_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_addr.size() <= dev) g_scratch_addr.resize(dev + 1, nullptr);
+    if (!g_scratch_addr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (err != hipSuccess || !ptr)
+            fail(CGGM_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(err));
+        g_scratch_addr[dev] = ptr;
+    }
+    return g_scratch_addr[dev];
+}
+
+int objective_noalloc_impl(const void *X, const void *Y, int64_t n, int64_t p, int64_t q,
+                           int dtype, const double *Lam, const double *Th, double lamL,
+                           double lamT, double *f_out, hipStream_t s) {
+    check_objective_args(X, Y, n, p, q, dtype, Lam, Th, lamL, lamT, f_out);
+    Arena sizer;
+    sizer.measure = true;
+    EvalWork e;
+    eval_layout(sizer, e, n, p, q, false, dtype);
+    if (sizer.used > (size_t)CGGM_NOALLOC_SCRATCH_BYTES)
+        fail(CGGM_ECAPACITY, "cggm_objective_noalloc: the workspace of this shape (" +
+                                 std::to_string(sizer.used) + " bytes) exceeds the " +
+                                 std::to_string((size_t)CGGM_NOALLOC_SCRATCH_BYTES) +
+                                 "-byte static scratch");
+    Arena arena;
+    arena.base = (char *)scratch_on_current_device();
+    eval_layout(arena, e, n, p, q, false, dtype);
+    const auto [X64, Y64] = fp64_inputs(s, dtype, n, p, q, X, Y, e.X64, e.Y64);
+    *f_out = objective_core(X64, Y64, n, p, q, Lam, Th, lamL, lamT, e, s);
+    return CGGM_OK;
+}
+
 int gradient_impl(const void *X_in, const void *Y_in, int64_t n, int64_t p, int64_t q,
                   int dtype, const double *Lam, const double *Th, double *GL, double *GT,
                   hipStream_t s) {
@@ -1316,6 +1365,15 @@ int cggm_objective(const void *X, const void *Y, int64_t n, int64_t p, int64_t q
     });
 }
 
+int cggm_objective_noalloc(const void *X, const void *Y, int64_t n, int64_t p, int64_t q,
+                           int dtype, const double *Lambda, const double *Theta, double lamL,
+                           double lamT, double *f_out, void *stream) {
+    return guarded([&] {
+        return objective_noalloc_impl(X, Y, n, p, q, dtype, Lambda, Theta, lamL, lamT, f_out,
+                                      (hipStream_t)stream);
+    });
+}
+
 int cggm_gradient(const void *X, const void *Y, int64_t n, int64_t p, int64_t q, int dtype,
                   const double *Lambda, const double *Theta, double *G_Lambda, double *G_Theta,
                   void *stream) {
@@ -1335,7 +1393,9 @@ const char *cggm_status_string(int status) {
         case CGGM_ELINESEARCH: return "line search found no Armijo step";
         case CGGM_ENOMEM: return "out of device memory or over the workspace budget";
         case CGGM_EHIP: return "HIP runtime error";
-        case CGGM_ECAPACITY: return "request larger than the server's device memory";
+        case CGGM_ECAPACITY:
+            return "problem larger than the device memory the call may use (server pool or "
+                   "static scratch)";
         default: return "unknown status";
     }
 }

@@ -66,6 +66,8 @@ def test_argument_errors_without_device(lib):
     f = ctypes.c_double()
     assert lib.cggm_objective(fake, fake, 4, 3, 2, 5, fake, fake, 0.1, 0.1, ctypes.byref(f),
                               None) == m.CGGM_EINVAL
+    assert lib.cggm_objective_noalloc(fake, fake, 4, 3, 2, -1, fake, fake, 0.1, 0.1,
+                                      ctypes.byref(f), None) == m.CGGM_EINVAL
     opt = m.Options()
     lib.cggm_default_options(ctypes.byref(opt))
     opt.ls_beta = 1.5
