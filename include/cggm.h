@@ -166,6 +166,26 @@ typedef struct {
                               size move the level (see cggm_solve); 0: the
                               level stays at split_level and a failing sweep
                               is redone with one tile per wave               */
+    int blockwise;         /* 1: block-wise Theta statistics (Sec. 4.2 of the
+                              paper, Algorithm 2): the p x p matrix Sxx is
+                              never formed; the Theta sweep runs by groups of
+                              consecutive row tiles and forms the Sxx columns
+                              of one group at a time from X (X^T X[:, group]
+                              / n on the matrix cores) into a slab of at most
+                              sxx_cache_bytes, skipping groups with no active
+                              coordinate.  Results are those of the dense
+                              mode up to the order of the tiles (with one
+                              group, bit for bit).  Default 0.               */
+    size_t sxx_cache_bytes;/* device bytes of that slab (0 = 2 GiB); at least
+                              one row tile (64 p doubles) is always held     */
+    int graphs;            /* 1: the kernel launches of each tiled sweep are
+                              captured once into a HIP graph and replayed on
+                              later sweeps with the same schedule, buffers,
+                              penalty and precision (fewer host launches for
+                              small problems; results identical).  Not with
+                              kstats, and not for the block-wise Theta sweep
+                              (it decides on the host which groups to form).
+                              Default 0; the request server sets it.          */
 } cggm_options;
 
 /* Fill `opt` with the defaults above. */
@@ -293,6 +313,26 @@ int cggm_objective(const void *X, const void *Y, int64_t n, int64_t p, int64_t q
 int cggm_objective_noalloc(const void *X, const void *Y, int64_t n, int64_t p, int64_t q,
                            int dtype, const double *Lambda, const double *Theta, double lamL,
                            double lamT, double *f_out, void *stream);
+
+/*
+ * One generalized Newton direction of the Lambda step (Algorithm 1, Eq. (6))
+ * at a given point, as cggm_solve computes it: at dense device Lambda
+ * (q x q, symmetric positive definite) and Theta (p x q) it forms Sigma, Psi
+ * and the gradients (Eq. (3)), screens the active set (Sec. 2.2) and makes
+ * opt->lambda_passes coordinate-descent passes over it from D = 0 in the
+ * schedule and precision of `opt` (NULL = defaults; tiled sweeps at
+ * opt->split_level, without the descent guards).  Outputs (caller device
+ * buffers, NULL skips): D (q x q, both triangles), U = D Sigma as maintained
+ * by the passes (q x q; FP32 arithmetic in the mixed mode, widened), and
+ * V = Theta Sigma as the Theta step forms it (p x q; split-BF16 products in
+ * the mixed mode).  For checking the steps of the solver against a
+ * reference; allocates and frees a solve workspace.  Errors as cggm_solve,
+ * CGGM_ENOTPD when Lambda is not positive definite.
+ */
+int cggm_lambda_direction(const void *X, const void *Y, int64_t n, int64_t p, int64_t q,
+                          int dtype, const double *Lambda, const double *Theta, double lamL,
+                          double lamT, const cggm_options *opt, double *D, double *U,
+                          double *V, void *stream);
 
 /*
  * Gradient of the smooth part g at (Lambda, Theta), Eq. (3):

@@ -7,7 +7,8 @@ library, but every call raises if ``libcggm.so`` is missing.
 
 Entry points mirror ``include/cggm.h``: :func:`cggm_solve`,
 :func:`cggm_solve_path`, :func:`cggm_objective`,
-:func:`cggm_objective_noalloc`, :func:`cggm_gradient`, the
+:func:`cggm_objective_noalloc`, :func:`cggm_lambda_direction`,
+:func:`cggm_gradient`, the
 request server :class:`Server` (``cggm_server_*``), plus
 ``cggm_status_string`` and the workspace-size queries.
 """
@@ -66,7 +67,8 @@ class Options(ctypes.Structure):
                 ("trace", ctypes.POINTER(TraceEntry)), ("trace_cap", ctypes.c_int),
                 ("trace_len", ctypes.c_int), ("kstats", ctypes.POINTER(KernelStats)),
                 ("theta_passes", ctypes.c_int), ("split_level", ctypes.c_int),
-                ("split_adapt", ctypes.c_int)]
+                ("split_adapt", ctypes.c_int), ("blockwise", ctypes.c_int),
+                ("sxx_cache_bytes", ctypes.c_size_t), ("graphs", ctypes.c_int)]
 
 
 class Request(ctypes.Structure):
@@ -159,6 +161,10 @@ def load() -> ctypes.CDLL:
     lib.cggm_objective_noalloc.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_int, _vp, _vp,
                                            ctypes.c_double, ctypes.c_double, _dp, _vp]
     lib.cggm_objective_noalloc.restype = ctypes.c_int
+    lib.cggm_lambda_direction.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_int, _vp, _vp,
+                                          ctypes.c_double, ctypes.c_double,
+                                          ctypes.POINTER(Options), _vp, _vp, _vp, _vp]
+    lib.cggm_lambda_direction.restype = ctypes.c_int
     lib.cggm_gradient.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_int, _vp, _vp, _vp, _vp,
                                   _vp]
     lib.cggm_gradient.restype = ctypes.c_int
@@ -234,13 +240,16 @@ class SolveResult:
 
 def _options(lib, *, max_iter, max_ls, ls_beta, ls_sigma, stall_iters, sweep, tile,
              lambda_passes, precision, workspace_budget, warm_Lambda, warm_Theta,
-             mixed_min_q=None, theta_passes=1, split_level=0, split_adapt=True) -> Options:
+             mixed_min_q=None, theta_passes=1, split_level=0, split_adapt=True,
+             blockwise=False, sxx_cache_bytes=0, graphs=False) -> Options:
     opt = Options()
     lib.cggm_default_options(ctypes.byref(opt))
     opt.max_iter, opt.max_ls, opt.ls_beta, opt.ls_sigma = max_iter, max_ls, ls_beta, ls_sigma
     opt.stall_iters, opt.sweep, opt.tile = stall_iters, sweep, tile
     opt.lambda_passes, opt.theta_passes = lambda_passes, theta_passes
     opt.split_level, opt.split_adapt = split_level, int(bool(split_adapt))
+    opt.blockwise, opt.sxx_cache_bytes = int(bool(blockwise)), int(sxx_cache_bytes)
+    opt.graphs = int(bool(graphs))
     opt.precision = PRECISIONS[precision]
     if mixed_min_q is not None:
         opt.mixed_min_q = mixed_min_q
@@ -291,6 +300,7 @@ def cggm_solve(X, Y, lam_Lambda: float, lam_Theta: float, tol: float = 1e-2, *,
                warm_Lambda=None, warm_Theta=None, trace_cap: int | None = None,
                keep_csr: bool = False, kernel_stats: bool = False,
                theta_passes: int = 1, split_level: int = 0, split_adapt: bool = True,
+               blockwise: bool = False, sxx_cache_bytes: int = 0, graphs: bool = False,
                stream=None) -> SolveResult:
     """Alternating Newton CD (Algorithm 1) on device X (n x p) and Y (n x q), float64."""
     lib = load()
@@ -302,7 +312,8 @@ def cggm_solve(X, Y, lam_Lambda: float, lam_Theta: float, tol: float = 1e-2, *,
                    workspace_budget=workspace_budget, warm_Lambda=warm_Lambda,
                    warm_Theta=warm_Theta, mixed_min_q=mixed_min_q,
                    theta_passes=theta_passes, split_level=split_level,
-                   split_adapt=split_adapt)
+                   split_adapt=split_adapt, blockwise=blockwise,
+                   sxx_cache_bytes=sxx_cache_bytes, graphs=graphs)
     cap = (max_iter + 1) if trace_cap is None else trace_cap
     trace_buf = (TraceEntry * max(cap, 1))()
     opt.trace = ctypes.cast(trace_buf, ctypes.POINTER(TraceEntry)) if cap > 0 else None
@@ -338,6 +349,7 @@ def cggm_solve_path(X, Y, lam_Lambda, lam_Theta, tol: float = 1e-2, *,
                     workspace_budget: int = 0, warm_Lambda=None,
                     warm_Theta=None, trace_cap: int | None = None, keep_csr: bool = False,
                     theta_passes: int = 1, split_level: int = 0, split_adapt: bool = True,
+                    blockwise: bool = False, sxx_cache_bytes: int = 0, graphs: bool = False,
                     stream=None) -> list:
     """Warm-started regularisation path: one SolveResult per (lam_Lambda[k], lam_Theta[k])."""
     lib = load()
@@ -354,7 +366,8 @@ def cggm_solve_path(X, Y, lam_Lambda, lam_Theta, tol: float = 1e-2, *,
                    workspace_budget=workspace_budget, warm_Lambda=warm_Lambda,
                    warm_Theta=warm_Theta, mixed_min_q=mixed_min_q,
                    theta_passes=theta_passes, split_level=split_level,
-                   split_adapt=split_adapt)
+                   split_adapt=split_adapt, blockwise=blockwise,
+                   sxx_cache_bytes=sxx_cache_bytes, graphs=graphs)
     cap = npath * (max_iter + 1) if trace_cap is None else trace_cap
     trace_buf = (TraceEntry * max(cap, 1))()
     opt.trace = ctypes.cast(trace_buf, ctypes.POINTER(TraceEntry)) if cap > 0 else None
@@ -409,6 +422,31 @@ def cggm_objective_noalloc(X, Y, Lambda, Theta, lam_Lambda: float, lam_Theta: fl
     return f.value
 
 
+def cggm_lambda_direction(X, Y, Lambda, Theta, lam_Lambda: float, lam_Theta: float, *,
+                          lambda_passes: int = 4, sweep: int = CGGM_SWEEP_TILED, tile: int = 0,
+                          precision: str = "fp64", mixed_min_q: int | None = None,
+                          split_level: int = 0, stream=None):
+    """(D, U, V): one Lambda Newton direction at (Lambda, Theta), the maintained
+    U = D Sigma and V = Theta Sigma as the solver forms them (device tensors)."""
+    import torch
+    lib = load()
+    n, p = X.shape
+    q = Y.shape[1]
+    opt = _options(lib, max_iter=1, max_ls=30, ls_beta=0.5, ls_sigma=1e-3, stall_iters=0,
+                   sweep=sweep, tile=tile, lambda_passes=lambda_passes, precision=precision,
+                   workspace_budget=0, warm_Lambda=None, warm_Theta=None,
+                   mixed_min_q=mixed_min_q, split_level=split_level)
+    D = torch.empty((q, q), dtype=torch.float64, device=X.device)
+    U = torch.empty((q, q), dtype=torch.float64, device=X.device)
+    V = torch.empty((p, q), dtype=torch.float64, device=X.device)
+    Xp, Yp, dtype = _inputs(X, Y)
+    _check(lib.cggm_lambda_direction(Xp, Yp, n, p, q, dtype, _dev(Lambda, "Lambda"),
+                                     _dev(Theta, "Theta"), float(lam_Lambda), float(lam_Theta),
+                                     ctypes.byref(opt), _dev(D, "D"), _dev(U, "U"), _dev(V, "V"),
+                                     _stream(stream)))
+    return D, U, V
+
+
 def cggm_gradient(X, Y, Lambda, Theta, stream=None):
     """(G_Lambda, G_Theta) of Eq. (3) as new device tensors."""
     import torch
@@ -428,11 +466,13 @@ def cggm_solve_workspace_bytes(n: int, p: int, q: int) -> int:
     return int(load().cggm_solve_workspace_bytes(n, p, q))
 
 
-def cggm_workspace_bytes(n: int, p: int, q: int, precision: str = "fp64") -> int:
+def cggm_workspace_bytes(n: int, p: int, q: int, precision: str = "fp64",
+                         blockwise: bool = False, sxx_cache_bytes: int = 0) -> int:
     lib = load()
     opt = Options()
     lib.cggm_default_options(ctypes.byref(opt))
     opt.precision = PRECISIONS[precision]
+    opt.blockwise, opt.sxx_cache_bytes = int(bool(blockwise)), int(sxx_cache_bytes)
     return int(lib.cggm_workspace_bytes(n, p, q, ctypes.byref(opt)))
 
 

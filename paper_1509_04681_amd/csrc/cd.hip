@@ -322,10 +322,14 @@ void sum_snapshots(hipStream_t st, const int *active, int nrect, int S, double *
 // with b = 2 Sxy_ij + 2 (Sxx V)_ij and a = 2 Sxx_ii Sigma_jj; the minimiser is
 // Theta_ij <- S_{lamT/a}(Theta_ij - b/a).  Moving Theta_ij by mu changes the b
 // of coordinate (i', j') by 2 Sxx_i'i Sigma_jj' mu.
+//
+// Sxx is addressed as Sxx[k * ldx + i] for the columns i of the tile's rows
+// (the full matrix with ldx = p, or the column slab of a row group whose base
+// pointer is offset by the group's first column).
 __global__ __launch_bounds__(BLOCK) void theta_gs_kernel(
     const TileRect *__restrict__ rects, const int *__restrict__ active, int S,
     const double *__restrict__ partial, int64_t p, int64_t q, const double *__restrict__ Sxx,
-    const double *__restrict__ Sxy, const double *__restrict__ Sigma,
+    int64_t ldx, const double *__restrict__ Sxy, const double *__restrict__ Sigma,
     const double *__restrict__ GT, double *__restrict__ Theta, double lamT,
     double *__restrict__ dT, int *__restrict__ changed, unsigned long long *__restrict__ ctr,
     int esz) {
@@ -346,7 +350,7 @@ __global__ __launch_bounds__(BLOCK) void theta_gs_kernel(
         Bs[r][c] = (r < R && c < C)
                        ? 2.0 * Sxy[(int64_t)(rc.r0 + r) * q + rc.c0 + c] + 2.0 * snap[k]
                        : 0.0;
-        sxx[r][c] = (r < R && c < R) ? Sxx[(int64_t)(rc.r0 + r) * p + rc.r0 + c] : 0.0;
+        sxx[r][c] = (r < R && c < R) ? Sxx[(int64_t)(rc.r0 + r) * ldx + rc.r0 + c] : 0.0;
         sig[r][c] = (r < C && c < C) ? Sigma[(int64_t)(rc.c0 + r) * q + rc.c0 + c] : 0.0;
     }
     if (ctr && tid == 0) {
@@ -358,9 +362,6 @@ __global__ __launch_bounds__(BLOCK) void theta_gs_kernel(
         // Gauss-Seidel: Sxx[I, I], Sigma[J, J], Sxy / G / Theta reads, Theta and delta writes
         atomicAdd(ctr + 3, (unsigned long long)(8 * (R * R + C * C + 5 * RC)));
         atomicAdd(ctr + 4, (unsigned long long)(4 * RC * C));
-        // update: Sigma[J, :] read, V[I, :] read and written
-        atomicAdd(ctr + 5, (unsigned long long)(esz * q * (C + 2 * R)));
-        atomicAdd(ctr + 6, (unsigned long long)(2 * RC * q));
     }
     __syncthreads();
     if (wid != 0) return;
@@ -443,7 +444,15 @@ __global__ __launch_bounds__(BLOCK) void theta_gs_kernel(
                 if (r2 + u < R) Bs[r2 + u][c] = bv[u] + sxx[r2 + u][r] * w2;
         }
     }
-    if (lane == 0) changed[e] = any_change;
+    if (lane == 0) {
+        changed[e] = any_change;
+        // update (run only for a tile that changed): Sigma[J, :] read, V[I, :]
+        // read and written
+        if (ctr && any_change) {
+            atomicAdd(ctr + 5, (unsigned long long)(esz * q * (C + 2 * R)));
+            atomicAdd(ctr + 6, (unsigned long long)(2 * (int64_t)R * C * q));
+        }
+    }
 }
 
 // Out[m][n] += sum_k op(Delta)[m][k] S[k][n] for m < R, k < Kd and the
@@ -669,11 +678,6 @@ __global__ __launch_bounds__(BLOCK) void lambda_gs_kernel(
         // triangles) and delta writes
         atomicAdd(ctr + 3, (unsigned long long)(8 * (2 * R * R + 2 * C * C + 7 * RC)));
         atomicAdd(ctr + 4, (unsigned long long)(16 * RC * C));
-        // update: Sigma rows read, U rows read and written (both index sets
-        // of an off-diagonal tile)
-        const int64_t ub = diag ? esz * q * 3 * R : esz * q * 3 * (R + C);
-        atomicAdd(ctr + 5, (unsigned long long)ub);
-        atomicAdd(ctr + 6, (unsigned long long)((diag ? 2 : 4) * RC * q));
     }
     __syncthreads();
     if (wid != 0) return;
@@ -851,7 +855,16 @@ __global__ __launch_bounds__(BLOCK) void lambda_gs_kernel(
             }
         }
     }
-    if (lane == 0) changed[e] = any_change;
+    if (lane == 0) {
+        changed[e] = any_change;
+        // update (run only for a tile that changed): Sigma rows read, U rows
+        // read and written (both index sets of an off-diagonal tile)
+        if (ctr && any_change) {
+            const int64_t ub = diag ? esz * q * 3 * R : esz * q * 3 * (R + C);
+            atomicAdd(ctr + 5, (unsigned long long)ub);
+            atomicAdd(ctr + 6, (unsigned long long)((diag ? 2 : 4) * (int64_t)R * C * q));
+        }
+    }
 }
 
 // U[I, :] += dD Sigma[J, :] and U[J, :] += dD^T Sigma[I, :] (off-diagonal
@@ -948,9 +961,9 @@ void lambda_activity(hipStream_t s, const TileRect *rects_dev, int nrect, int64_
 }
 
 void theta_wave(hipStream_t s, const TileRect *rects_dev, const int *active, int nrect,
-                int64_t p, int64_t q, const double *Sxx, const double *Sxy, const double *Sigma,
-                double *V, const double *GT, double *Theta, double lamT, double *dT,
-                int *changed, const CdScratch &scr, const WaveProbe *probe,
+                int64_t p, int64_t q, const double *Sxx, int64_t ldx, const double *Sxy,
+                const double *Sigma, double *V, const double *GT, double *Theta, double lamT,
+                double *dT, int *changed, const CdScratch &scr, const WaveProbe *probe,
                 const SweepF32 *f32) {
     if (nrect <= 0) return;
     constexpr int NB = snap_blocks_per_tile<TT>();
@@ -959,18 +972,19 @@ void theta_wave(hipStream_t s, const TileRect *rects_dev, const int *active, int
     const unsigned nsb = (unsigned)snapshot_blocks((int64_t)nrect * S, NB);
     record(s, probe, 0);
     if (lo) {
-        SnapArgs<1, float> args{{f32->Sxx}, {f32->ldp}, {f32->V}, {f32->ldq}};
+        SnapArgs<1, float> args{{f32->Sxx}, {f32->ldx}, {f32->V}, {f32->ldq}};
         snapshot32_kernel<TT, 1><<<nsb, WAVE, 0, s>>>(rects_dev, active, S, nrect, p, args,
                                                       scr.partial);
     } else {
-        SnapArgs<1, double> args{{Sxx}, {p}, {V}, {q}};
+        SnapArgs<1, double> args{{Sxx}, {ldx}, {V}, {q}};
         snapshot_kernel<TT, 1, double><<<nsb, WAVE, 0, s>>>(rects_dev, active, S, nrect, p, args,
                                                             scr.partial);
     }
     CGGM_LAUNCH_CHECK();
     sum_snapshots<TT>(s, active, nrect, S, scr.partial);
     record(s, probe, 1);
-    theta_gs_kernel<<<nrect, BLOCK, 0, s>>>(rects_dev, active, S, scr.partial, p, q, Sxx, Sxy,
+    theta_gs_kernel<<<nrect, BLOCK, 0, s>>>(rects_dev, active, S, scr.partial, p, q, Sxx, ldx,
+                                            Sxy,
                                             Sigma, GT, Theta, lamT, dT, changed,
                                             probe ? probe->counters : nullptr,
                                             lo ? (int)sizeof(float) : (int)sizeof(double));

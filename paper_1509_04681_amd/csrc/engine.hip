@@ -42,6 +42,15 @@ __global__ void widen_kernel(int64_t count, const float *a, double *b) {   // b 
     if (e < count) b[e] = (double)a[e];
 }
 
+// y (rows x cols, ld ldy) = x (FP32, ld ldx) widened
+__global__ void widen2d_kernel(int64_t rows, int64_t cols, const float *x, int64_t ldx,
+                               double *y, int64_t ldy) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= rows * cols) return;
+    const int64_t r = e / cols, c = e % cols;
+    y[r * ldy + c] = (double)x[r * ldx + c];
+}
+
 __global__ void add_kernel(int64_t count, const double *a, double *b) {   // b += a
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e < count) b[e] += a[e];
@@ -159,17 +168,22 @@ struct Work {
     float *SP32 = nullptr, *Psi32 = nullptr, *Sig32 = nullptr, *U32 = nullptr;
     float *Sxx32 = nullptr, *V32 = nullptr;
     double *X64 = nullptr, *Y64 = nullptr;          // FP64 copies of FP32 inputs
+    int64_t sxx_ld = 0;     // row length of Sxx as the Theta sweep reads it
+    float *Sxx32slab = nullptr;                     // block-wise mode, mixed: FP32 slab
 };
 
 constexpr int NSCAL = 64;
 
 // Layout of the workspace; with a.measure it only sizes it.
+// slab_cols == 0: the full Sxx (p x p); otherwise the block-wise mode's slab
+// of slab_cols columns of Sxx (p x slab_cols) in its place.
 void layout(Arena &a, Work &w, int64_t n, int64_t p, int64_t q, int64_t ntheta_rects,
             int64_t nlambda_rects, int max_tiles, bool mixed = false, bool f32 = false,
-            bool f32_inputs = false) {
+            bool f32_inputs = false, int64_t slab_cols = 0) {
     const int64_t qq = q * q, pq = p * q, nq = n * q;
     w.n = n, w.p = p, w.q = q;
-    w.Sxx = a.take<double>(p * p);
+    w.sxx_ld = slab_cols ? slab_cols : p;
+    w.Sxx = a.take<double>(p * w.sxx_ld);
     w.Sxy = a.take<double>(pq);
     w.Syy = a.take<double>(qq);
     w.Lam = a.take<double>(qq);
@@ -215,7 +229,10 @@ void layout(Arena &a, Work &w, int64_t n, int64_t p, int64_t q, int64_t ntheta_r
         w.Psi32 = a.take<float>(q * lq);
         w.Sig32 = a.take<float>(q * lq);
         w.U32 = a.take<float>(q * lq);
-        w.Sxx32 = a.take<float>(p * lp);
+        if (slab_cols)
+            w.Sxx32slab = a.take<float>(p * slab_cols);
+        else
+            w.Sxx32 = a.take<float>(p * lp);
         w.V32 = a.take<float>(p * lq);
     }
     if (f32_inputs) {
@@ -237,11 +254,67 @@ enum {
     S_NONFIN = 20,   // 2: non-finite counts of X and Y
 };
 
+// Captured launch sequences of the tiled sweeps (options.graphs): the wave
+// loop of a sweep -- a fixed sequence of kernel launches for a given schedule
+// -- is recorded once into a HIP graph and replayed on later sweeps, which
+// saves the host-side cost of hundreds of small launches per pass.  Every
+// kernel argument that can differ between sweeps is part of the key: the
+// schedule, the buffer the swapped parameter currently lives in (the line
+// search swaps Lambda with its trial), the penalty and the precision of the
+// operands.  At most MAX graphs are kept (the oldest is dropped).
+struct SweepGraphs {
+    static constexpr size_t MAX = 32;
+    struct Entry {
+        const Schedule *sch;
+        const void *buf;
+        double lam;
+        bool f32;
+        hipGraphExec_t exec;
+    };
+    std::vector<Entry> cache;
+    int64_t captured = 0, replayed = 0;
+    ~SweepGraphs() {
+        for (auto &e : cache)
+            if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    }
+    template <class F>
+    void run(hipStream_t s, const Schedule *sch, const void *buf, double lam, bool f32,
+             F &&launch) {
+        for (auto &e : cache)
+            if (e.sch == sch && e.buf == buf && e.lam == lam && e.f32 == f32) {
+                CGGM_HIP(hipGraphLaunch(e.exec, s));
+                ++replayed;
+                return;
+            }
+        hipGraph_t g = nullptr;
+        CGGM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        try {
+            launch();
+        } catch (...) {
+            if (hipStreamEndCapture(s, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        CGGM_HIP(hipStreamEndCapture(s, &g));
+        hipGraphExec_t exec = nullptr;
+        const hipError_t err = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        CGGM_HIP(err);
+        if (cache.size() >= MAX) {
+            (void)hipGraphExecDestroy(cache.front().exec);
+            cache.erase(cache.begin());
+        }
+        cache.push_back({sch, buf, lam, f32, exec});
+        ++captured;
+        CGGM_HIP(hipGraphLaunch(exec, s));
+    }
+};
+
 struct Ctx {
     hipStream_t s;
     Work &w;
     double lamL, lamT;
     bool mixed = false;   // split-BF16 V and FP32 sweep operands
+    SweepGraphs *graphs = nullptr;   // capture and replay the sweeps' wave loops
     bool f32() const { return mixed && w.Sig32 != nullptr; }
 };
 
@@ -269,7 +342,7 @@ SweepF32 sweep_operands(const Ctx &c) {
     const Work &w = c.w;
     f.on = true;
     f.ldq = f32_ld(w.q);
-    f.ldp = f32_ld(w.p);
+    f.ldx = f32_ld(w.p);
     f.SP = w.SP32;
     f.Psi = w.Psi32;
     f.Sigma = w.Sig32;
@@ -291,11 +364,16 @@ void refresh_sigma(Ctx &c) {
 constexpr double F_ROUNDING = 1e-14;
 
 // Sxx = X^T X / n, Sxy = X^T Y / n, Syy = Y^T Y / n (uncentred, Sec. 2.1).
-void statistics(Ctx &c, const double *X, const double *Y) {
+// In the block-wise mode Sxx is not formed here: the Theta sweep forms the
+// columns of a row group at a time (Sec. 4.2).
+void statistics(Ctx &c, const double *X, const double *Y, bool full_sxx = true) {
     Work &w = c.w;
     const double inv_n = 1.0 / (double)w.n;
-    gemm(c.s, true, false, w.p, w.p, w.n, inv_n, X, w.p, X, w.p, 0.0, w.Sxx, w.p, UPLO_LOWER);
-    symmetrize_from_lower(c.s, w.p, w.Sxx);
+    if (full_sxx) {
+        gemm(c.s, true, false, w.p, w.p, w.n, inv_n, X, w.p, X, w.p, 0.0, w.Sxx, w.p,
+             UPLO_LOWER);
+        symmetrize_from_lower(c.s, w.p, w.Sxx);
+    }
     gemm(c.s, true, false, w.p, w.q, w.n, inv_n, X, w.p, Y, w.q, 0.0, w.Sxy, w.q);
     gemm(c.s, true, false, w.q, w.q, w.n, inv_n, Y, w.q, Y, w.q, 0.0, w.Syy, w.q, UPLO_LOWER);
     symmetrize_from_lower(c.s, w.q, w.Syy);
@@ -413,20 +491,84 @@ struct KernelTimer {
     }
 };
 
+// Block-wise mode (Sec. 4.2, Algorithm 2): the Theta sweep holds the Sxx
+// columns of one group of `rows` consecutive rows (a slab, p x rows, formed
+// from X on the matrix cores as X^T X[:, group] / n when a wave of that group
+// needs it; Sxx is symmetric, so these are also the rows a tile of the group
+// reads) instead of the whole p x p matrix.  The waves of a group are
+// consecutive, so each group's slab is formed at most once per pass, and
+// groups without an active coordinate are skipped altogether (neither their
+// slab nor their waves run).
+struct SxxSlab {
+    bool on = false;
+    int64_t rows = 0;          // Sxx columns per group (a multiple of the tile edge)
+    const double *X = nullptr;
+    int64_t cur = -1;          // group whose columns the slab holds
+    std::vector<int> act;      // host copy of the rect activity of the sweep
+    int64_t formed = 0;        // slabs formed (statistics)
+};
+
+void form_slab(Ctx &c, SxxSlab &sl, int64_t g) {
+    Work &w = c.w;
+    const int64_t r0 = g * sl.rows, cols = std::min(w.p, r0 + sl.rows) - r0;
+    gemm(c.s, true, false, w.p, cols, w.n, 1.0 / (double)w.n, sl.X, w.p, sl.X + r0, w.p, 0.0,
+         w.Sxx, w.sxx_ld);
+    if (w.Sxx32slab)
+        to_f32(c.s, w.p, cols, w.Sxx, w.sxx_ld, w.Sxx32slab, w.sxx_ld);
+    sl.cur = g;
+    ++sl.formed;
+}
+
 // One CD pass over S_Theta; the activity of the tiles is taken on the first
 // pass (pass == 0) from the top-of-iteration gradient, further passes reuse it.
-void run_theta_sweep(Ctx &c, const Schedule &sch, KernelTimer *kt = nullptr, int pass = 0) {
+void run_theta_sweep(Ctx &c, const Schedule &sch, KernelTimer *kt = nullptr, int pass = 0,
+                     SxxSlab *sl = nullptr) {
     Work &w = c.w;
-    const SweepF32 f32 = sweep_operands(c);
+    SweepF32 f32 = sweep_operands(c);
     if (pass == 0)
         theta_activity(c.s, w.rects_theta, (int)sch.rects.size(), w.q, w.GT, w.Th, c.lamT,
                        w.act_theta);
+    const bool block = sl && sl->on;
+    if (block && pass == 0) {
+        sl->act.resize(sch.rects.size());
+        CGGM_HIP(hipMemcpyAsync(sl->act.data(), w.act_theta, sizeof(int) * sch.rects.size(),
+                                hipMemcpyDeviceToHost, c.s));
+        CGGM_HIP(hipStreamSynchronize(c.s));
+    }
+    if (c.graphs && !block && !(kt && kt->on())) {
+        c.graphs->run(c.s, &sch, w.Th, c.lamT, f32.on, [&] {
+            for (int k = 0; k < sch.waves(); ++k) {
+                const int b = sch.wave_start[k], e = sch.wave_start[k + 1];
+                theta_wave(c.s, w.rects_theta + b, w.act_theta + b, e - b, w.p, w.q, w.Sxx, w.p,
+                           w.Sxy, w.Sig, w.V, w.GT, w.Th, c.lamT, w.dT, w.changed, w.cd, nullptr,
+                           &f32);
+            }
+        });
+        return;
+    }
     for (int k = 0; k < sch.waves(); ++k) {
         const int b = sch.wave_start[k], e = sch.wave_start[k + 1];
+        const double *Sxx = w.Sxx;
+        int64_t ldx = w.p;
+        if (block) {
+            bool any = false;
+            for (int r = b; r < e && !any; ++r) any = sl->act[r] != 0;
+            if (!any) continue;
+            const int64_t g = sch.rects[b].r0 / sl->rows;
+            if (g != sl->cur) form_slab(c, *sl, g);
+            // column i of the group at Sxx[k * ldx + i]: the slab shifted by the
+            // group's first column
+            Sxx = w.Sxx - g * sl->rows;
+            ldx = w.sxx_ld;
+            if (f32.on) {
+                f32.Sxx = w.Sxx32slab - g * sl->rows;
+                f32.ldx = w.sxx_ld;
+            }
+        }
         WaveProbe pr;
         if (kt && kt->on()) pr = kt->probe();
-        theta_wave(c.s, w.rects_theta + b, w.act_theta + b, e - b, w.p, w.q, w.Sxx, w.Sxy, w.Sig,
-                   w.V, w.GT, w.Th, c.lamT, w.dT, w.changed, w.cd,
+        theta_wave(c.s, w.rects_theta + b, w.act_theta + b, e - b, w.p, w.q, Sxx, ldx, w.Sxy,
+                   w.Sig, w.V, w.GT, w.Th, c.lamT, w.dT, w.changed, w.cd,
                    (kt && kt->on()) ? &pr : nullptr, &f32);
     }
 }
@@ -444,6 +586,17 @@ void run_lambda_sweep(Ctx &c, const Schedule &sch, KernelTimer *kt = nullptr, in
             fill(c.s, w.q * w.q, 0.0, w.U);
         lambda_activity(c.s, w.rects_lambda, (int)sch.rects.size(), w.q, w.GL, w.Lam, c.lamL,
                         w.act_lambda);
+    }
+    if (c.graphs && !(kt && kt->on())) {
+        c.graphs->run(c.s, &sch, w.Lam, c.lamL, f32.on, [&] {
+            for (int k = 0; k < sch.waves(); ++k) {
+                const int b = sch.wave_start[k], e = sch.wave_start[k + 1];
+                lambda_wave(c.s, w.rects_lambda + b, w.act_lambda + b, e - b, w.q, w.Sig, w.Psi,
+                            w.SP, w.GL, w.Lam, c.lamL, w.D, w.U, w.dD, w.changed, w.cd, nullptr,
+                            &f32);
+            }
+        });
+        return;
     }
     for (int k = 0; k < sch.waves(); ++k) {
         const int b = sch.wave_start[k], e = sch.wave_start[k + 1];
@@ -526,7 +679,8 @@ cggm_options checked_options(const cggm_options *opt_in) {
     if (opt.max_iter < 0 || opt.max_ls < 1 || !(opt.ls_beta > 0.0 && opt.ls_beta < 1.0) ||
         !(opt.ls_sigma > 0.0 && opt.ls_sigma < 1.0) || opt.stall_iters < 0 ||
         opt.lambda_passes < 1 || opt.mixed_min_q < 0 || opt.theta_passes < 1 ||
-        opt.split_level < 0 || opt.split_level > 6 ||
+        opt.split_level < 0 || opt.split_level > 6 || (opt.blockwise != 0 && opt.blockwise != 1) ||
+        (opt.graphs != 0 && opt.graphs != 1) ||
         (opt.precision != CGGM_PRECISION_FP64 && opt.precision != CGGM_PRECISION_MIXED) ||
         (opt.sweep != CGGM_SWEEP_TILED && opt.sweep != CGGM_SWEEP_SEQUENTIAL))
         fail(CGGM_EINVAL, "invalid options");
@@ -552,6 +706,8 @@ struct Solver::Impl {
     Work w;
     const double *X = nullptr;
     KernelTimer kt_lambda, kt_theta;
+    SxxSlab slab;                 // block-wise mode: the Theta sweep's Sxx columns
+    SweepGraphs graphs;           // options.graphs: captured sweep launch sequences
     hipEvent_t ev[5] = {};
     std::chrono::steady_clock::time_point t0;
     int trace_len = 0;
@@ -564,7 +720,21 @@ struct Solver::Impl {
         mixed = opt.precision == CGGM_PRECISION_MIXED && q >= opt.mixed_min_q;
         seq = opt.sweep == CGGM_SWEEP_SEQUENTIAL;
         const auto [tileL, tileT] = tile_edges(opt.tile);
-        th_sched = theta_schedule(p, q, tileT, seq);
+        if (opt.blockwise) {
+            // Sxx columns per group from the budget (Sec. 4.2: as many columns as
+            // fit), whole row tiles, at least one: 8 bytes per entry, 12 in the
+            // mixed mode (FP32 copy).
+            const size_t budget = opt.sxx_cache_bytes ? opt.sxx_cache_bytes : (size_t(2) << 30);
+            const int64_t per_tile = (int64_t)tileT * p * (mixed ? 12 : 8);
+            const int64_t P = (p + tileT - 1) / tileT;
+            const int64_t G = std::max<int64_t>(1, std::min<int64_t>(P, (int64_t)budget / per_tile));
+            slab.on = true;
+            slab.rows = G * tileT;
+            th_sched = seq ? theta_schedule(p, q, tileT, true)
+                           : theta_schedule_grouped(p, q, tileT, G);
+        } else {
+            th_sched = theta_schedule(p, q, tileT, seq);
+        }
         la_sched = lambda_schedule(q, tileL, seq);
         for (auto [src, dst] : {std::pair<Schedule *, Schedule *>{&th_sched, &th_safe},
                                 std::pair<Schedule *, Schedule *>{&la_sched, &la_safe}}) {
@@ -586,7 +756,8 @@ struct Solver::Impl {
     }
     void lay(Arena &a) {
         layout(a, w, n, p, q, (int64_t)th_sched.rects.size(), (int64_t)la_sched.rects.size(),
-               max_tiles, mixed, mixed, dtype == CGGM_F32);
+               max_tiles, mixed, mixed, dtype == CGGM_F32,
+               slab.on ? std::min(slab.rows, (p + 63) / 64 * 64) : 0);
     }
     const Schedule &split_sched(std::vector<std::unique_ptr<Schedule>> &cache,
                                 const Schedule &base, int level) {
@@ -638,9 +809,11 @@ struct Solver::Impl {
             kt_theta.init(w.kctr + 8);
         }
         t0 = std::chrono::steady_clock::now();
-        statistics(c, X, Y);
+        statistics(c, X, Y, !slab.on);
+        slab.X = X;
+        slab.cur = -1;
         if (c.f32()) {
-            to_f32(s, p, p, w.Sxx, p, w.Sxx32, f32_ld(p));
+            if (!slab.on) to_f32(s, p, p, w.Sxx, p, w.Sxx32, f32_ld(p));
             fill_f32(s, p * f32_ld(q), 0.0f, w.V32);   // the padding columns stay zero
         }
         loaded = true;
@@ -674,7 +847,42 @@ struct Solver::Impl {
         started = true;
     }
     SolveOutcome run(double lamL, double lamT, double tol);
+    void direction(double lamL, double lamT, double *D_out, double *U_out, double *V_out);
 };
+
+// One Lambda direction at the current iterate (the top-of-iteration
+// evaluation, the active sets and options.lambda_passes CD passes, in the
+// run's precision and schedule at options.split_level) and V = Theta Sigma as
+// the Theta step forms it; D, the maintained U = D Sigma and V are copied out
+// in FP64.  The iterate is not changed.
+void Solver::Impl::direction(double lamL, double lamT, double *D_out, double *U_out,
+                             double *V_out) {
+    if (!started) fail(CGGM_EINVAL, "direction before start");
+    check_lambda(lamL, lamT);
+    Ctx c{s, w, lamL, lamT, mixed};
+    reduce_dot(s, w.n * q, w.A, w.R, w.partials, w.scal + S_AR);
+    gradients(c, X);
+    const Schedule &sch = split_sched(la_split, la_sched, seq ? 0 : opt.split_level);
+    for (int pass = 0; pass < opt.lambda_passes; ++pass) run_lambda_sweep(c, sch, nullptr, pass);
+    theta_sigma(c);
+    const int64_t qq = q * q;
+    auto out2d = [&](double *dst, int64_t rows, const double *src64, const float *src32) {
+        if (!dst) return;
+        if (src32) {
+            const int64_t count = rows * q;
+            widen2d_kernel<<<nblk(count), BLOCK, 0, s>>>(rows, q, src32, f32_ld(q), dst, q);
+            CGGM_LAUNCH_CHECK();
+        } else {
+            CGGM_HIP(hipMemcpyAsync(dst, src64, sizeof(double) * rows * q, hipMemcpyDeviceToDevice,
+                                    s));
+        }
+    };
+    if (D_out)
+        CGGM_HIP(hipMemcpyAsync(D_out, w.D, sizeof(double) * qq, hipMemcpyDeviceToDevice, s));
+    out2d(U_out, q, w.U, c.f32() ? w.U32 : nullptr);
+    out2d(V_out, p, w.V, c.f32() ? w.V32 : nullptr);
+    CGGM_HIP(hipStreamSynchronize(s));
+}
 
 // Algorithm 1 from the current iterate (Lambda, its factor L, Sigma, Theta,
 // A = X Theta and R = A Sigma all current) to the stopping rule.  On return
@@ -684,6 +892,7 @@ SolveOutcome Solver::Impl::run(double lamL, double lamT, double tol) {
     check_lambda(lamL, lamT);
     if (!(tol >= 0.0) || !isfinite(tol)) fail(CGGM_EINVAL, "tol must be finite and >= 0");
     Ctx c{s, w, lamL, lamT, mixed};
+    if (opt.graphs && !seq) c.graphs = &graphs;
     // Mixed mode forms V from split-BF16 products while the iterate is far
     // from the optimum and switches to FP64 for the rest of the run once the
     // subgradient falls below MIXED_FP64_BELOW of the stopping scale: the
@@ -753,7 +962,8 @@ SolveOutcome Solver::Impl::run(double lamL, double lamT, double tol) {
             c.mixed = false;
             swept_mixed = false;
             theta_sigma(c);
-            for (int pass = 0; pass < opt.theta_passes; ++pass) run_theta_sweep(c, *sch, nullptr, pass);
+            for (int pass = 0; pass < opt.theta_passes; ++pass)
+                run_theta_sweep(c, *sch, nullptr, pass, &slab);
             ++last_fallbacks;
             theta_products(c, X);
             evaluate();
@@ -939,7 +1149,8 @@ SolveOutcome Solver::Impl::run(double lamL, double lamT, double tol) {
         swept_mixed = c.mixed;
         theta_sigma(c);                                              // V = Theta Sigma
         for (int pass = 0; pass < opt.theta_passes; ++pass)
-            run_theta_sweep(c, split_sched(th_split, th_sched, th_level), &kt_theta, pass);
+            run_theta_sweep(c, split_sched(th_split, th_sched, th_level), &kt_theta, pass,
+                            &slab);
         theta_products(c, X);
     }
     SolveOutcome o;
@@ -962,6 +1173,9 @@ SolveOutcome Solver::run(double lamL, double lamT, double tol) {
     return impl_->run(lamL, lamT, tol);
 }
 int Solver::trace_len() const { return impl_->trace_len; }
+void Solver::direction(double lamL, double lamT, double *D, double *U, double *V) {
+    impl_->direction(lamL, lamT, D, U, V);
+}
 
 void Solver::copy_dense(double *Lambda, double *Theta) {
     Impl &m = *impl_;
@@ -1072,6 +1286,26 @@ int solve_path_impl(const void *X, const void *Y, int64_t n, int64_t p, int64_t 
     if (opt_in) opt_in->trace_len = sv.trace_len();
     for (int k = 0; k < npath; ++k) out[k] = reinterpret_cast<cggm_result *>(res[k].release());
     return status;
+}
+
+int direction_impl(const void *X, const void *Y, int64_t n, int64_t p, int64_t q, int dtype,
+                   const double *Lam, const double *Th, double lamL, double lamT,
+                   cggm_options *opt_in, double *D, double *U, double *V, hipStream_t s) {
+    if (!X || !Y || !Lam || !Th) fail(CGGM_EINVAL, "NULL pointer argument");
+    check_sizes(n, p, q);
+    check_dtype(dtype);
+    check_lambda(lamL, lamT);
+    cggm_options opt = checked_options(opt_in);
+    opt.warm_Lambda = Lam;
+    opt.warm_Theta = Th;
+    opt.trace = nullptr;
+    opt.kstats = nullptr;
+    Solver sv(n, p, q, &opt, s, dtype);
+    sv.allocate();
+    sv.load(X, Y);
+    sv.start();
+    sv.direction(lamL, lamT, D, U, V);
+    return CGGM_OK;
 }
 
 // ------------------------------------------------------- objective/gradient --
@@ -1278,6 +1512,9 @@ void cggm_default_options(cggm_options *opt) {
     opt->theta_passes = 1;
     opt->split_level = 0;
     opt->split_adapt = 1;
+    opt->blockwise = 0;
+    opt->sxx_cache_bytes = 0;
+    opt->graphs = 0;
 }
 
 size_t cggm_solve_workspace_bytes(int64_t n, int64_t p, int64_t q) {
@@ -1371,6 +1608,19 @@ int cggm_objective_noalloc(const void *X, const void *Y, int64_t n, int64_t p, i
     return guarded([&] {
         return objective_noalloc_impl(X, Y, n, p, q, dtype, Lambda, Theta, lamL, lamT, f_out,
                                       (hipStream_t)stream);
+    });
+}
+
+int cggm_lambda_direction(const void *X, const void *Y, int64_t n, int64_t p, int64_t q,
+                          int dtype, const double *Lambda, const double *Theta, double lamL,
+                          double lamT, const cggm_options *opt, double *D, double *U,
+                          double *V, void *stream) {
+    return guarded([&] {
+        cggm_options o;
+        cggm_default_options(&o);
+        if (opt) o = *opt;
+        return direction_impl(X, Y, n, p, q, dtype, Lambda, Theta, lamL, lamT, &o, D, U, V,
+                              (hipStream_t)stream);
     });
 }
 

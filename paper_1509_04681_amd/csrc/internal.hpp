@@ -179,7 +179,9 @@ struct CdScratch {
 // the Gauss-Seidel stage still reads FP64 blocks and writes FP64 parameters.
 struct SweepF32 {
     bool on = false;
-    int64_t ldq = 0, ldp = 0;   // row lengths: q and p rounded up to 4 (padding zero)
+    int64_t ldq = 0;            // row length of the q-column arrays: q rounded up to 4
+    int64_t ldx = 0;            // row length of Sxx as streamed (p rounded up to 4, or
+                                // the slab width in the block-wise mode; padding zero)
     const float *SP = nullptr, *Psi = nullptr, *Sigma = nullptr, *Sxx = nullptr;  // q or p rows
     float *U = nullptr, *V = nullptr;
 };
@@ -196,10 +198,12 @@ void lambda_activity(hipStream_t s, const TileRect *rects_dev, int nrect, int64_
 // runs exact Gauss-Seidel over its active coordinates from a snapshot of
 // b = 2 Sxy + 2 Sxx V, writes the updated Theta and its delta (dT, nrect
 // tiles of THETA_TILE^2), then V[rows, :] += dTheta Sigma[cols, :].
+// Sxx: element (k, i) at Sxx[k * ldx + i] for every row k and every column i
+// of the wave's tile rows (the full matrix with ldx = p, or a column slab).
 void theta_wave(hipStream_t s, const TileRect *rects_dev, const int *active, int nrect,
-                int64_t p, int64_t q, const double *Sxx, const double *Sxy, const double *Sigma,
-                double *V, const double *GT, double *Theta, double lamT, double *dT,
-                int *changed, const CdScratch &scr, const WaveProbe *probe = nullptr,
+                int64_t p, int64_t q, const double *Sxx, int64_t ldx, const double *Sxy,
+                const double *Sigma, double *V, const double *GT, double *Theta, double lamT,
+                double *dT, int *changed, const CdScratch &scr, const WaveProbe *probe = nullptr,
                 const SweepF32 *f32 = nullptr);
 
 // The three stages of a Lambda wave (lambda_wave runs them in order).

@@ -62,6 +62,35 @@ inline Schedule theta_schedule(int64_t p, int64_t q, int tile, bool sequential) 
     return s;
 }
 
+// Theta by row groups (block-wise mode): the row tiles are taken in groups of
+// `group` consecutive row tiles, and each group's tiles are scheduled like the
+// whole matrix above -- tile (I, J) of the group in wave (J - I') mod W_g,
+// I' = I - first row tile of the group, W_g = max(#row tiles of the group,
+// #column blocks) -- so every wave is row- and column-disjoint and lies in one
+// group, and the waves of a group are consecutive (the group's Sxx columns
+// are formed once per sweep).  With group >= #row tiles it is theta_schedule.
+inline Schedule theta_schedule_grouped(int64_t p, int64_t q, int tile, int64_t group) {
+    Schedule s;
+    s.wave_start.push_back(0);
+    const int64_t P = (p + tile - 1) / tile, Q = (q + tile - 1) / tile;
+    for (int64_t g0 = 0; g0 < P; g0 += group) {
+        const int64_t G = std::min(group, P - g0), W = std::max(G, Q);
+        for (int64_t w = 0; w < W; ++w) {
+            bool any = false;
+            for (int64_t I = 0; I < G; ++I) {
+                const int64_t J = (I + w) % W;
+                if (J >= Q) continue;
+                const int64_t r = g0 + I;
+                s.rects.push_back(rect(r * tile, std::min(p, (r + 1) * tile), J * tile,
+                                       std::min(q, (J + 1) * tile)));
+                any = true;
+            }
+            if (any) s.finish_wave();
+        }
+    }
+    return s;
+}
+
 // Lambda: first the wave of all diagonal tiles, then the rounds of a
 // round-robin pairing of the column blocks (each block once per round).
 inline Schedule lambda_schedule(int64_t q, int tile, bool sequential) {

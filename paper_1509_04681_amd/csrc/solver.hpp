@@ -48,6 +48,9 @@ class Solver {
     // A result handle of the current iterate (dense copies and CSR).
     cggm_result *make_result(const SolveOutcome &o);
     int trace_len() const;
+    // One Lambda direction at the current iterate and V = Theta Sigma, copied
+    // to device buffers (NULL skips): D, U = D Sigma (q x q), V (p x q).
+    void direction(double lamL, double lamT, double *D, double *U, double *V);
     void finish_kernel_stats();          // fills options.kstats if given
 
   private:

@@ -8,7 +8,7 @@ int main(){
 R(X)R(Y)R(n)R(p)R(q)R(npath)R(lamL)R(lamT)R(tol)R(precision)R(max_iter)R(lambda_passes)R(mixed_min_q)R(Lambda_out)R(Theta_out)R(dtype)
 printf("req size %zu\n", sizeof(cggm_request));
 #define O(f) printf("opt %s %zu\n", #f, offsetof(cggm_options, f));
-O(max_iter)O(max_ls)O(ls_beta)O(ls_sigma)O(stall_iters)O(sweep)O(tile)O(lambda_passes)O(precision)O(mixed_min_q)O(workspace_budget)O(warm_Lambda)O(warm_Theta)O(trace)O(trace_cap)O(trace_len)O(kstats)O(theta_passes)O(split_level)O(split_adapt)
+O(max_iter)O(max_ls)O(ls_beta)O(ls_sigma)O(stall_iters)O(sweep)O(tile)O(lambda_passes)O(precision)O(mixed_min_q)O(workspace_budget)O(warm_Lambda)O(warm_Theta)O(trace)O(trace_cap)O(trace_len)O(kstats)O(theta_passes)O(split_level)O(split_adapt)O(blockwise)O(sxx_cache_bytes)O(graphs)
 printf("opt size %zu\n", sizeof(cggm_options));
 #define I(f) printf("info %s %zu\n", #f, offsetof(cggm_request_info, f));
 I(status)I(slot)I(iters_total)I(t_submit_ms)I(t_admit_ms)I(t_done_ms)I(footprint)

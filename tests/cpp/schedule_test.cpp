@@ -145,6 +145,39 @@ static int dump(int64_t q, int tile, int parts) {
     return 0;
 }
 
+// Grouped Theta schedule: every tile once, waves row- and column-disjoint,
+// each wave inside one group of `group` row tiles, the waves of a group
+// consecutive; with one group it equals theta_schedule.
+static void theta_grouped(int64_t p, int64_t q, int tile, int64_t group) {
+    const Schedule s = theta_schedule_grouped(p, q, tile, group);
+    check_waves(s);
+    const int64_t P = (p + tile - 1) / tile, Q = (q + tile - 1) / tile;
+    std::set<std::pair<int, int>> seen;
+    int64_t last_group = -1;
+    for (int w = 0; w < s.waves(); ++w) {
+        std::set<int> rows, cols;
+        const int64_t g = (s.rects[s.wave_start[w]].r0 / tile) / group;
+        CHECK(g >= last_group);                       // groups in order, consecutive
+        last_group = g;
+        for (int k = s.wave_start[w]; k < s.wave_start[w + 1]; ++k) {
+            const TileRect &r = s.rects[k];
+            CHECK((r.r0 / tile) / group == g);
+            CHECK(rows.insert(r.r0).second && cols.insert(r.c0).second);
+            CHECK(r.r0 % tile == 0 && r.c0 % tile == 0);
+            CHECK(r.r1 == std::min<int64_t>(p, r.r0 + tile));
+            CHECK(r.c1 == std::min<int64_t>(q, r.c0 + tile));
+            CHECK(seen.insert({r.r0, r.c0}).second);
+        }
+    }
+    CHECK((int64_t)seen.size() == P * Q);
+    if (group >= P) {
+        const Schedule t = theta_schedule(p, q, tile, false);
+        CHECK(t.wave_start == s.wave_start);
+        for (size_t k = 0; k < t.rects.size(); ++k)
+            CHECK(t.rects[k].r0 == s.rects[k].r0 && t.rects[k].c0 == s.rects[k].c0);
+    }
+}
+
 int main(int argc, char **argv) {
     if (argc == 5 && std::string(argv[1]) == "dump")
         return dump(atoll(argv[2]), atoi(argv[3]), atoi(argv[4]));
@@ -158,6 +191,10 @@ int main(int argc, char **argv) {
     lambda(515, 32);
     for (int parts : {1, 2, 3, 4, 64, 1000})
         for (int64_t q : {64, 130, 640, 1000, 20000}) split(q, parts);
+    for (int64_t group : {1, 2, 3, 5, 64, 1000})
+        for (int64_t p : {1, 64, 130, 700, 2000})
+            for (int64_t q : {1, 65, 640}) theta_grouped(p, q, 64, group);
+    theta_grouped(20000, 4000, 64, 83);
     sequential(5, 7);
     sequential(1, 1);
     printf("schedule: %d checks passed\n", checks);

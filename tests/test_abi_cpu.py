@@ -157,6 +157,26 @@ def test_path_and_workspace_arguments_without_device(lib):
     assert lib.cggm_workspace_bytes(0, 200, 100, None) == 0
 
 
+def test_blockwise_footprint(lib):
+    """The block-wise mode holds a slab of Sxx columns (the budget, whole row
+    tiles of 64 p doubles, at least one) in place of the p x p matrix."""
+    import paper_1509_04681_amd as m
+    n, p, q = 1000, 20000, 4000
+    dense = m.cggm_workspace_bytes(n, p, q)
+    block = m.cggm_workspace_bytes(n, p, q, blockwise=True, sxx_cache_bytes=1 << 30)
+    slab = (1 << 30) // (64 * p * 8) * 64 * p * 8
+    assert dense - block == 8 * p * p - slab
+    tiny = m.cggm_workspace_bytes(n, p, q, blockwise=True, sxx_cache_bytes=1)
+    assert dense - tiny == 8 * p * p - 64 * p * 8
+    # the block-wise configuration's size: p = 200000, q = 40000 -- Sxx alone
+    # would be 320 GB; the dense p x q arrays (Theta, V, the gradient, Sxy and
+    # the guard's copy of Theta, 64 GB each) still exceed one device
+    big_dense = m.cggm_workspace_bytes(n, 200000, 40000)
+    big_block = m.cggm_workspace_bytes(n, 200000, 40000, blockwise=True)
+    assert big_dense - big_block == 8 * 200000 ** 2 - (2 << 30) // (64 * 200000 * 8) * 64 * 200000 * 8
+    assert big_block > 288e9
+
+
 def test_server_arguments_without_device(lib):
     import paper_1509_04681_amd as m
     h = ctypes.c_void_p()

@@ -1,0 +1,94 @@
+"""The Lambda step's Newton direction (Algorithm 1, Eq. (6)) on its own,
+through cggm_lambda_direction: in the oracle's coordinate order the GPU's
+direction D equals the oracle's element by element; the maintained U = D Sigma
+and V = Theta Sigma equal their definitions.  In the mixed mode the same
+quantities are compared with the FP64 path element by element; the measured
+errors are printed and bounded (the bounds are stated with the mixed mode's
+description)."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cg():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1509_04681_amd as m
+    m.load()
+    return m
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.build()
+    return oracle
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda:0")
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def iterate(cg, pr, iters):
+    """A realistic point: the FP64 solver's iterate after `iters` iterations."""
+    r = cg.cggm_solve(dev(pr.X), dev(pr.Y), pr.lam_Lambda, pr.lam_Theta, tol=0.0,
+                      max_iter=iters, stall_iters=0, trace_cap=0)
+    return r.Lambda.cpu().numpy(), r.Theta.cpu().numpy()
+
+
+@pytest.mark.parametrize("p,q,n,passes", [(40, 50, 60, 1), (70, 33, 90, 3)])
+def test_sequential_direction_matches_oracle(cg, orc, p, q, n, passes):
+    pr = synth.chain_problem(p=p, q=q, n=n, density=0.05, lam=0.08, seed=p + q)
+    Lam, Th = iterate(cg, pr, 3)
+    D, U, V = cg.cggm_lambda_direction(dev(pr.X), dev(pr.Y), dev(Lam), dev(Th),
+                                       pr.lam_Lambda, pr.lam_Theta, lambda_passes=passes,
+                                       sweep=cg.CGGM_SWEEP_SEQUENTIAL)
+    S = orc.stats(pr.X, pr.Y)
+    GL, GT, Sig, Psi = orc.gradient(S, Lam, Th)
+    aL, _ = orc.active_sets(GL, GT, Lam, Th, pr.lam_Lambda, pr.lam_Theta)
+    Do = orc.lambda_direction(Sig, Psi, GL, Lam, aL, pr.lam_Lambda, passes=passes)
+    D, U, V = D.cpu().numpy(), U.cpu().numpy(), V.cpu().numpy()
+    print(f"p={p} q={q} passes={passes}: |D - D_oracle| rel {rel(D, Do):.2e}, "
+          f"nnz D {np.count_nonzero(D)} / oracle {np.count_nonzero(Do)}", flush=True)
+    assert np.count_nonzero(Do) > 0
+    np.testing.assert_allclose(D, Do, rtol=1e-10, atol=1e-12 * np.abs(Do).max())
+    assert np.array_equal(D == 0, Do == 0)
+    assert rel(U, D @ Sig) < 1e-12
+    assert rel(V, Th @ Sig) < 1e-12
+
+
+@pytest.mark.parametrize("p,q,n", [(530, 530, 200), (4096, 4096, 500)])
+def test_mixed_mode_errors_per_result(cg, orc, p, q, n):
+    """Mixed against FP64 at the same point (the FP64 iterate after 3
+    iterations): V = Theta Sigma from split-BF16 products, U = D Sigma
+    maintained in FP32 by the FP32 sweeps, and the direction D itself."""
+    pr = synth.chain_problem(p=p, q=q, n=n, density=0.01, lam=0.05, seed=7)
+    Lam, Th = iterate(cg, pr, 3)
+    X, Y, L, T = dev(pr.X), dev(pr.Y), dev(Lam), dev(Th)
+    d64, u64, v64 = (a.cpu().numpy() for a in cg.cggm_lambda_direction(
+        X, Y, L, T, pr.lam_Lambda, pr.lam_Theta))
+    dmx, umx, vmx = (a.cpu().numpy() for a in cg.cggm_lambda_direction(
+        X, Y, L, T, pr.lam_Lambda, pr.lam_Theta, precision="mixed", mixed_min_q=0))
+    Sig = np.linalg.inv(Lam)
+    e_v = rel(vmx, Th @ Sig)
+    e_v64 = rel(v64, Th @ Sig)
+    e_u = rel(umx, dmx @ Sig)
+    e_d = rel(dmx, d64)
+    supp = int(((np.abs(dmx) > 1e-6) != (np.abs(d64) > 1e-6)).sum())
+    print(f"p={p} q={q}: V split-bf16 {e_v:.2e} (fp64 {e_v64:.2e}); U fp32 {e_u:.2e}; "
+          f"D mixed vs fp64 {e_d:.2e}; D support differences {supp} of "
+          f"{int((np.abs(d64) > 1e-6).sum())}", flush=True)
+    assert e_v64 < 1e-12
+    assert e_v < 1e-5
+    assert e_u < 1e-5
+    assert e_d < 1e-3
