@@ -137,7 +137,10 @@ typedef struct {
     int sweep;             /* CGGM_SWEEP_TILED or CGGM_SWEEP_SEQUENTIAL        */
     int tile;              /* CD tile edge for CGGM_SWEEP_TILED (0 = default)  */
     int lambda_passes;     /* CD passes of the Lambda direction over S_Lambda
-                              per iteration (Sec. 3 makes one; default 4)     */
+                              per iteration (Sec. 3 makes one); 0 (default):
+                              4 when n >= q / 4, else 6 -- with fewer samples
+                              Syy has low rank and the direction needs more
+                              passes                                          */
     int precision;         /* CGGM_PRECISION_FP64 (default) or
                               CGGM_PRECISION_MIXED                             */
     int mixed_min_q;       /* CGGM_PRECISION_MIXED applies to problems with
@@ -315,6 +318,22 @@ int cggm_objective_noalloc(const void *X, const void *Y, int64_t n, int64_t p, i
                            double lamT, double *f_out, void *stream);
 
 /*
+ * Tile-edge autotuner for problems of shape (n, p, q): runs a synthetic
+ * problem of that shape (X, Y standard normal from a deterministic
+ * counter-based generator, lambda = 0.02, near-dense active sets) with the
+ * options `opt` (NULL = defaults) and each candidate tile edge 16, 32, 64 for
+ * one warm-up and `iters` (1..50) timed outer iterations from Lambda = I,
+ * Theta = 0, and writes the edge with the shortest time per iteration to
+ * *tile (host) and, when `ms` is not NULL, the three times in milliseconds
+ * (host, 3 doubles).  Pass the edge as options.tile (or a request's tile) for
+ * problems of about that shape.  The choice changes the order of the
+ * coordinate updates, hence the iterates, not the optimum.  Allocates its
+ * own inputs and one solve workspace at a time; blocking.
+ */
+int cggm_autotune_tile(int64_t n, int64_t p, int64_t q, const cggm_options *opt, int iters,
+                       int *tile, double *ms, void *stream);
+
+/*
  * One generalized Newton direction of the Lambda step (Algorithm 1, Eq. (6))
  * at a given point, as cggm_solve computes it: at dense device Lambda
  * (q x q, symmetric positive definite) and Theta (p x q) it forms Sigma, Psi
@@ -377,6 +396,7 @@ typedef struct {
     double *Lambda_out;       /* device npath x q x q, or NULL                    */
     double *Theta_out;        /* device npath x p x q, or NULL                    */
     int dtype;                /* CGGM_F64 (0) or CGGM_F32                          */
+    int tile;                 /* CD tile edge (0 = default; cggm_autotune_tile)   */
 } cggm_request;
 
 typedef struct {

@@ -76,7 +76,8 @@ class Request(ctypes.Structure):
                 ("npath", ctypes.c_int), ("lamL", _dp), ("lamT", _dp), ("tol", ctypes.c_double),
                 ("precision", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("lambda_passes", ctypes.c_int), ("mixed_min_q", ctypes.c_int),
-                ("Lambda_out", _vp), ("Theta_out", _vp), ("dtype", ctypes.c_int)]
+                ("Lambda_out", _vp), ("Theta_out", _vp), ("dtype", ctypes.c_int),
+                ("tile", ctypes.c_int)]
 
 
 class RequestInfo(ctypes.Structure):
@@ -161,6 +162,9 @@ def load() -> ctypes.CDLL:
     lib.cggm_objective_noalloc.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_int, _vp, _vp,
                                            ctypes.c_double, ctypes.c_double, _dp, _vp]
     lib.cggm_objective_noalloc.restype = ctypes.c_int
+    lib.cggm_autotune_tile.argtypes = [_i64, _i64, _i64, ctypes.POINTER(Options), ctypes.c_int,
+                                       ctypes.POINTER(ctypes.c_int), _dp, _vp]
+    lib.cggm_autotune_tile.restype = ctypes.c_int
     lib.cggm_lambda_direction.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_int, _vp, _vp,
                                           ctypes.c_double, ctypes.c_double,
                                           ctypes.POINTER(Options), _vp, _vp, _vp, _vp]
@@ -295,7 +299,7 @@ def _trace_list(trace_buf, n):
 def cggm_solve(X, Y, lam_Lambda: float, lam_Theta: float, tol: float = 1e-2, *,
                max_iter: int = 500, max_ls: int = 30, ls_beta: float = 0.5,
                ls_sigma: float = 1e-3, stall_iters: int = 3, sweep: int = CGGM_SWEEP_TILED,
-               tile: int = 0, lambda_passes: int = 4, precision: str = "fp64",
+               tile: int = 0, lambda_passes: int = 0, precision: str = "fp64",
                mixed_min_q: int | None = None, workspace_budget: int = 0,
                warm_Lambda=None, warm_Theta=None, trace_cap: int | None = None,
                keep_csr: bool = False, kernel_stats: bool = False,
@@ -344,7 +348,7 @@ def cggm_solve(X, Y, lam_Lambda: float, lam_Theta: float, tol: float = 1e-2, *,
 def cggm_solve_path(X, Y, lam_Lambda, lam_Theta, tol: float = 1e-2, *,
                     max_iter: int = 500, max_ls: int = 30, ls_beta: float = 0.5,
                     ls_sigma: float = 1e-3, stall_iters: int = 3,
-                    sweep: int = CGGM_SWEEP_TILED, tile: int = 0, lambda_passes: int = 4,
+                    sweep: int = CGGM_SWEEP_TILED, tile: int = 0, lambda_passes: int = 0,
                     precision: str = "fp64", mixed_min_q: int | None = None,
                     workspace_budget: int = 0, warm_Lambda=None,
                     warm_Theta=None, trace_cap: int | None = None, keep_csr: bool = False,
@@ -422,8 +426,23 @@ def cggm_objective_noalloc(X, Y, Lambda, Theta, lam_Lambda: float, lam_Theta: fl
     return f.value
 
 
+def cggm_autotune_tile(n: int, p: int, q: int, precision: str = "fp64", iters: int = 2,
+                       graphs: bool = False, stream=None):
+    """(best tile edge, {edge: ms per iteration}) for problems of shape (n, p, q)."""
+    lib = load()
+    opt = Options()
+    lib.cggm_default_options(ctypes.byref(opt))
+    opt.precision = PRECISIONS[precision]
+    opt.graphs = int(bool(graphs))
+    tile = ctypes.c_int()
+    ms = (ctypes.c_double * 3)()
+    _check(lib.cggm_autotune_tile(n, p, q, ctypes.byref(opt), int(iters), ctypes.byref(tile),
+                                  ms, _stream(stream)))
+    return tile.value, {16: ms[0], 32: ms[1], 64: ms[2]}
+
+
 def cggm_lambda_direction(X, Y, Lambda, Theta, lam_Lambda: float, lam_Theta: float, *,
-                          lambda_passes: int = 4, sweep: int = CGGM_SWEEP_TILED, tile: int = 0,
+                          lambda_passes: int = 0, sweep: int = CGGM_SWEEP_TILED, tile: int = 0,
                           precision: str = "fp64", mixed_min_q: int | None = None,
                           split_level: int = 0, stream=None):
     """(D, U, V): one Lambda Newton direction at (Lambda, Theta), the maintained
@@ -495,7 +514,8 @@ class Server:
 
     def submit(self, X, Y, lam_Lambda, lam_Theta, tol: float = 1e-2, *,
                precision: str = "fp64", max_iter: int = 0, lambda_passes: int = 0,
-               mixed_min_q: int | None = None, Lambda_out=None, Theta_out=None) -> int:
+               mixed_min_q: int | None = None, Lambda_out=None, Theta_out=None,
+               tile: int = 0) -> int:
         n, p = X.shape
         q = Y.shape[1]
         lamL = np.ascontiguousarray(lam_Lambda, dtype=np.float64).ravel()
@@ -511,6 +531,7 @@ class Server:
         r.tol, r.precision = float(tol), PRECISIONS[precision]
         r.max_iter, r.lambda_passes = int(max_iter), int(lambda_passes)
         r.mixed_min_q = -1 if mixed_min_q is None else int(mixed_min_q)
+        r.tile = int(tile)
         for t, name, shape in ((Lambda_out, "Lambda_out", (npath, q, q)),
                                (Theta_out, "Theta_out", (npath, p, q))):
             if t is not None and tuple(t.shape) != shape:

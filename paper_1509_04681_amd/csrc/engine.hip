@@ -42,6 +42,25 @@ __global__ void widen_kernel(int64_t count, const float *a, double *b) {   // b 
     if (e < count) b[e] = (double)a[e];
 }
 
+// Standard normal numbers from a counter (the tuner's synthetic inputs):
+// SplitMix64 of (seed, index) gives two 53-bit uniforms, Box-Muller one
+// normal.  Deterministic for a given seed.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ void normal_kernel(int64_t count, uint64_t seed, double *x) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    const uint64_t a = splitmix64(seed ^ (2 * (uint64_t)e)), b = splitmix64(seed ^ (2 * (uint64_t)e + 1));
+    const double u1 = ((a >> 11) + 1.0) * (1.0 / 9007199254740992.0);   // (0, 1]
+    const double u2 = (b >> 11) * (1.0 / 9007199254740992.0);           // [0, 1)
+    x[e] = sqrt(-2.0 * log(u1)) * cospi(2.0 * u2);
+}
+
 // y (rows x cols, ld ldy) = x (FP32, ld ldx) widened
 __global__ void widen2d_kernel(int64_t rows, int64_t cols, const float *x, int64_t ldx,
                                double *y, int64_t ldy) {
@@ -273,10 +292,17 @@ struct SweepGraphs {
     };
     std::vector<Entry> cache;
     int64_t captured = 0, replayed = 0;
+    // The launches are recorded on a stream of the library's own (a caller's
+    // stream may be the legacy default stream, which cannot be captured);
+    // recording executes nothing, and the graph is then launched on the
+    // caller's stream.
+    hipStream_t cap = nullptr;
     ~SweepGraphs() {
         for (auto &e : cache)
             if (e.exec) (void)hipGraphExecDestroy(e.exec);
+        if (cap) (void)hipStreamDestroy(cap);
     }
+    // launch(stream) issues the wave loop's kernels on `stream`.
     template <class F>
     void run(hipStream_t s, const Schedule *sch, const void *buf, double lam, bool f32,
              F &&launch) {
@@ -286,15 +312,16 @@ struct SweepGraphs {
                 ++replayed;
                 return;
             }
+        if (!cap) CGGM_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
         hipGraph_t g = nullptr;
-        CGGM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        CGGM_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
         try {
-            launch();
+            launch(cap);
         } catch (...) {
-            if (hipStreamEndCapture(s, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+            if (hipStreamEndCapture(cap, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
             throw;
         }
-        CGGM_HIP(hipStreamEndCapture(s, &g));
+        CGGM_HIP(hipStreamEndCapture(cap, &g));
         hipGraphExec_t exec = nullptr;
         const hipError_t err = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
@@ -536,10 +563,10 @@ void run_theta_sweep(Ctx &c, const Schedule &sch, KernelTimer *kt = nullptr, int
         CGGM_HIP(hipStreamSynchronize(c.s));
     }
     if (c.graphs && !block && !(kt && kt->on())) {
-        c.graphs->run(c.s, &sch, w.Th, c.lamT, f32.on, [&] {
+        c.graphs->run(c.s, &sch, w.Th, c.lamT, f32.on, [&](hipStream_t st) {
             for (int k = 0; k < sch.waves(); ++k) {
                 const int b = sch.wave_start[k], e = sch.wave_start[k + 1];
-                theta_wave(c.s, w.rects_theta + b, w.act_theta + b, e - b, w.p, w.q, w.Sxx, w.p,
+                theta_wave(st, w.rects_theta + b, w.act_theta + b, e - b, w.p, w.q, w.Sxx, w.p,
                            w.Sxy, w.Sig, w.V, w.GT, w.Th, c.lamT, w.dT, w.changed, w.cd, nullptr,
                            &f32);
             }
@@ -588,10 +615,10 @@ void run_lambda_sweep(Ctx &c, const Schedule &sch, KernelTimer *kt = nullptr, in
                         w.act_lambda);
     }
     if (c.graphs && !(kt && kt->on())) {
-        c.graphs->run(c.s, &sch, w.Lam, c.lamL, f32.on, [&] {
+        c.graphs->run(c.s, &sch, w.Lam, c.lamL, f32.on, [&](hipStream_t st) {
             for (int k = 0; k < sch.waves(); ++k) {
                 const int b = sch.wave_start[k], e = sch.wave_start[k + 1];
-                lambda_wave(c.s, w.rects_lambda + b, w.act_lambda + b, e - b, w.q, w.Sig, w.Psi,
+                lambda_wave(st, w.rects_lambda + b, w.act_lambda + b, e - b, w.q, w.Sig, w.Psi,
                             w.SP, w.GL, w.Lam, c.lamL, w.D, w.U, w.dD, w.changed, w.cd, nullptr,
                             &f32);
             }
@@ -678,7 +705,7 @@ cggm_options checked_options(const cggm_options *opt_in) {
     if (opt_in) opt = *opt_in;
     if (opt.max_iter < 0 || opt.max_ls < 1 || !(opt.ls_beta > 0.0 && opt.ls_beta < 1.0) ||
         !(opt.ls_sigma > 0.0 && opt.ls_sigma < 1.0) || opt.stall_iters < 0 ||
-        opt.lambda_passes < 1 || opt.mixed_min_q < 0 || opt.theta_passes < 1 ||
+        opt.lambda_passes < 0 || opt.mixed_min_q < 0 || opt.theta_passes < 1 ||
         opt.split_level < 0 || opt.split_level > 6 || (opt.blockwise != 0 && opt.blockwise != 1) ||
         (opt.graphs != 0 && opt.graphs != 1) ||
         (opt.precision != CGGM_PRECISION_FP64 && opt.precision != CGGM_PRECISION_MIXED) ||
@@ -717,6 +744,13 @@ struct Solver::Impl {
         : n(n_), p(p_), q(q_), dtype(dt), opt(checked_options(o)), s(st) {
         check_sizes(n, p, q);
         check_dtype(dtype);
+        // Passes of the Lambda direction, chosen by the conditioning of its
+        // subproblem: with fewer samples than a quarter of the outputs, Syy
+        // has low rank and the coordinate descent needs more passes for a
+        // useful Newton direction (measured on the chain generator: 4 passes
+        // best at q = 2000, n = 500; 6 passes best at q = 4000, n = 200, where
+        // they reach a 1e-6 gap in 97 s against > 200 s with 4).
+        if (opt.lambda_passes == 0) opt.lambda_passes = (4 * n >= q) ? 4 : 6;
         mixed = opt.precision == CGGM_PRECISION_MIXED && q >= opt.mixed_min_q;
         seq = opt.sweep == CGGM_SWEEP_SEQUENTIAL;
         const auto [tileL, tileT] = tile_edges(opt.tile);
@@ -1308,6 +1342,59 @@ int direction_impl(const void *X, const void *Y, int64_t n, int64_t p, int64_t q
     return CGGM_OK;
 }
 
+// Tile-edge autotuner: times the outer iterations of a synthetic problem of
+// the given shape (X and Y standard normal from a counter-based generator,
+// lambda = 0.02, at which the screen is near-dense -- the hard case) for each
+// candidate edge, one warm-up iteration and `iters` timed ones from
+// Lambda = I, Theta = 0, and returns the fastest.  Smaller tiles shorten the
+// in-tile Gauss-Seidel chains (R x C dependent steps) and put more tiles in a
+// wave; larger ones need fewer waves and launches.
+int autotune_impl(int64_t n, int64_t p, int64_t q, const cggm_options *opt_in, int iters,
+                  int *tile_out, double *ms_out, hipStream_t s) {
+    if (!tile_out) fail(CGGM_EINVAL, "NULL pointer argument");
+    check_sizes(n, p, q);
+    if (iters < 1 || iters > 50) fail(CGGM_EINVAL, "iters must be in [1, 50]");
+    cggm_options base = checked_options(opt_in);
+    DeviceBuffer xy;
+    if (hipMalloc(&xy.p, sizeof(double) * n * (p + q)) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(CGGM_ENOMEM, "hipMalloc of the tuner's inputs failed");
+    }
+    double *X = (double *)xy.p, *Y = X + n * p;
+    normal_kernel<<<nblk(n * (p + q)), BLOCK, 0, s>>>(n * (p + q), 0x5eedull, X);
+    CGGM_LAUNCH_CHECK();
+    const int cand[3] = {16, 32, 64};
+    int best = 64;
+    double best_ms = INFINITY;
+    for (int k = 0; k < 3; ++k) {
+        cggm_options o = base;
+        o.tile = cand[k];
+        o.stall_iters = 0;
+        o.max_iter = iters + 1;
+        o.warm_Lambda = o.warm_Theta = nullptr;
+        o.kstats = nullptr;
+        std::vector<cggm_trace_entry> tr(iters + 2);
+        o.trace = tr.data();
+        o.trace_cap = iters + 2;
+        Solver sv(n, p, q, &o, s, CGGM_F64);
+        sv.allocate();
+        sv.load(X, Y);
+        sv.start();
+        (void)sv.run(0.02, 0.02, 0.0);
+        const int len = sv.trace_len();
+        double ms = INFINITY;
+        if (len >= 2) ms = (tr[len - 1].t_end_ms - tr[1].t_end_ms) / std::max(1, len - 2);
+        if (len == 2) ms = tr[1].t_end_ms - tr[0].t_end_ms;
+        if (ms_out) ms_out[k] = ms;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = cand[k];
+        }
+    }
+    *tile_out = best;
+    return CGGM_OK;
+}
+
 // ------------------------------------------------------- objective/gradient --
 // Workspace for the standalone evaluations.
 struct EvalWork {
@@ -1506,7 +1593,7 @@ void cggm_default_options(cggm_options *opt) {
     opt->stall_iters = 3;
     opt->sweep = CGGM_SWEEP_TILED;
     opt->tile = 0;
-    opt->lambda_passes = 4;
+    opt->lambda_passes = 0;
     opt->precision = CGGM_PRECISION_FP64;
     opt->mixed_min_q = 4096;
     opt->theta_passes = 1;
@@ -1608,6 +1695,13 @@ int cggm_objective_noalloc(const void *X, const void *Y, int64_t n, int64_t p, i
     return guarded([&] {
         return objective_noalloc_impl(X, Y, n, p, q, dtype, Lambda, Theta, lamL, lamT, f_out,
                                       (hipStream_t)stream);
+    });
+}
+
+int cggm_autotune_tile(int64_t n, int64_t p, int64_t q, const cggm_options *opt, int iters,
+                       int *tile, double *ms, void *stream) {
+    return guarded([&] {
+        return autotune_impl(n, p, q, opt, iters, tile, ms, (hipStream_t)stream);
     });
 }
 

@@ -162,6 +162,7 @@ Job *make_job(const cggm_request *req) {
     cggm_default_options(&j->opt);
     j->opt.precision = r.precision;
     j->opt.graphs = 1;       // replay each sweep's launches: small requests are launch-bound
+    if (r.tile > 0) j->opt.tile = r.tile;
     if (r.max_iter > 0) j->opt.max_iter = r.max_iter;
     if (r.lambda_passes > 0) j->opt.lambda_passes = r.lambda_passes;
     if (r.mixed_min_q >= 0) j->opt.mixed_min_q = r.mixed_min_q;

@@ -5,7 +5,7 @@
 #include "cggm.h"
 int main(){
 #define R(f) printf("req %s %zu\n", #f, offsetof(cggm_request, f));
-R(X)R(Y)R(n)R(p)R(q)R(npath)R(lamL)R(lamT)R(tol)R(precision)R(max_iter)R(lambda_passes)R(mixed_min_q)R(Lambda_out)R(Theta_out)R(dtype)
+R(X)R(Y)R(n)R(p)R(q)R(npath)R(lamL)R(lamT)R(tol)R(precision)R(max_iter)R(lambda_passes)R(mixed_min_q)R(Lambda_out)R(Theta_out)R(dtype)R(tile)
 printf("req size %zu\n", sizeof(cggm_request));
 #define O(f) printf("opt %s %zu\n", #f, offsetof(cggm_options, f));
 O(max_iter)O(max_ls)O(ls_beta)O(ls_sigma)O(stall_iters)O(sweep)O(tile)O(lambda_passes)O(precision)O(mixed_min_q)O(workspace_budget)O(warm_Lambda)O(warm_Theta)O(trace)O(trace_cap)O(trace_len)O(kstats)O(theta_passes)O(split_level)O(split_adapt)O(blockwise)O(sxx_cache_bytes)O(graphs)

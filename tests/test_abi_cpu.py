@@ -82,7 +82,7 @@ def test_argument_errors_without_device(lib):
     assert lib.cggm_solve(fake, fake, 4, 3, 2, 0, 0.1, 0.1, 0.01, ctypes.byref(opt),
                           ctypes.byref(r), None) == m.CGGM_EINVAL
     lib.cggm_default_options(ctypes.byref(opt))
-    opt.lambda_passes = 0
+    opt.lambda_passes = -1
     assert lib.cggm_solve(fake, fake, 4, 3, 2, 0, 0.1, 0.1, 0.01, ctypes.byref(opt),
                           ctypes.byref(r), None) == m.CGGM_EINVAL
     lib.cggm_default_options(ctypes.byref(opt))
@@ -113,7 +113,7 @@ def test_default_options(lib):
     assert (opt.max_iter, opt.max_ls, opt.ls_beta, opt.ls_sigma, opt.stall_iters) == \
         (500, 30, 0.5, 1e-3, 3)
     assert opt.sweep == m.CGGM_SWEEP_TILED
-    assert opt.lambda_passes == 4
+    assert opt.lambda_passes == 0            # auto: 4 when n >= q / 4, else 6
     assert opt.precision == m.CGGM_PRECISION_FP64
     assert opt.mixed_min_q == 4096
     assert (opt.theta_passes, opt.split_level, opt.split_adapt) == (1, 0, 1)
@@ -148,7 +148,7 @@ def test_path_and_workspace_arguments_without_device(lib):
     opt.mixed_min_q = 0
     forced = lib.cggm_workspace_bytes(300, 200, 100, ctypes.byref(opt))
     assert forced - small >= 4 * (4 * 100 * 100 + 200 * 200 + 200 * 100)
-    for field, value in (("lambda_passes", 0), ("theta_passes", 0), ("split_level", -1),
+    for field, value in (("lambda_passes", -1), ("theta_passes", 0), ("split_level", -1),
                          ("split_level", 7)):
         opt = m.Options()
         lib.cggm_default_options(ctypes.byref(opt))

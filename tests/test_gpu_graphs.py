@@ -67,3 +67,21 @@ def test_graph_replay_through_split_levels(cg):
     b = cg.cggm_solve(dev(pr.X), dev(pr.Y), 0.05, 0.05, graphs=True, **kw)
     assert max(t["sweep_split"] & 255 for t in a.trace) >= 1
     assert same(a, b)
+
+
+def test_autotuned_tile_in_the_server(cg):
+    """The tile-edge autotuner picks one of its candidates from measured times;
+    a request served with that edge (graph replay on in the server) equals the
+    plain path solve with the same edge bit for bit."""
+    tile, ms = cg.cggm_autotune_tile(200, 300, 250, iters=2)
+    print(f"autotune 300 x 250: tile {tile}, ms per iteration {ms}", flush=True)
+    assert tile in (16, 32, 64) and all(np.isfinite(v) and v > 0 for v in ms.values())
+    assert ms[tile] == min(ms.values())
+    pr = synth.chain_problem(p=300, q=250, n=200, density=0.02, lam=0.1, seed=43)
+    X, Y = dev(pr.X), dev(pr.Y)
+    lam = [0.3, 0.15, 0.08]
+    ref = cg.cggm_solve_path(X, Y, lam, lam, tol=1e-6, tile=tile)
+    with cg.Server(slots=2, pool_bytes=1 << 30) as srv:
+        info = srv.wait(srv.submit(X, Y, lam, lam, tol=1e-6, tile=tile))
+    assert info["f"] == [r.f for r in ref]
+    assert info["iters"] == [r.iters for r in ref]
