@@ -263,6 +263,10 @@ WORKLOADS = {
     "chain2k": dict(p=2000, q=2000, n=500, density=0.01, lam=0.05),
     # p = q = 20000, n = 1000, 0.05% dense Theta, lambda = 0.02
     "chain20k": dict(p=20000, q=20000, n=1000, density=0.0005, lam=0.02),
+    # the same generator at reduced sizes with the same sample ratio n / q =
+    # 0.05 (convergence study of the 20000 x 20000 configuration)
+    "chain4k": dict(p=4000, q=4000, n=200, density=0.0005, lam=0.02),
+    "chain8k": dict(p=8000, q=8000, n=400, density=0.0005, lam=0.02),
     # parity case large enough (K >= 512) that tile gradient snapshots are
     # split over several workgroups
     "chain530": dict(p=530, q=515, n=100, density=0.005, lam=0.5, seed=21),

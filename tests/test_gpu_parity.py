@@ -245,6 +245,29 @@ def test_golden_chain40(cg):
     assert ((sT == gold["support_Theta"]) | gold["borderline_Theta"]).all()
 
 
+def test_golden_chain2k(cg):
+    """The 2000 x 2000 chain workload (n = 500, lambda = 0.05) solved with the
+    default options against the oracle's optimum stored in
+    tests/golden/chain2k.json (f within 1e-8, supports above 1e-6 equal
+    outside the borderline band)."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "chain2k.json")
+    if not os.path.exists(path):
+        pytest.skip("tests/golden/chain2k.json has not been written")
+    gold = load_golden("chain2k")
+    pr = synth.workload("chain2k")
+    g = cg.cggm_solve(dev(pr.X), dev(pr.Y), pr.lam_Lambda, pr.lam_Theta, tol=0.0,
+                      max_iter=3000, trace_cap=0)
+    sL = np.abs(g.Lambda.cpu().numpy()) > SUPPORT_EPS
+    sT = np.abs(g.Theta.cpu().numpy()) > SUPPORT_EPS
+    mL = int((~((sL == gold["support_Lambda"]) | gold["borderline_Lambda"])).sum())
+    mT = int((~((sT == gold["support_Theta"]) | gold["borderline_Theta"])).sum())
+    print(f"chain2k: f_gpu={g.f!r} f_oracle={gold['f_star']!r} "
+          f"rel={abs(g.f - gold['f_star']) / abs(gold['f_star']):.2e} iters={g.iters} "
+          f"support mismatches L={mL} T={mT}", flush=True)
+    assert abs(g.f - gold["f_star"]) <= F_RTOL * abs(gold["f_star"])
+    assert mL == 0 and mT == 0
+
+
 def test_monotone_and_pd_trace(cg):
     pr = synth.chain_problem(p=60, q=70, n=80, density=0.05, lam=0.08, seed=5)
     g = cg.cggm_solve(dev(pr.X), dev(pr.Y), pr.lam_Lambda, pr.lam_Theta, tol=0.0, max_iter=400)
