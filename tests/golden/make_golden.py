@@ -59,6 +59,9 @@ def main():
     ap.add_argument("--max-iter", type=int, default=20000)
     ap.add_argument("--state-dir", default=None)
     ap.add_argument("--lambda-passes", type=int, default=1)
+    ap.add_argument("--tol", type=float, default=0.0,
+                    help="stop also when the subgradient is below tol (||Lambda||_1 + "
+                         "||Theta||_1) (0: only at the rounding floor of f)")
     args = ap.parse_args()
     pr = synth.workload(args.workload, seed=args.seed)
     state = args.state_dir
@@ -72,7 +75,7 @@ def main():
         done, fs = meta["done"], meta["f"]
     t0 = time.time()
     while True:
-        r = oracle.solve(pr.X, pr.Y, pr.lam_Lambda, pr.lam_Theta, tol=0.0,
+        r = oracle.solve(pr.X, pr.Y, pr.lam_Lambda, pr.lam_Theta, tol=args.tol,
                          max_iter=args.chunk, stall_iters=3, Lambda0=Lam, Theta0=Th,
                          lambda_passes=args.lambda_passes)
         Lam, Th = r.Lambda, r.Theta
@@ -86,7 +89,7 @@ def main():
             np.save(os.path.join(state, "Lambda.npy"), Lam)
             np.save(os.path.join(state, "Theta.npy"), Th)
             json.dump({"done": done, "f": fs}, open(os.path.join(state, "meta.json"), "w"))
-        if r.status == oracle.ORC_STALLED or done >= args.max_iter:
+        if r.status in (oracle.ORC_STALLED, oracle.ORC_OK) or done >= args.max_iter:
             break
     out = {
         "workload": args.workload, "seed": args.seed, "n": pr.n, "p": pr.p, "q": pr.q,
@@ -103,8 +106,9 @@ def main():
         "borderline_Lambda": pack_mask((np.abs(Lam) >= 1e-7) & (np.abs(Lam) <= 1e-5)),
         "borderline_Theta": pack_mask((np.abs(Th) >= 1e-7) & (np.abs(Th) <= 1e-5)),
         "f_trace_head": fs[:50],
-        "generator": "synth.workload(%r, seed=%r) -> oracle.solve(tol=0, stall_iters=3, "
-                     "lambda_passes=%d)" % (args.workload, args.seed, args.lambda_passes),
+        "generator": "synth.workload(%r, seed=%r) -> oracle.solve(tol=%g, stall_iters=3, "
+                     "lambda_passes=%d)" % (args.workload, args.seed, args.tol,
+                                            args.lambda_passes),
     }
     with open(os.path.join(HERE, f"{args.workload}.json"), "w") as fh:
         json.dump(out, fh, indent=1)
