@@ -343,7 +343,9 @@ int cggm_autotune_tile(int64_t n, int64_t p, int64_t q, const cggm_options *opt,
  * opt->split_level, without the descent guards).  Outputs (caller device
  * buffers, NULL skips): D (q x q, both triangles), U = D Sigma as maintained
  * by the passes (q x q; FP32 arithmetic in the mixed mode, widened), and
- * V = Theta Sigma as the Theta step forms it (p x q; split-BF16 products in
+ * V = Theta Sigma as the Theta step forms it (p x q: a sparse-by-dense FP64
+ * product when fewer than 2% of Theta's entries are nonzero, else a dense
+ * FP64 product, or split-BF16 products in the mixed mode; stored in FP32 in
  * the mixed mode).  For checking the steps of the solver against a
  * reference; allocates and frees a solve workspace.  Errors as cggm_solve,
  * CGGM_ENOTPD when Lambda is not positive definite.

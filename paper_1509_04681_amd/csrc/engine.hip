@@ -61,6 +61,79 @@ __global__ void normal_kernel(int64_t count, uint64_t seed, double *x) {
     x[e] = sqrt(-2.0 * log(u1)) * cospi(2.0 * u2);
 }
 
+// V = Theta Sigma with Theta sparse (Sec. 3.2: V is kept from the rows of
+// Sigma that Theta's nonzeros select).  One workgroup per (row i of Theta,
+// block of VS_COLS columns): it scans Theta[i, :], stages the row's nonzeros
+// (k, Theta_ik) in LDS in order, and accumulates Theta_ik Sigma[k, cols] in
+// FP64 registers, k ascending (deterministic); the row is written once, in
+// FP64 (V) or rounded to FP32 (V32, row length ld).  Rows of Sigma are read
+// with consecutive lanes on consecutive columns.
+constexpr int VS_PER_THREAD = 8;
+constexpr int VS_COLS = BLOCK * VS_PER_THREAD;
+constexpr int VS_CAP = 1024;
+
+__global__ __launch_bounds__(BLOCK) void theta_sigma_sparse_kernel(
+    int64_t q, int64_t ncb, const double *__restrict__ Theta, const double *__restrict__ Sigma,
+    double *__restrict__ V, float *__restrict__ V32, int64_t ld) {
+    const int64_t i = (int64_t)blockIdx.x / ncb;               // ncb column blocks per row
+    const int64_t c0 = ((int64_t)blockIdx.x % ncb) * VS_COLS;
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
+    __shared__ int kidx[VS_CAP];
+    __shared__ double kval[VS_CAP];
+    __shared__ int wsum[BLOCK / WAVE];
+    double acc[VS_PER_THREAD];
+#pragma unroll
+    for (int u = 0; u < VS_PER_THREAD; ++u) acc[u] = 0.0;
+    const double *row = Theta + i * q;
+    int count = 0;                                  // staged nonzeros (uniform)
+    auto flush = [&] {
+        for (int j = 0; j < count; ++j) {
+            const double tv = kval[j];
+            const double *srow = Sigma + (int64_t)kidx[j] * q + c0 + tid;
+#pragma unroll
+            for (int u = 0; u < VS_PER_THREAD; ++u)
+                if (c0 + tid + u * BLOCK < q) acc[u] = fma(tv, srow[u * BLOCK], acc[u]);
+        }
+        count = 0;
+    };
+    for (int64_t k0 = 0; k0 < q; k0 += BLOCK) {
+        const int64_t k = k0 + tid;
+        const double v = k < q ? row[k] : 0.0;
+        const bool nz = v != 0.0;
+        const uint64_t m = __ballot(nz);
+        if (lane == 0) wsum[wid] = __popcll(m);
+        __syncthreads();
+        int before = 0, total = 0;
+#pragma unroll
+        for (int w2 = 0; w2 < BLOCK / WAVE; ++w2) {
+            before += (w2 < wid) ? wsum[w2] : 0;
+            total += wsum[w2];
+        }
+        if (count + total > VS_CAP) {                 // room for this block first
+            flush();
+            __syncthreads();                          // staged entries consumed
+        }
+        if (nz) {
+            const int pos = count + before + __popcll(m & ((1ull << lane) - 1ull));
+            kidx[pos] = (int)k;
+            kval[pos] = v;
+        }
+        count += total;
+        __syncthreads();                              // staged entries and wsum visible
+    }
+    flush();
+#pragma unroll
+    for (int u = 0; u < VS_PER_THREAD; ++u) {
+        const int64_t col = c0 + tid + u * BLOCK;
+        if (col < q) {
+            if (V32)
+                V32[i * ld + col] = (float)acc[u];
+            else
+                V[i * ld + col] = acc[u];
+        }
+    }
+}
+
 // y (rows x cols, ld ldy) = x (FP32, ld ldx) widened
 __global__ void widen2d_kernel(int64_t rows, int64_t cols, const float *x, int64_t ldx,
                                double *y, int64_t ldy) {
@@ -342,14 +415,29 @@ struct Ctx {
     double lamL, lamT;
     bool mixed = false;   // split-BF16 V and FP32 sweep operands
     SweepGraphs *graphs = nullptr;   // capture and replay the sweeps' wave loops
+    double theta_density = -1.0;     // nnz(Theta) / (p q) of the iterate (< 0: unknown)
     bool f32() const { return mixed && w.Sig32 != nullptr; }
 };
 
 // V = Theta Sigma: FP64 MFMA, or in mixed mode from the BF16 pieces of Theta
 // and Sigma (Sigma symmetric: its rows are the columns the product needs) into
 // the FP32 V the mixed Theta sweep maintains.
+// Fraction of nonzeros in Theta below which V = Theta Sigma is formed as a
+// sparse-by-dense product (about 16 nnz q bytes of Sigma rows and Theta scans
+// against 2 p q^2 flops of the dense product).
+constexpr double SPARSE_V_DENSITY = 0.02;
+
 void theta_sigma(Ctx &c) {
     Work &w = c.w;
+    if (c.theta_density >= 0.0 && c.theta_density < SPARSE_V_DENSITY) {
+        const int64_t ncb = (w.q + VS_COLS - 1) / VS_COLS;
+        const bool to32 = c.f32();
+        theta_sigma_sparse_kernel<<<(unsigned)(w.p * ncb), BLOCK, 0, c.s>>>(
+            w.q, ncb, w.Th, w.Sig, to32 ? nullptr : w.V, to32 ? w.V32 : nullptr,
+            to32 ? f32_ld(w.q) : w.q);
+        CGGM_LAUNCH_CHECK();
+        return;
+    }
     if (!c.mixed) {
         gemm(c.s, false, false, w.p, w.q, w.q, 1.0, w.Th, w.q, w.Sig, w.q, 0.0, w.V, w.q);
         return;
@@ -896,6 +984,11 @@ void Solver::Impl::direction(double lamL, double lamT, double *D_out, double *U_
     Ctx c{s, w, lamL, lamT, mixed};
     reduce_dot(s, w.n * q, w.A, w.R, w.partials, w.scal + S_AR);
     gradients(c, X);
+    reduce_top_stats(s, p, q, w.Sxy, w.GT, w.Th, lamT, 0, w.partials, w.scal + S_THETA);
+    double h[5];
+    CGGM_HIP(hipMemcpyAsync(h, w.scal + S_THETA, sizeof(h), hipMemcpyDeviceToHost, s));
+    CGGM_HIP(hipStreamSynchronize(s));
+    c.theta_density = h[4] / ((double)p * (double)q);   // V as the Theta step forms it
     const Schedule &sch = split_sched(la_split, la_sched, seq ? 0 : opt.split_level);
     for (int pass = 0; pass < opt.lambda_passes; ++pass) run_lambda_sweep(c, sch, nullptr, pass);
     theta_sigma(c);
@@ -973,6 +1066,7 @@ SolveOutcome Solver::Impl::run(double lamL, double lamT, double tol) {
         evaluate();
         CGGM_HIP(hipEventRecord(ev[1], s));
         top = read_top(c, true);
+        c.theta_density = (double)top.nnzT / ((double)p * (double)q);
         kt_theta.collect();                       // the last Theta sweep is done
         // Descent guard: the Theta sweep must not raise f.  A sweep steered by
         // the mixed-precision operands is redone in FP64 at the same level (and

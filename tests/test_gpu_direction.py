@@ -92,3 +92,23 @@ def test_mixed_mode_errors_per_result(cg, orc, p, q, n):
     assert e_v < 1e-5
     assert e_u < 1e-5
     assert e_d < 1e-3
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_sparse_theta_product(cg, precision):
+    """With fewer than 2% of Theta's entries nonzero, V = Theta Sigma is formed
+    from the rows of Sigma that the nonzeros select (FP64 accumulation,
+    stored in FP32 in the mixed mode): element by element equal to the dense
+    product to FP64 rounding, or to FP32 rounding of it."""
+    pr = synth.chain_problem(p=700, q=530, n=300, density=0.004, lam=0.25, seed=11)
+    rng = np.random.default_rng(12)
+    Lam = synth.random_spd(530, rng, degree=3.0) + 0.2 * np.eye(530)
+    Th = synth.dense_theta(700, 530, 0.01, rng)               # 1% of the entries nonzero
+    dens = np.count_nonzero(Th) / Th.size
+    _, _, V = cg.cggm_lambda_direction(dev(pr.X), dev(pr.Y), dev(Lam), dev(Th), pr.lam_Lambda,
+                                       pr.lam_Theta, precision=precision, mixed_min_q=0)
+    ref = Th @ np.linalg.inv(Lam)
+    err = rel(V.cpu().numpy(), ref)
+    print(f"{precision}: Theta density {dens:.4f}, V rel err {err:.2e}", flush=True)
+    assert 0 < dens < 0.02
+    assert err < (1e-13 if precision == "fp64" else 1e-7)
