@@ -634,6 +634,18 @@ void form_slab(Ctx &c, SxxSlab &sl, int64_t g) {
     ++sl.formed;
 }
 
+// The 64 x 64 rects of the wave [b, e) of `sch`.  The snapshot reads operands
+// through buffer resources when there is one: the schedule then has 64-edge
+// tiles, and every smaller one ends at the matrix edge.
+int full_rects(const Schedule &sch, int b, int e) {
+    int n = 0;
+    for (int r = b; r < e; ++r) {
+        const TileRect &t = sch.rects[r];
+        n += (t.r1 - t.r0 == THETA_TILE && t.c1 - t.c0 == THETA_TILE) ? 1 : 0;
+    }
+    return n;
+}
+
 // One CD pass over S_Theta; the activity of the tiles is taken on the first
 // pass (pass == 0) from the top-of-iteration gradient, further passes reuse it.
 void run_theta_sweep(Ctx &c, const Schedule &sch, KernelTimer *kt = nullptr, int pass = 0,
@@ -654,6 +666,7 @@ void run_theta_sweep(Ctx &c, const Schedule &sch, KernelTimer *kt = nullptr, int
         c.graphs->run(c.s, &sch, w.Th, c.lamT, f32.on, [&](hipStream_t st) {
             for (int k = 0; k < sch.waves(); ++k) {
                 const int b = sch.wave_start[k], e = sch.wave_start[k + 1];
+                f32.full_rects = full_rects(sch, b, e);
                 theta_wave(st, w.rects_theta + b, w.act_theta + b, e - b, w.p, w.q, w.Sxx, w.p,
                            w.Sxy, w.Sig, w.V, w.GT, w.Th, c.lamT, w.dT, w.changed, w.cd, nullptr,
                            &f32);
@@ -682,6 +695,7 @@ void run_theta_sweep(Ctx &c, const Schedule &sch, KernelTimer *kt = nullptr, int
         }
         WaveProbe pr;
         if (kt && kt->on()) pr = kt->probe();
+        f32.full_rects = full_rects(sch, b, e);
         theta_wave(c.s, w.rects_theta + b, w.act_theta + b, e - b, w.p, w.q, Sxx, ldx, w.Sxy,
                    w.Sig, w.V, w.GT, w.Th, c.lamT, w.dT, w.changed, w.cd,
                    (kt && kt->on()) ? &pr : nullptr, &f32);
@@ -692,7 +706,7 @@ void run_theta_sweep(Ctx &c, const Schedule &sch, KernelTimer *kt = nullptr, int
 // on the first pass and carry over to further passes (pass > 0).
 void run_lambda_sweep(Ctx &c, const Schedule &sch, KernelTimer *kt = nullptr, int pass = 0) {
     Work &w = c.w;
-    const SweepF32 f32 = sweep_operands(c);
+    SweepF32 f32 = sweep_operands(c);
     if (pass == 0) {
         fill(c.s, w.q * w.q, 0.0, w.D);
         if (f32.on)
@@ -706,6 +720,7 @@ void run_lambda_sweep(Ctx &c, const Schedule &sch, KernelTimer *kt = nullptr, in
         c.graphs->run(c.s, &sch, w.Lam, c.lamL, f32.on, [&](hipStream_t st) {
             for (int k = 0; k < sch.waves(); ++k) {
                 const int b = sch.wave_start[k], e = sch.wave_start[k + 1];
+                f32.full_rects = full_rects(sch, b, e);
                 lambda_wave(st, w.rects_lambda + b, w.act_lambda + b, e - b, w.q, w.Sig, w.Psi,
                             w.SP, w.GL, w.Lam, c.lamL, w.D, w.U, w.dD, w.changed, w.cd, nullptr,
                             &f32);
@@ -717,6 +732,7 @@ void run_lambda_sweep(Ctx &c, const Schedule &sch, KernelTimer *kt = nullptr, in
         const int b = sch.wave_start[k], e = sch.wave_start[k + 1];
         WaveProbe pr;
         if (kt && kt->on()) pr = kt->probe();
+        f32.full_rects = full_rects(sch, b, e);
         lambda_wave(c.s, w.rects_lambda + b, w.act_lambda + b, e - b, w.q, w.Sig, w.Psi, w.SP,
                     w.GL, w.Lam, c.lamL, w.D, w.U, w.dD, w.changed, w.cd,
                     (kt && kt->on()) ? &pr : nullptr, &f32);

@@ -184,6 +184,8 @@ struct SweepF32 {
                                 // the slab width in the block-wise mode; padding zero)
     const float *SP = nullptr, *Psi = nullptr, *Sigma = nullptr, *Sxx = nullptr;  // q or p rows
     float *U = nullptr, *V = nullptr;
+    int full_rects = -1;        // 64 x 64 rects of the current wave (-1: not known),
+                                // set in either precision
 };
 inline int64_t f32_ld(int64_t cols) { return (cols + 3) / 4 * 4; }
 
@@ -214,10 +216,10 @@ void theta_wave(hipStream_t s, const TileRect *rects_dev, const int *active, int
 // byte size of the streamed operands (for the traffic counters).
 int lambda_snapshot(hipStream_t s, const TileRect *rects_dev, const int *active, int nrect,
                     int64_t q, const double *SP, const double *U, const double *Psi,
-                    const CdScratch &scr);
+                    const CdScratch &scr, int full = -1);
 int lambda_snapshot(hipStream_t s, const TileRect *rects_dev, const int *active, int nrect,
                     int64_t q, const float *SP, const float *U, const float *Psi, int64_t ld,
-                    const CdScratch &scr);
+                    const CdScratch &scr, int full = -1);
 void lambda_gauss_seidel(hipStream_t s, const TileRect *rects_dev, const int *active, int nrect,
                          int S, int64_t q, const double *Sigma, const double *Psi,
                          const double *GL, const double *Lam, double lamL, double *D,
