@@ -724,7 +724,34 @@ struct Swz64 {
         return p[r * 64 + (c ^ r)];
     }
 };
+// The same block unswizzled, for one that is only written and read by rows
+// (lane = column): the slot of (r, c) is then an immediate offset plus the
+// lane's.
+struct Row64 {
+    double *p;
+    __device__ __forceinline__ double &operator()(int r, int c) const { return p[r * 64 + c]; }
+};
 
+// Exact Gauss-Seidel over the active coordinates of one tile, row by row,
+// lane = column, by the four wavefronts of the workgroup with one workgroup
+// barrier per row r:
+//   wave 0 runs the coordinate chain of row r: the row's coordinates in lane
+//     order with v_readlane broadcasts, the in-row couplings x read from LDS,
+//     the dependent chain of one step three fused multiply-adds and a clamp
+//     (soft threshold as t - max(min(t, hi), lo)); it writes D, the tile's
+//     delta, and the row's moves and w1, w4 sums for the other waves, and
+//     after the barrier folds row r's moves into row r + 1 of the snapshot;
+//   wave 1 forms the couplings x_l(c) of row r + 1 (from the Sigma / Psi rows
+//     of the tile, the (J, J) columns held in registers) into the other of
+//     two LDS buffers;
+//   waves 2 and 3 fold the moves of row r - 1 into rows r + 1 .. R - 1 of the
+//     snapshot (even and odd rows), holding the rows of S_IJ and SP_IJ in
+//     registers.
+// So the chain of row r + 1 starts right after the barrier that ends row r,
+// with its couplings formed and every earlier row's moves folded in, in row
+// order.  The arithmetic of every value is that of one wavefront doing all of
+// it, except the sums w2, w3 of row r + 1 (a butterfly sum instead of four
+// strided partial sums).
 __global__ __launch_bounds__(BLOCK) void lambda_gs_kernel(
     const TileRect *__restrict__ rects, const int *__restrict__ active, int S,
     const double *__restrict__ partial, int64_t q, const double *__restrict__ Sigma,
@@ -732,9 +759,10 @@ __global__ __launch_bounds__(BLOCK) void lambda_gs_kernel(
     const double *__restrict__ Lam, double lamL, double *__restrict__ D,
     double *__restrict__ dD, int *__restrict__ changed, unsigned long long *__restrict__ ctr,
     int esz) {
-    static_assert(T == 64, "the Lambda tile is one wavefront wide");
+    static_assert(T == 64 && BLOCK == 4 * WAVE, "one 64-wide tile, four wavefronts");
     const int e = blockIdx.x;
-    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1);
+    const int wid = __builtin_amdgcn_readfirstlane(tid / WAVE);
     if (!active[e]) {
         if (tid == 0) changed[e] = 0;
         return;
@@ -742,21 +770,26 @@ __global__ __launch_bounds__(BLOCK) void lambda_gs_kernel(
     const TileRect rc = rects[e];
     const int R = rc.r1 - rc.r0, C = rc.c1 - rc.c0;
     const bool diag = rc.r0 == rc.c0;
-    // b snapshot, and the Sigma / Psi blocks (I, J) and (J, J); the rows of
-    // the (I, I) blocks are read per row from global memory (Sigma and Psi are
-    // symmetric, so row r of a block also serves as its column r).
-    __shared__ double lds[5 * T * T];
-    const Swz64 Bs{lds}, sIJ{lds + T * T}, pIJ{lds + 2 * T * T}, sJJ{lds + 3 * T * T},
-        pJJ{lds + 4 * T * T};
+    // LDS: the b snapshot (row r, once its chain has read it, carries row r's
+    // moves), two coupling buffers X (l, c), the w1 / w4 sums of the last two
+    // rows and their "row moved" flags.
+    __shared__ double lds[3 * T * T + 4 * T + 2];
+    // (S_IJ and SP_IJ are staged in the coupling buffers' memory, swizzled,
+    // before the first couplings are formed)
+    const Swz64 Bs{lds}, St{lds + T * T}, SPt{lds + 2 * T * T};
+    const Row64 X0{lds + T * T}, X1{lds + 2 * T * T};
+    double *const W1 = lds + 3 * T * T, *const W4 = W1 + 2 * T;
+    int *const MOV = reinterpret_cast<int *>(W4 + 2 * T);
     const double *snap = partial + (int64_t)e * S * T * T;    // summed into part 0
+    // S_IJ and SP_IJ staged in the coupling buffers for waves 2 and 3
     for (int k = tid; k < T * T; k += BLOCK) {
         const int r = k / T, c = k % T;
-        const bool ij = r < R && c < C, jj = r < C && c < C;
-        Bs(r, c) = ij ? snap[k] + GL[(int64_t)(rc.r0 + r) * q + rc.c0 + c] : 0.0;
-        sIJ(r, c) = ij ? Sigma[(int64_t)(rc.r0 + r) * q + rc.c0 + c] : 0.0;
-        pIJ(r, c) = ij ? Psi[(int64_t)(rc.r0 + r) * q + rc.c0 + c] : 0.0;
-        sJJ(r, c) = jj ? Sigma[(int64_t)(rc.c0 + r) * q + rc.c0 + c] : 0.0;
-        pJJ(r, c) = jj ? Psi[(int64_t)(rc.c0 + r) * q + rc.c0 + c] : 0.0;
+        const bool ij = r < R && c < C;
+        const int64_t o = (int64_t)(rc.r0 + r) * q + rc.c0 + c;
+        Bs(r, c) = ij ? snap[k] + GL[o] : 0.0;
+        const double s = ij ? Sigma[o] : 0.0, pv = ij ? Psi[o] : 0.0;
+        St(r, c) = s;
+        SPt(r, c) = s + pv;
     }
     if (ctr && tid == 0) {
         const int64_t RC = (int64_t)R * C;
@@ -770,182 +803,208 @@ __global__ __launch_bounds__(BLOCK) void lambda_gs_kernel(
         atomicAdd(ctr + 4, (unsigned long long)(16 * RC * C));
     }
     __syncthreads();
-    if (wid != 0) return;
-
-    const int c = lane;
-    const bool inC = c < C;
-    const double s_jj = sJJ(c, c), p_jj = pJJ(c, c);   // zero outside the tile
-    // lane c keeps column c of the (J, J) blocks in registers for the whole
-    // tile (one wavefront per SIMD here, so the register file allows it)
-    double sJc[T], pJc[T];
+    // Waves 0, 1: column `lane` of S_JJ and P_JJ; waves 2, 3: row `lane` of
+    // S_IJ and SP_IJ (zero outside the tile).
+    double regA[T], regB[T];
+    if (wid >= 2) {
 #pragma unroll
-    for (int l = 0; l < T; ++l) {
-        sJc[l] = sJJ(l, c);
-        pJc[l] = pJJ(l, c);
+        for (int l = 0; l < T; ++l) {
+            regA[l] = St(lane, l);
+            regB[l] = SPt(lane, l);
+        }
+    } else {
+        const bool inC = lane < C;
+#pragma unroll
+        for (int l = 0; l < T; ++l) {
+            const int64_t o = (int64_t)(rc.c0 + l) * q + rc.c0 + lane;
+            regA[l] = (inC && l < C) ? Sigma[o] : 0.0;
+            regB[l] = (inC && l < C) ? Psi[o] : 0.0;
+        }
     }
+    __syncthreads();                                  // the staging buffers are free
+    // x_l(c) = SP_ii S_lc + S_ii P_lc + S_il SP_ic + P_il S_ic of row rn
+    auto couplings = [&](int rn, const Row64 &X) {
+        const int64_t ro = (int64_t)(rc.r0 + rn) * q;
+        const double sii = Sigma[ro + rc.r0 + rn], pii = Psi[ro + rc.r0 + rn];
+        const bool inC = lane < C;
+        const double s_c = inC ? Sigma[ro + rc.c0 + lane] : 0.0;
+        const double p_c = inC ? Psi[ro + rc.c0 + lane] : 0.0;
+        const double spii = sii + pii, sp_c = s_c + p_c;
+#pragma unroll
+        for (int l = 0; l < T; ++l) {
+            const double s_il = readlane_f64(s_c, l), p_il = readlane_f64(p_c, l);
+            X(l, lane) = fma(spii, regA[l], fma(sii, regB[l], fma(s_il, sp_c, p_il * s_c)));
+        }
+    };
+    if (wid == 1) couplings(0, X0);
+    __syncthreads();
+
+    // ---- per-row state of wave 0 (coordinate chain) ----
+    const int c = lane;
+    const bool inC = c < C, inR = lane < R;
+    const double s_jj = (wid == 0 && inC) ? Sigma[(int64_t)(rc.c0 + c) * q + rc.c0 + c] : 0.0;
+    const double p_jj = (wid == 0 && inC) ? Psi[(int64_t)(rc.c0 + c) * q + rc.c0 + c] : 0.0;
     int any_change = 0;
     double *dDe = dD + (int64_t)e * T * T;
-    // Per-row global operands, fetched one row ahead: lane r2 holds
-    // Sigma_II[r][r2] and Psi_II[r][r2]; lane c holds Lambda, D and G at (r, c).
+    // Row operands fetched one row ahead: lane r2 holds Sigma_II[r][r2] and
+    // Psi_II[r][r2]; lane c holds S_IJ, P_IJ, Lambda, D and G at (r, c).
     // (The prefetch of D's next row precedes this row's writes: the only
     // writes into later rows of the tile are the mirror entries of a diagonal
     // tile, below the diagonal, which the coordinate loop never reads.)
-    const bool inR = lane < R;
-    double srow_n = 0.0, prow_n = 0.0, lam_n = 0.0, d_n = 0.0, g_n = 0.0;
+    double srow_n = 0.0, prow_n = 0.0, sij_n = 0.0, pij_n = 0.0;
+    double lam_n = 0.0, d_n = 0.0, g_n = 0.0;
     auto fetch_row = [&](int r) {
         const int64_t ro = (int64_t)(rc.r0 + r) * q;
-        if (inR) {
-            srow_n = Sigma[ro + rc.r0 + lane];
-            prow_n = Psi[ro + rc.r0 + lane];
-        }
-        if (inC) {
+        srow_n = inR ? Sigma[ro + rc.r0 + lane] : 0.0;
+        prow_n = inR ? Psi[ro + rc.r0 + lane] : 0.0;
+        sij_n = inC ? Sigma[ro + rc.c0 + c] : 0.0;
+        pij_n = inC ? Psi[ro + rc.c0 + c] : 0.0;
+        if (wid == 0 && inC) {
             lam_n = Lam[ro + rc.c0 + c];
             d_n = D[ro + rc.c0 + c];
             g_n = GL[ro + rc.c0 + c];
         }
     };
-    fetch_row(0);
+    if (wid == 0 || wid >= 2) fetch_row(0);
+
     for (int r = 0; r < R; ++r) {
-        const double srow = srow_n, prow = prow_n, lamv = lam_n, d0 = d_n, g = g_n;
-        if (r + 1 < R) fetch_row(r + 1);
-        const int64_t i = rc.r0 + r;
-        const bool colok = inC && (!diag || c >= r);
-        const double s_ij = sIJ(r, c), p_ij = pIJ(r, c);
-        double b = Bs(r, c);
-        const double sii = readlane_f64(srow, r), pii = readlane_f64(prow, r);
-        const double spii = sii + pii;
-        const bool self = diag && c == r;
-        const double a = self ? sii * sii + 2.0 * sii * pii
-                              : s_ij * s_ij + sii * s_jj + sii * p_jj + s_jj * pii +
-                                    2.0 * s_ij * p_ij;
-        const bool act = colok && a > 0.0 && (fabs(g) > lamL || lamv != 0.0);
-        const uint64_t mask = __ballot(act);
-        const double ainv = act ? 1.0 / a : 0.0;
-        const double thr = lamL * ainv;
-        // c = Lambda_ij + D_ij with D_ij as left by earlier passes (zero on the
-        // first), unchanged until the coordinate is visited
-        const double cv = lamv + d0;
-        double w1 = 0.0, w4 = 0.0, mu_mine = 0.0, s_mine;
-        // Coordinate l of the row (lane order): its new value is
-        // s = S_thr(cv - b / a), broadcast from lane l; every lane then moves
-        // b by mu_e x_l with mu = s - cv_l.  The chain from one coordinate's b
-        // to the next is b -> t -> clamp -> s -> broadcast -> b; the coupling
-        // x_l and the cv_l term do not depend on b.  A diagonal tile halves
-        // the move of its self coordinate (l == r).
-        // One coordinate step; the (J, J) column entries come from registers
-        // (dense rows, unrolled scan) or from LDS (sparse rows).
-        const double sp_ij = s_ij + p_ij;
-        const double thr_hi = __builtin_canonicalize(thr), thr_lo = __builtin_canonicalize(-thr);
-        auto step = [&](int l, double sJl, double pJl, auto diag_tile) {
-            constexpr bool DIAG = decltype(diag_tile)::value;
-            const double s_il = readlane_f64(s_ij, l), p_il = readlane_f64(p_ij, l);
-            const double cv_l = readlane_f64(cv, l);
-            // x = SP_ii S_lc + SP_il S_ic + P_ic S_il + P_lc S_ii
-            const double x = fma(spii, sJl, fma(sii, pJl, fma(s_il, sp_ij, p_il * s_ij)));
-            const double t = cv - b * ainv;
-            const double st = t - fmax(fmin(t, thr_hi), thr_lo);   // S_thr(t), exact zeros
-            const double s_l = readlane_f64(st, l);
-            const double mu = s_l - cv_l;
-            double mue = mu;
-            if (DIAG && l == r) {
-                mue = 0.5 * mu;
-                b += mue * x;
-            } else {
-                b = fma(s_l, x, fma(-cv_l, x, b));
-            }
-            w1 += mue * sJl;
-            w4 += mue * pJl;
-            s_mine = (c == l) ? st : s_mine;
-        };
-        auto row_dense = [&](auto diag_tile) {
+        const int par = r & 1;
+        // the row operands of row r (waves 2, 3 use those of row r - 1,
+        // fetched in the previous iteration)
+        const double srow = srow_n, prow = prow_n, s_ij = sij_n, p_ij = pij_n;
+        // wave 0's results of the row, used after the barrier
+        double w1 = 0.0, w4 = 0.0, mue_mine = 0.0;
+        uint64_t moved = 0;
+        if (wid == 0) {
+            const double lamv = lam_n, d0 = d_n, g = g_n;
+            if (r + 1 < R) fetch_row(r + 1);
+            const Row64 X = par ? X1 : X0;
+            const int64_t i = rc.r0 + r;
+            const bool colok = inC && (!diag || c >= r);
+            double b = Bs(r, c);
+            const double sii = readlane_f64(srow, r), pii = readlane_f64(prow, r);
+            const bool self = diag && c == r;
+            const double a = self ? sii * sii + 2.0 * sii * pii
+                                  : s_ij * s_ij + sii * s_jj + sii * p_jj + s_jj * pii +
+                                        2.0 * s_ij * p_ij;
+            const bool act = colok && a > 0.0 && (fabs(g) > lamL || lamv != 0.0);
+            const uint64_t mask = __ballot(act);
+            const double ainv = act ? 1.0 / a : 0.0;
+            const double thr = lamL * ainv;
+            // c = Lambda_ij + D_ij with D_ij as left by earlier passes (zero
+            // on the first), unchanged until the coordinate is visited
+            const double cv = lamv + d0;
+            double s_mine = cv;                      // unvisited lanes keep their value
+            const double thr_hi = __builtin_canonicalize(thr), thr_lo = __builtin_canonicalize(-thr);
+            // Coordinate l of the row (lane order): its new value is
+            // s = S_thr(cv - b / a), broadcast from lane l; every lane then
+            // moves b by mu_e x_l with mu = s - cv_l.  The chain from one
+            // coordinate's b to the next is b -> t -> clamp -> s -> broadcast
+            // -> b; x_l and cv_l do not depend on b.  A diagonal tile halves
+            // the move of its self coordinate (l == r).
+            auto step = [&](int l, double x, auto diag_tile) {
+                constexpr bool DIAG = decltype(diag_tile)::value;
+                const double cv_l = readlane_f64(cv, l);
+                const double t = cv - b * ainv;
+                const double st = t - fmax(fmin(t, thr_hi), thr_lo);   // S_thr(t), exact zeros
+                const double s_l = readlane_f64(st, l);
+                const double mu = s_l - cv_l;
+                double mue = mu;
+                if (DIAG && l == r) {
+                    mue = 0.5 * mu;
+                    b += mue * x;
+                } else {
+                    b = fma(s_l, x, fma(-cv_l, x, b));
+                }
+                w1 += mue * regA[l];
+                w4 += mue * regB[l];
+                s_mine = (c == l) ? st : s_mine;
+            };
+            auto row = [&](auto diag_tile) {
+                double xn = X(0, c);             // the next coupling, read one step ahead
 #pragma unroll
-            for (int l = 0; l < T; ++l)
-                if ((mask >> l) & 1ull) step(l, sJc[l], pJc[l], diag_tile);
-        };
-        auto row_sparse = [&](auto diag_tile) {
-            for (uint64_t m = mask; m; m &= m - 1) {
-                const int l = __ffsll((unsigned long long)m) - 1;
-                step(l, sJJ(l, c), pJJ(l, c), diag_tile);
+                for (int l = 0; l < T; ++l) {
+                    const double x = xn;
+                    if (l + 1 < T) xn = X(l + 1, c);
+                    if ((mask >> l) & 1ull) step(l, x, diag_tile);
+                }
+            };
+            if (mask) {
+                if (diag)
+                    row(std::integral_constant<bool, true>{});
+                else
+                    row(std::integral_constant<bool, false>{});
             }
-        };
-        s_mine = cv;                         // unvisited lanes keep their value
-        if (__popcll(mask) >= GS_DENSE_ROW) {
-            if (diag)
-                row_dense(std::integral_constant<bool, true>{});
-            else
-                row_dense(std::integral_constant<bool, false>{});
-        } else if (mask) {
-            if (diag)
-                row_sparse(std::integral_constant<bool, true>{});
-            else
-                row_sparse(std::integral_constant<bool, false>{});
-        }
-        mu_mine = ((mask >> c) & 1ull) ? s_mine - cv : 0.0;
-        if (colok && mu_mine != 0.0) {
-            // new D = S - Lambda, so a thresholded coordinate gives exactly
-            // Lambda + D = 0
-            D[i * q + rc.c0 + c] = s_mine - lamv;
-            D[(int64_t)(rc.c0 + c) * q + i] = s_mine - lamv;
-        }
-        if (inC) {
-            if (!diag) {
-                dDe[r * T + c] = mu_mine;
-            } else if (c >= r) {                 // symmetric delta of a diagonal tile
-                dDe[r * T + c] = mu_mine;
-                dDe[c * T + r] = mu_mine;
+            const double mu_mine = ((mask >> c) & 1ull) ? s_mine - cv : 0.0;
+            if (colok && mu_mine != 0.0) {
+                // new D = S - Lambda, so a thresholded coordinate gives
+                // exactly Lambda + D = 0
+                D[i * q + rc.c0 + c] = s_mine - lamv;
+                D[(int64_t)(rc.c0 + c) * q + i] = s_mine - lamv;
             }
-        }
-        // Corrections of the later rows r2 of the tile:
-        //   b[r2][c] += SP_II[r2][r] w1_c + S_IJ[r][c] w2_r2 + P_IJ[r][c] w3_r2
-        //               + S_II[r][r2] w4_c,
-        //   w2_r2 = sum_l SP_IJ[r2][l] mu_e,l,   w3_r2 = sum_l S_IJ[r2][l] mu_e,l.
-        const double mue_mine = (diag && c == r) ? 0.5 * mu_mine : mu_mine;
-        uint64_t moved = __ballot(mu_mine != 0.0);
-        if (moved == 0) continue;
-        any_change = 1;
-        double w2 = 0.0, w3 = 0.0;            // lane r2 accumulates row r2's values
-        if (__popcll(moved) >= 16) {
-            // dense row: all 64 columns, four partial sums, loads in flight
-            double a2[4] = {0.0, 0.0, 0.0, 0.0}, a3[4] = {0.0, 0.0, 0.0, 0.0};
-            for (int l0 = 0; l0 < T; l0 += 4) {
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const double m = readlane_f64(mue_mine, l0 + u);
-                    const double sv = sIJ(lane, l0 + u);
-                    a2[u] += (sv + pIJ(lane, l0 + u)) * m;
-                    a3[u] += sv * m;
+            if (inC) {
+                if (!diag) {
+                    dDe[r * T + c] = mu_mine;
+                } else if (c >= r) {                 // symmetric delta of a diagonal tile
+                    dDe[r * T + c] = mu_mine;
+                    dDe[c * T + r] = mu_mine;
                 }
             }
-            w2 = (a2[0] + a2[1]) + (a2[2] + a2[3]);
-            w3 = (a3[0] + a3[1]) + (a3[2] + a3[3]);
+            mue_mine = (diag && c == r) ? 0.5 * mu_mine : mu_mine;
+            moved = __ballot(mu_mine != 0.0);
+            if (moved) any_change = 1;
+            // Later rows r2 of the tile then gain
+            //   b[r2][c] += SP_II[r2][r] w1_c + S_IJ[r][c] w2_r2 + P_IJ[r][c] w3_r2
+            //               + S_II[r][r2] w4_c,
+            //   w2_r2 = sum_l SP_IJ[r2][l] mu_e,l,   w3_r2 = sum_l S_IJ[r2][l] mu_e,l.
+            Bs(r, c) = mue_mine;
+            W1[par * T + c] = w1;
+            W4[par * T + c] = w4;
+            if (lane == 0) MOV[par] = moved != 0;
+        } else if (wid == 1) {
+            if (r + 1 < R) couplings(r + 1, par ? X0 : X1);
         } else {
-            while (moved) {
-                const int l = __ffsll((unsigned long long)moved) - 1;
-                moved &= moved - 1;
-                const double m = readlane_f64(mue_mine, l);
-                const double sv = sIJ(lane, l);
-                w2 += (sv + pIJ(lane, l)) * m;
-                w3 += sv * m;
-            }
-        }
-        // (lanes outside the tile add zeros: their LDS entries are zero)
-        for (int r2 = r + 1; r2 < R; r2 += 4) {
-            double bv[4];
+            // fold the moves of row src = r - 1 into rows src + 2 .. R - 1
+            // (this wave's parity of them); fetch row r's operands for the
+            // next row
+            const int src = r - 1;
+            if (r + 1 < R) fetch_row(r);
+            if (src >= 0 && MOV[src & 1] && src + 2 < R) {
+                const double m_l = Bs(src, lane);     // lane l: mu_e of coordinate (src, l)
+                double a2[4] = {0.0, 0.0, 0.0, 0.0}, a3[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (r2 + u < R) bv[u] = Bs(r2 + u, c);
+                for (int l0 = 0; l0 < T; l0 += 4) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (r2 + u < R) {
-                    const int rr = r2 + u;
+                    for (int u = 0; u < 4; ++u) {
+                        const double m = readlane_f64(m_l, l0 + u);
+                        a2[u] += regB[l0 + u] * m;
+                        a3[u] += regA[l0 + u] * m;
+                    }
+                }
+                const double w2 = (a2[0] + a2[1]) + (a2[2] + a2[3]);   // lane r2: row r2's sums
+                const double w3 = (a3[0] + a3[1]) + (a3[2] + a3[3]);
+                const double w1s = W1[(src & 1) * T + lane], w4s = W4[(src & 1) * T + lane];
+                int rr = src + 2;
+                if ((rr & 1) != (wid & 1)) ++rr;
+                for (; rr < R; rr += 2) {
                     const double w2r = readlane_f64(w2, rr), w3r = readlane_f64(w3, rr);
                     const double s_r2 = readlane_f64(srow, rr), p_r2 = readlane_f64(prow, rr);
-                    Bs(rr, c) = bv[u] + ((s_r2 + p_r2) * w1 + s_ij * w2r + p_ij * w3r + s_r2 * w4);
+                    Bs(rr, c) = Bs(rr, c) + ((s_r2 + p_r2) * w1s + s_ij * w2r + p_ij * w3r +
+                                             s_r2 * w4s);
                 }
             }
         }
+        __syncthreads();
+        if (wid == 0 && moved && r + 1 < R) {
+            // row r + 1 now, the rows after it by waves 2 and 3 during the next row
+            const double w2n = wave_sum((sij_n + pij_n) * mue_mine);
+            const double w3n = wave_sum(sij_n * mue_mine);
+            const double s_r2 = readlane_f64(srow, r + 1), p_r2 = readlane_f64(prow, r + 1);
+            Bs(r + 1, c) =
+                Bs(r + 1, c) + ((s_r2 + p_r2) * w1 + s_ij * w2n + p_ij * w3n + s_r2 * w4);
+        }
     }
-    if (lane == 0) {
+    if (wid == 0 && lane == 0) {
         changed[e] = any_change;
         // update (run only for a tile that changed): Sigma rows read, U rows
         // read and written (both index sets of an off-diagonal tile)

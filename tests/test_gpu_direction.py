@@ -67,6 +67,40 @@ def test_sequential_direction_matches_oracle(cg, orc, p, q, n, passes):
     assert rel(V, Th @ Sig) < 1e-12
 
 
+@pytest.mark.parametrize("p,q,n,passes,tile,level", [(120, 150, 100, 2, 64, 0),
+                                                     (90, 200, 160, 1, 64, 1),
+                                                     (60, 100, 90, 2, 32, 0)])
+def test_tiled_direction_matches_its_definition(cg, orc, tmp_path, p, q, n, passes, tile,
+                                                level):
+    """The tiled direction (waves of tiles, exact Gauss-Seidel inside a tile
+    from the snapshot at the start of its sub-wave) against that schedule
+    written out coordinate by coordinate in numpy, with the library's own wave
+    lists: ragged edge tiles (q not a multiple of the tile edge), diagonal and
+    off-diagonal tiles, several passes, sub-waves."""
+    import shutil
+    from tiled_emulation import build_schedule_exe, sub_waves, tiled_direction
+    if shutil.which("g++") is None:
+        pytest.skip("needs g++ for the schedule dump")
+    pr = synth.chain_problem(p=p, q=q, n=n, density=0.05, lam=0.06, seed=q + passes)
+    Lam, Th = iterate(cg, pr, 3)
+    D, U, _ = cg.cggm_lambda_direction(dev(pr.X), dev(pr.Y), dev(Lam), dev(Th),
+                                       pr.lam_Lambda, pr.lam_Theta, lambda_passes=passes,
+                                       tile=tile, split_level=level)
+    S = orc.stats(pr.X, pr.Y)
+    GL, GT, Sig, Psi = orc.gradient(S, Lam, Th)
+    aL, _ = orc.active_sets(GL, GT, Lam, Th, pr.lam_Lambda, pr.lam_Theta)
+    waves = sub_waves(build_schedule_exe(tmp_path), q, tile, 2 ** level)
+    De = tiled_direction(Sig, Psi, GL, Lam, aL, pr.lam_Lambda, waves, passes)
+    D, U = D.cpu().numpy(), U.cpu().numpy()
+    print(f"q={q} tile={tile} passes={passes} level={level}: |D - D_def| rel "
+          f"{rel(D, De):.2e}, nnz {np.count_nonzero(D)} / {np.count_nonzero(De)}, "
+          f"active {int(aL.sum())}", flush=True)
+    assert np.count_nonzero(De) > q
+    assert rel(D, De) < 1e-9
+    assert np.array_equal(D == 0, De == 0)
+    assert rel(U, D @ Sig) < 1e-12
+
+
 @pytest.mark.parametrize("p,q,n", [(530, 530, 200), (4096, 4096, 500)])
 def test_mixed_mode_errors_per_result(cg, orc, p, q, n):
     """Mixed against FP64 at the same point (the FP64 iterate after 3

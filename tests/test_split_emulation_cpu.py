@@ -11,28 +11,20 @@ between every pair of outputs), the concurrent passes diverge and no Armijo
 step exists, while running each wave as enough consecutive sub-waves gives a
 descent direction the line search accepts.  The direction, its decrease and
 the line search are measured with the oracle's functions.  CPU only."""
-import os
 import shutil
-import subprocess
 
 import numpy as np
 import pytest
 
 import synth
-
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+from tiled_emulation import build_schedule_exe, sub_waves, tiled_direction
 
 
 @pytest.fixture(scope="module")
 def schedule_exe(tmp_path_factory):
     if shutil.which("g++") is None:
         pytest.skip("needs g++")
-    exe = tmp_path_factory.mktemp("sched") / "schedule_test"
-    subprocess.run(["g++", "-std=c++17", "-O1", "-Wall", "-Werror",
-                    "-I", os.path.join(ROOT, "paper_1509_04681_amd", "csrc"),
-                    os.path.join(ROOT, "tests", "cpp", "schedule_test.cpp"), "-o", str(exe)],
-                   check=True)
-    return str(exe)
+    return build_schedule_exe(tmp_path_factory.mktemp("sched"))
 
 
 @pytest.fixture(scope="module")
@@ -40,54 +32,6 @@ def orc():
     import oracle
     oracle.build()
     return oracle
-
-
-def sub_waves(exe, q, tile, parts):
-    out = subprocess.run([exe, "dump", str(q), str(tile), str(parts)], capture_output=True,
-                         text=True, check=True).stdout
-    waves = []
-    for line in out.splitlines():
-        v = [int(x) for x in line.split()]
-        waves.append([tuple(v[k:k + 4]) for k in range(0, len(v), 4)])
-    return waves
-
-
-def tiled_direction(Sig, Psi, G, Lam, act, lam, waves, passes):
-    """Lambda CD passes run wave by wave: every tile of a sub-wave starts from
-    the same D (its snapshot), runs exact Gauss-Seidel over its active upper-
-    triangle coordinates in row order, and the tiles' changes are added at the
-    end of the sub-wave (disjoint coordinates)."""
-    q = Sig.shape[0]
-    D = np.zeros((q, q))
-    for _ in range(passes):
-        for wave in waves:
-            U = D @ Sig
-            change = np.zeros((q, q))
-            for r0, r1, c0, c1 in wave:
-                Dl, Ul = D.copy(), U.copy()
-                for i in range(r0, r1):
-                    for j in range(max(i, c0), c1):
-                        if not act[i, j]:
-                            continue
-                        if i == j:
-                            a = Sig[i, i] ** 2 + 2 * Sig[i, i] * Psi[i, i]
-                        else:
-                            a = (Sig[i, j] ** 2 + Sig[i, i] * Sig[j, j] + Sig[i, i] * Psi[j, j]
-                                 + Sig[j, j] * Psi[i, i] + 2 * Sig[i, j] * Psi[i, j])
-                        b = G[i, j] + Sig[i] @ Ul[:, j] + Psi[i] @ Ul[:, j] + Psi[j] @ Ul[:, i]
-                        c = Lam[i, j] + Dl[i, j]
-                        w = c - b / a
-                        mu = -c + np.sign(w) * max(abs(w) - lam / a, 0.0)
-                        if mu == 0.0:
-                            continue
-                        Dl[i, j] += mu
-                        Ul[i] += mu * Sig[j]
-                        if i != j:
-                            Dl[j, i] += mu
-                            Ul[j] += mu * Sig[i]
-                change += Dl - D
-            D = D + change
-    return D
 
 
 def test_split_levels_repair_a_divergent_direction(schedule_exe, orc):
