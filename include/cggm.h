@@ -323,9 +323,11 @@ int cggm_objective_noalloc(const void *X, const void *Y, int64_t n, int64_t p, i
  * counter-based generator, lambda = 0.02, near-dense active sets) with the
  * options `opt` (NULL = defaults) and each candidate tile edge 16, 32, 64 for
  * one warm-up and `iters` (1..50) timed outer iterations from Lambda = I,
- * Theta = 0, and writes the edge with the shortest time per iteration to
- * *tile (host) and, when `ms` is not NULL, the three times in milliseconds
- * (host, 3 doubles).  Pass the edge as options.tile (or a request's tile) for
+ * Theta = 0, twice per edge in the order 64, 32, 16, 16, 32, 64, and writes
+ * to *tile (host) the edge with the shortest time per iteration (the better
+ * of its two runs), where 64 stays unless a smaller edge is at least 5%
+ * faster, and, when `ms` is not NULL, the three times in milliseconds (host,
+ * 3 doubles, for 16, 32, 64).  Pass the edge as options.tile (or a request's tile) for
  * problems of about that shape.  The choice changes the order of the
  * coordinate updates, hence the iterates, not the optimum.  Allocates its
  * own inputs and one solve workspace at a time; blocking.

@@ -46,8 +46,8 @@ constexpr int GS_DENSE_ROW = 16;
 constexpr int LDT = TT + 1;
 
 // ----------------------------------------------------------------- activity --
-// active[r] = 1 when rect r holds a coordinate with |G| > lam or P != 0
-// (upper triangle only for the diagonal rects of Lambda).
+// active[r] = the number of coordinates of rect r with |G| > lam or P != 0
+// (upper triangle only for the diagonal rects of Lambda); nonzero = active.
 __global__ __launch_bounds__(BLOCK) void tile_activity_kernel(const TileRect *__restrict__ rects,
                                                               int64_t ld, const double *__restrict__ G,
                                                               const double *__restrict__ P,
@@ -56,16 +56,20 @@ __global__ __launch_bounds__(BLOCK) void tile_activity_kernel(const TileRect *__
     const TileRect rc = rects[blockIdx.x];
     const int R = rc.r1 - rc.r0, C = rc.c1 - rc.c0;
     const bool diag = upper && rc.r0 == rc.c0;
-    int any = 0;
+    __shared__ int count;
+    if (threadIdx.x == 0) count = 0;
+    __syncthreads();
+    int mine = 0;
     for (int k = threadIdx.x; k < R * C; k += BLOCK) {
         const int r = k / C, c = k % C;
         if (!diag || c >= r) {
             const int64_t idx = (int64_t)(rc.r0 + r) * ld + rc.c0 + c;
-            any |= (fabs(G[idx]) > lam || P[idx] != 0.0);
+            mine += (fabs(G[idx]) > lam || P[idx] != 0.0) ? 1 : 0;
         }
     }
-    any = __syncthreads_or(any);
-    if (threadIdx.x == 0) active[blockIdx.x] = any;
+    if (mine) atomicAdd(&count, mine);
+    __syncthreads();
+    if (threadIdx.x == 0) active[blockIdx.x] = count;
 }
 
 // ----------------------------------------------------------------- snapshot --
@@ -733,25 +737,218 @@ struct Row64 {
 };
 
 // Exact Gauss-Seidel over the active coordinates of one tile, row by row,
-// lane = column, by the four wavefronts of the workgroup with one workgroup
-// barrier per row r:
-//   wave 0 runs the coordinate chain of row r: the row's coordinates in lane
-//     order with v_readlane broadcasts, the in-row couplings x read from LDS,
-//     the dependent chain of one step three fused multiply-adds and a clamp
-//     (soft threshold as t - max(min(t, hi), lo)); it writes D, the tile's
-//     delta, and the row's moves and w1, w4 sums for the other waves, and
-//     after the barrier folds row r's moves into row r + 1 of the snapshot;
-//   wave 1 forms the couplings x_l(c) of row r + 1 (from the Sigma / Psi rows
-//     of the tile, the (J, J) columns held in registers) into the other of
-//     two LDS buffers;
-//   waves 2 and 3 fold the moves of row r - 1 into rows r + 1 .. R - 1 of the
-//     snapshot (even and odd rows), holding the rows of S_IJ and SP_IJ in
-//     registers.
+// lane = column: the row's coordinates in lane order with v_readlane
+// broadcasts, the dependent chain of one step three fused multiply-adds and
+// a clamp (soft threshold as t - max(min(t, hi), lo)), then the moves of the
+// row folded into the later rows.  A tile with fewer than GS_WIDE_MIN active
+// coordinates is run by one wavefront, which forms each coupling x_l(c) in
+// the step and folds each row into all later rows itself.  A denser tile
+// is run by the four wavefronts of the workgroup with one workgroup barrier
+// per row r:
+//   wave 0 runs only the coordinate chain of row r, the couplings read from
+//     LDS a step ahead; it writes D, the tile's delta, and the row's moves
+//     and w1, w4 sums for the other waves, and after the barrier folds row
+//     r's moves into row r + 1;
+//   wave 1 forms the couplings of row r + 1 (from the Sigma / Psi rows of the
+//     tile, the (J, J) columns held in registers) into the other of two LDS
+//     buffers;
+//   waves 2 and 3 fold row r - 1's moves into rows r + 1 .. R - 1 (even and
+//     odd rows), holding the rows of S_IJ and SP_IJ in registers.
 // So the chain of row r + 1 starts right after the barrier that ends row r,
 // with its couplings formed and every earlier row's moves folded in, in row
-// order.  The arithmetic of every value is that of one wavefront doing all of
-// it, except the sums w2, w3 of row r + 1 (a butterfly sum instead of four
-// strided partial sums).
+// order.  Both forms compute every value as one wavefront doing all of it
+// would, except the four-wave form's sums w2, w3 of row r + 1 (a butterfly
+// sum instead of four strided partial sums).
+constexpr int GS_WIDE_MIN = 256;
+
+// The one-wavefront form of lambda_gs_kernel for a sparse tile: wave 0 of the
+// workgroup after the snapshot, S_IJ and P_IJ are staged (Bs, St, Pt).
+__device__ __forceinline__ void lambda_gs_one_wave(
+    const TileRect rc, int e, int64_t q, const double *__restrict__ Sigma,
+    const double *__restrict__ Psi, const double *__restrict__ GL,
+    const double *__restrict__ Lam, double lamL, double *__restrict__ D,
+    double *__restrict__ dD, int *__restrict__ changed, unsigned long long *__restrict__ ctr,
+    int esz, const Swz64 Bs, const Swz64 St, const Swz64 Pt) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int R = rc.r1 - rc.r0, C = rc.c1 - rc.c0;
+    const bool diag = rc.r0 == rc.c0;
+    const int c = lane;
+    const bool inC = c < C;
+    const double s_jj = inC ? Sigma[(int64_t)(rc.c0 + c) * q + rc.c0 + c] : 0.0;
+    const double p_jj = inC ? Psi[(int64_t)(rc.c0 + c) * q + rc.c0 + c] : 0.0;
+    // lane c keeps column c of the (J, J) blocks in registers for the whole
+    // tile
+    double sJc[T], pJc[T];
+#pragma unroll
+    for (int l = 0; l < T; ++l) {
+        const int64_t o = (int64_t)(rc.c0 + l) * q + rc.c0 + c;
+        sJc[l] = (inC && l < C) ? Sigma[o] : 0.0;
+        pJc[l] = (inC && l < C) ? Psi[o] : 0.0;
+    }
+    int any_change = 0;
+    double *dDe = dD + (int64_t)e * T * T;
+    // Per-row global operands, fetched one row ahead: lane r2 holds
+    // Sigma_II[r][r2] and Psi_II[r][r2]; lane c holds Lambda, D and G at (r, c).
+    // (The prefetch of D's next row precedes this row's writes: the only
+    // writes into later rows of the tile are the mirror entries of a diagonal
+    // tile, below the diagonal, which the coordinate loop never reads.)
+    const bool inR = lane < R;
+    double srow_n = 0.0, prow_n = 0.0, lam_n = 0.0, d_n = 0.0, g_n = 0.0;
+    auto fetch_row = [&](int r) {
+        const int64_t ro = (int64_t)(rc.r0 + r) * q;
+        if (inR) {
+            srow_n = Sigma[ro + rc.r0 + lane];
+            prow_n = Psi[ro + rc.r0 + lane];
+        }
+        if (inC) {
+            lam_n = Lam[ro + rc.c0 + c];
+            d_n = D[ro + rc.c0 + c];
+            g_n = GL[ro + rc.c0 + c];
+        }
+    };
+    fetch_row(0);
+    for (int r = 0; r < R; ++r) {
+        const double srow = srow_n, prow = prow_n, lamv = lam_n, d0 = d_n, g = g_n;
+        if (r + 1 < R) fetch_row(r + 1);
+        const int64_t i = rc.r0 + r;
+        const bool colok = inC && (!diag || c >= r);
+        const double s_ij = St(r, c), p_ij = Pt(r, c);
+        double b = Bs(r, c);
+        const double sii = readlane_f64(srow, r), pii = readlane_f64(prow, r);
+        const double spii = sii + pii;
+        const bool self = diag && c == r;
+        const double a = self ? sii * sii + 2.0 * sii * pii
+                              : s_ij * s_ij + sii * s_jj + sii * p_jj + s_jj * pii +
+                                    2.0 * s_ij * p_ij;
+        const bool act = colok && a > 0.0 && (fabs(g) > lamL || lamv != 0.0);
+        const uint64_t mask = __ballot(act);
+        const double ainv = act ? 1.0 / a : 0.0;
+        const double thr = lamL * ainv;
+        // c = Lambda_ij + D_ij with D_ij as left by earlier passes (zero on the
+        // first), unchanged until the coordinate is visited
+        const double cv = lamv + d0;
+        double w1 = 0.0, w4 = 0.0, mu_mine = 0.0, s_mine;
+        // Coordinate l of the row (lane order): its new value is
+        // s = S_thr(cv - b / a), broadcast from lane l; every lane then moves
+        // b by mu_e x_l with mu = s - cv_l.  The chain from one coordinate's b
+        // to the next is b -> t -> clamp -> s -> broadcast -> b; the coupling
+        // x_l and the cv_l term do not depend on b.  A diagonal tile halves
+        // the move of its self coordinate (l == r).
+        // One coordinate step; the (J, J) column entries come from registers
+        // (dense rows, unrolled scan) or from LDS (sparse rows).
+        const double sp_ij = s_ij + p_ij;
+        const double thr_hi = __builtin_canonicalize(thr), thr_lo = __builtin_canonicalize(-thr);
+        auto step = [&](int l, double sJl, double pJl, auto diag_tile) {
+            constexpr bool DIAG = decltype(diag_tile)::value;
+            const double s_il = readlane_f64(s_ij, l), p_il = readlane_f64(p_ij, l);
+            const double cv_l = readlane_f64(cv, l);
+            // x = SP_ii S_lc + SP_il S_ic + P_ic S_il + P_lc S_ii
+            const double x = fma(spii, sJl, fma(sii, pJl, fma(s_il, sp_ij, p_il * s_ij)));
+            const double t = cv - b * ainv;
+            const double st = t - fmax(fmin(t, thr_hi), thr_lo);   // S_thr(t), exact zeros
+            const double s_l = readlane_f64(st, l);
+            const double mu = s_l - cv_l;
+            double mue = mu;
+            if (DIAG && l == r) {
+                mue = 0.5 * mu;
+                b += mue * x;
+            } else {
+                b = fma(s_l, x, fma(-cv_l, x, b));
+            }
+            w1 += mue * sJl;
+            w4 += mue * pJl;
+            s_mine = (c == l) ? st : s_mine;
+        };
+        auto row_dense = [&](auto diag_tile) {
+#pragma unroll
+            for (int l = 0; l < T; ++l)
+                if ((mask >> l) & 1ull) step(l, sJc[l], pJc[l], diag_tile);
+        };
+        s_mine = cv;                         // unvisited lanes keep their value
+        if (mask) {
+            if (diag)
+                row_dense(std::integral_constant<bool, true>{});
+            else
+                row_dense(std::integral_constant<bool, false>{});
+        }
+        mu_mine = ((mask >> c) & 1ull) ? s_mine - cv : 0.0;
+        if (colok && mu_mine != 0.0) {
+            // new D = S - Lambda, so a thresholded coordinate gives exactly
+            // Lambda + D = 0
+            D[i * q + rc.c0 + c] = s_mine - lamv;
+            D[(int64_t)(rc.c0 + c) * q + i] = s_mine - lamv;
+        }
+        if (inC) {
+            if (!diag) {
+                dDe[r * T + c] = mu_mine;
+            } else if (c >= r) {                 // symmetric delta of a diagonal tile
+                dDe[r * T + c] = mu_mine;
+                dDe[c * T + r] = mu_mine;
+            }
+        }
+        // Corrections of the later rows r2 of the tile:
+        //   b[r2][c] += SP_II[r2][r] w1_c + S_IJ[r][c] w2_r2 + P_IJ[r][c] w3_r2
+        //               + S_II[r][r2] w4_c,
+        //   w2_r2 = sum_l SP_IJ[r2][l] mu_e,l,   w3_r2 = sum_l S_IJ[r2][l] mu_e,l.
+        const double mue_mine = (diag && c == r) ? 0.5 * mu_mine : mu_mine;
+        uint64_t moved = __ballot(mu_mine != 0.0);
+        if (moved == 0) continue;
+        any_change = 1;
+        double w2 = 0.0, w3 = 0.0;            // lane r2 accumulates row r2's values
+        if (__popcll(moved) >= 16) {
+            // dense row: all 64 columns, four partial sums, loads in flight
+            double a2[4] = {0.0, 0.0, 0.0, 0.0}, a3[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int l0 = 0; l0 < T; l0 += 4) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const double m = readlane_f64(mue_mine, l0 + u);
+                    const double sv = St(lane, l0 + u);
+                    a2[u] += (sv + Pt(lane, l0 + u)) * m;
+                    a3[u] += sv * m;
+                }
+            }
+            w2 = (a2[0] + a2[1]) + (a2[2] + a2[3]);
+            w3 = (a3[0] + a3[1]) + (a3[2] + a3[3]);
+        } else {
+            while (moved) {
+                const int l = __ffsll((unsigned long long)moved) - 1;
+                moved &= moved - 1;
+                const double m = readlane_f64(mue_mine, l);
+                const double sv = St(lane, l);
+                w2 += (sv + Pt(lane, l)) * m;
+                w3 += sv * m;
+            }
+        }
+        // (lanes outside the tile add zeros: their LDS entries are zero)
+        for (int r2 = r + 1; r2 < R; r2 += 4) {
+            double bv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (r2 + u < R) bv[u] = Bs(r2 + u, c);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (r2 + u < R) {
+                    const int rr = r2 + u;
+                    const double w2r = readlane_f64(w2, rr), w3r = readlane_f64(w3, rr);
+                    const double s_r2 = readlane_f64(srow, rr), p_r2 = readlane_f64(prow, rr);
+                    Bs(rr, c) = bv[u] + ((s_r2 + p_r2) * w1 + s_ij * w2r + p_ij * w3r + s_r2 * w4);
+                }
+            }
+        }
+    }
+    if (lane == 0) {
+        changed[e] = any_change;
+        // update (run only for a tile that changed): Sigma rows read, U rows
+        // read and written (both index sets of an off-diagonal tile)
+        if (ctr && any_change) {
+            const int64_t ub = diag ? esz * q * 3 * R : esz * q * 3 * (R + C);
+            atomicAdd(ctr + 5, (unsigned long long)ub);
+            atomicAdd(ctr + 6, (unsigned long long)((diag ? 2 : 4) * (int64_t)R * C * q));
+        }
+    }
+}
+
+
 __global__ __launch_bounds__(BLOCK) void lambda_gs_kernel(
     const TileRect *__restrict__ rects, const int *__restrict__ active, int S,
     const double *__restrict__ partial, int64_t q, const double *__restrict__ Sigma,
@@ -770,26 +967,25 @@ __global__ __launch_bounds__(BLOCK) void lambda_gs_kernel(
     const TileRect rc = rects[e];
     const int R = rc.r1 - rc.r0, C = rc.c1 - rc.c0;
     const bool diag = rc.r0 == rc.c0;
-    // LDS: the b snapshot (row r, once its chain has read it, carries row r's
-    // moves), two coupling buffers X (l, c), the w1 / w4 sums of the last two
-    // rows and their "row moved" flags.
+    // LDS: the b snapshot, S_IJ and P_IJ (XOR-swizzled: rows and columns are
+    // both conflict-free); in the four-wave form, once waves 2 and 3 hold
+    // their rows of S_IJ and SP_IJ, the two coupling blocks X (l, c) take the
+    // place of S_IJ and P_IJ, row r of the snapshot carries row r's moves once
+    // its chain has read it, and the w1 / w4 sums of the last two rows and
+    // their "row moved" flags follow.
     __shared__ double lds[3 * T * T + 4 * T + 2];
-    // (S_IJ and SP_IJ are staged in the coupling buffers' memory, swizzled,
-    // before the first couplings are formed)
-    const Swz64 Bs{lds}, St{lds + T * T}, SPt{lds + 2 * T * T};
+    const Swz64 Bs{lds}, St{lds + T * T}, Pt{lds + 2 * T * T};
     const Row64 X0{lds + T * T}, X1{lds + 2 * T * T};
     double *const W1 = lds + 3 * T * T, *const W4 = W1 + 2 * T;
     int *const MOV = reinterpret_cast<int *>(W4 + 2 * T);
     const double *snap = partial + (int64_t)e * S * T * T;    // summed into part 0
-    // S_IJ and SP_IJ staged in the coupling buffers for waves 2 and 3
     for (int k = tid; k < T * T; k += BLOCK) {
         const int r = k / T, c = k % T;
         const bool ij = r < R && c < C;
         const int64_t o = (int64_t)(rc.r0 + r) * q + rc.c0 + c;
         Bs(r, c) = ij ? snap[k] + GL[o] : 0.0;
-        const double s = ij ? Sigma[o] : 0.0, pv = ij ? Psi[o] : 0.0;
-        St(r, c) = s;
-        SPt(r, c) = s + pv;
+        St(r, c) = ij ? Sigma[o] : 0.0;
+        Pt(r, c) = ij ? Psi[o] : 0.0;
     }
     if (ctr && tid == 0) {
         const int64_t RC = (int64_t)R * C;
@@ -803,14 +999,21 @@ __global__ __launch_bounds__(BLOCK) void lambda_gs_kernel(
         atomicAdd(ctr + 4, (unsigned long long)(16 * RC * C));
     }
     __syncthreads();
+    if (active[e] < GS_WIDE_MIN) {
+        if (wid == 0)
+            lambda_gs_one_wave(rc, e, q, Sigma, Psi, GL, Lam, lamL, D, dD, changed, ctr, esz, Bs,
+                               St, Pt);
+        return;
+    }
     // Waves 0, 1: column `lane` of S_JJ and P_JJ; waves 2, 3: row `lane` of
     // S_IJ and SP_IJ (zero outside the tile).
     double regA[T], regB[T];
     if (wid >= 2) {
 #pragma unroll
         for (int l = 0; l < T; ++l) {
-            regA[l] = St(lane, l);
-            regB[l] = SPt(lane, l);
+            const double s = St(lane, l);
+            regA[l] = s;
+            regB[l] = s + Pt(lane, l);
         }
     } else {
         const bool inC = lane < C;

@@ -70,13 +70,18 @@ def test_graph_replay_through_split_levels(cg):
 
 
 def test_autotuned_tile_in_the_server(cg):
-    """The tile-edge autotuner picks one of its candidates from measured times;
-    a request served with that edge (graph replay on in the server) equals the
-    plain path solve with the same edge bit for bit."""
+    """The tile-edge autotuner picks one of its candidates from measured times
+    (the default 64 unless a smaller edge is at least 5% faster); a request
+    served with that edge (graph replay on in the server) equals the plain
+    path solve with the same edge bit for bit."""
     tile, ms = cg.cggm_autotune_tile(200, 300, 250, iters=2)
     print(f"autotune 300 x 250: tile {tile}, ms per iteration {ms}", flush=True)
     assert tile in (16, 32, 64) and all(np.isfinite(v) and v > 0 for v in ms.values())
-    assert ms[tile] == min(ms.values())
+    expect = 64
+    for edge in (32, 16):
+        if ms[edge] < 0.95 * ms[expect]:
+            expect = edge
+    assert tile == expect
     pr = synth.chain_problem(p=300, q=250, n=200, density=0.02, lam=0.1, seed=43)
     X, Y = dev(pr.X), dev(pr.Y)
     lam = [0.3, 0.15, 0.08]
