@@ -40,8 +40,8 @@ namespace {
 constexpr int T = LAMBDA_TILE;    // 64
 constexpr int TT = THETA_TILE;    // 64
 // Rows with at least this many active coordinates take the unrolled
-// register-operand scan in the Gauss-Seidel kernels; sparser rows iterate over
-// their active lanes only.
+// register-operand scan in the Theta Gauss-Seidel kernel; sparser rows iterate
+// over their active lanes only.
 constexpr int GS_DENSE_ROW = 16;
 constexpr int LDT = TT + 1;
 
