@@ -1091,8 +1091,7 @@ SolveOutcome Solver::Impl::run(double lamL, double lamT, double tol) {
         // wave (exact block Gauss-Seidel; at q = 20000 about a minute).
         bool th_fired = false;
         while (t > 0 && !seq) {
-            const double theta_guard = swept_mixed ? 1e-10 : F_ROUNDING;
-            if (!(top.f > f_after_ls + theta_guard * std::max(1.0, fabs(f_after_ls)))) break;
+            if (!(top.f > f_after_ls + F_ROUNDING * std::max(1.0, fabs(f_after_ls)))) break;
             th_fired = true;
             CGGM_HIP(hipMemcpyAsync(w.Th, w.ThOld, sizeof(double) * pq, hipMemcpyDeviceToDevice,
                                     s));
