@@ -268,6 +268,35 @@ def test_golden_chain2k(cg):
     assert mL == 0 and mT == 0
 
 
+def test_chain2k_against_oracle_tail(cg):
+    """The 2000 x 2000 chain workload solved to its rounding floor with the
+    default options, against tests/golden/chain2k_tail.json: the oracle's
+    objective f_K after K iterations bounds f* from above, so the solve's
+    limit may not exceed it; and the oracle's geometric-tail extrapolation of
+    f* (fitted over its last 10 decreases) must agree with that limit within
+    twice the spread of the extrapolations over windows of 10 to 80
+    decreases.  The extrapolation is the oracle's estimate of f*, not f*."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "chain2k_tail.json")
+    if not os.path.exists(path):
+        pytest.skip("tests/golden/chain2k_tail.json has not been written")
+    import json
+    with open(path) as fh:
+        tail = json.load(fh)
+    pr = synth.workload("chain2k")
+    # f no longer changes in its 12th digit after ~600 iterations here
+    g = cg.cggm_solve(dev(pr.X), dev(pr.Y), pr.lam_Lambda, pr.lam_Theta, tol=0.0,
+                      max_iter=800, trace_cap=0)
+    nL = int(np.count_nonzero(np.abs(g.Lambda.cpu().numpy()) > SUPPORT_EPS))
+    nT = int(np.count_nonzero(np.abs(g.Theta.cpu().numpy()) > SUPPORT_EPS))
+    est, tol = tail["f_star_estimate"], 2.0 * tail["f_star_spread"]
+    print(f"chain2k: f_gpu={g.f!r} iters={g.iters} oracle f_K={tail['f_K']!r} "
+          f"(K={tail['iterations']}) f*~{est!r} +- {tol:.2e} "
+          f"(gpu - est = {g.f - est:.2e}); nnz gpu {nL}/{nT} oracle at K "
+          f"{tail['nnz_Lambda']}/{tail['nnz_Theta']}", flush=True)
+    assert g.f <= tail["f_K"] * (1 + 1e-12)
+    assert abs(g.f - est) <= tol
+
+
 def test_monotone_and_pd_trace(cg):
     pr = synth.chain_problem(p=60, q=70, n=80, density=0.05, lam=0.08, seed=5)
     g = cg.cggm_solve(dev(pr.X), dev(pr.Y), pr.lam_Lambda, pr.lam_Theta, tol=0.0, max_iter=400)
