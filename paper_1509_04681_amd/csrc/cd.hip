@@ -835,7 +835,7 @@ __device__ __forceinline__ void lambda_gs_one_wave(
         // x_l and the cv_l term do not depend on b.  A diagonal tile halves
         // the move of its self coordinate (l == r).
         // One coordinate step; the (J, J) column entries come from registers
-        // (dense rows, unrolled scan) or from LDS (sparse rows).
+        // (an unrolled scan over the row, masked by the active lanes).
         const double sp_ij = s_ij + p_ij;
         const double thr_hi = __builtin_canonicalize(thr), thr_lo = __builtin_canonicalize(-thr);
         auto step = [&](int l, double sJl, double pJl, auto diag_tile) {
