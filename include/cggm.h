@@ -367,6 +367,40 @@ int cggm_gradient(const void *X, const void *Y, int64_t n, int64_t p, int64_t q,
                   const double *Lambda, const double *Theta, double *G_Lambda,
                   double *G_Theta, void *stream);
 
+/*
+ * Columns of Sigma = Lambda^{-1} by conjugate gradients, as the block-wise
+ * method (Sec. 4.1) obtains the Sigma columns of a block: for each listed
+ * column j it solves Lambda x = e_j, with Lambda sparse symmetric positive
+ * definite, in O(m_Lambda) work per iteration and column; up to 64 columns
+ * advance together (one sparse-by-dense product per iteration), larger lists
+ * run in batches of 64.
+ *   rowptr, col, val: Lambda in CSR with both triangles stored (device
+ *     pointers; rowptr holds q + 1 int64 offsets starting at 0, col the int32
+ *     column of each of the rowptr[q] entries, val their values).  rowptr is
+ *     checked on the host and col on the device before any product: a
+ *     decreasing rowptr or a column outside [0, q) gives CGGM_EINVAL.  The
+ *     symmetry of Lambda is the caller's to guarantee.
+ *   cols: host array of k column indices in [0, q) (repeats allowed).
+ *   tol: a column stops once its residual norm ||e_j - Lambda x|| is at most
+ *     tol (the right-hand side has unit norm, so tol is relative); tol >= 0.
+ *   max_iter: iterations per batch, >= 1 (checked every 8 iterations, so a
+ *     batch may run up to 7 iterations past convergence, without changing
+ *     its converged columns).
+ *   Sigma_C: caller device buffer of q x k doubles, row-major: column t is
+ *     Sigma's column cols[t].
+ *   iters, resid (host, may be NULL): the most iterations a batch ran, and
+ *     the largest final residual norm over the columns.
+ * Returns CGGM_OK when every column reached tol, CGGM_MAXITER (result valid)
+ * when some did not within max_iter, CGGM_ENOTPD when a search direction met
+ * a curvature p^T Lambda p that is not positive (Lambda not positive
+ * definite), CGGM_EINVAL, CGGM_ENOMEM (the call allocates 2 KiB per row of
+ * Lambda plus 2 MiB, freed before it returns) or CGGM_EHIP.  Work is ordered
+ * on `stream` and the call returns when it is done.
+ */
+int cggm_sigma_columns(const int64_t *rowptr, const int32_t *col, const double *val,
+                       int64_t q, const int32_t *cols, int64_t k, double tol, int max_iter,
+                       double *Sigma_C, int *iters, double *resid, void *stream);
+
 /* ---- request server (continuous batching on one GPU) --------------------
  *
  * Solves regularisation paths of many independent problems concurrently on

@@ -8,7 +8,7 @@ library, but every call raises if ``libcggm.so`` is missing.
 Entry points mirror ``include/cggm.h``: :func:`cggm_solve`,
 :func:`cggm_solve_path`, :func:`cggm_objective`,
 :func:`cggm_objective_noalloc`, :func:`cggm_lambda_direction`,
-:func:`cggm_gradient`, the
+:func:`cggm_gradient`, :func:`cggm_sigma_columns`, the
 request server :class:`Server` (``cggm_server_*``), plus
 ``cggm_status_string`` and the workspace-size queries.
 """
@@ -172,6 +172,10 @@ def load() -> ctypes.CDLL:
     lib.cggm_gradient.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_int, _vp, _vp, _vp, _vp,
                                   _vp]
     lib.cggm_gradient.restype = ctypes.c_int
+    lib.cggm_sigma_columns.argtypes = [_vp, _vp, _vp, _i64, _vp, _i64, ctypes.c_double,
+                                       ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_int),
+                                       ctypes.POINTER(ctypes.c_double), _vp]
+    lib.cggm_sigma_columns.restype = ctypes.c_int
     lib.cggm_status_string.argtypes = [ctypes.c_int]
     lib.cggm_status_string.restype = ctypes.c_char_p
     lib.cggm_last_error.argtypes = []
@@ -479,6 +483,49 @@ def cggm_gradient(X, Y, Lambda, Theta, stream=None):
                              _dev(Theta, "Theta"), _dev(GL, "G_Lambda"), _dev(GT, "G_Theta"),
                              _stream(stream)))
     return GL, GT
+
+
+@dataclasses.dataclass
+class SigmaColumns:
+    Sigma_C: object        # q x k device tensor: column t is Sigma's column cols[t]
+    iters: int             # the most iterations a batch of 64 columns ran
+    resid: float           # largest final residual norm over the columns
+    status: int            # CGGM_OK, or CGGM_MAXITER when some column missed tol
+
+
+def cggm_sigma_columns(rowptr, col, val, cols, tol=1e-12, max_iter=1000, stream=None):
+    """Columns `cols` of Sigma = Lambda^{-1} by conjugate gradients on a sparse
+    symmetric positive definite Lambda (Sec. 4.1): Lambda in CSR as device
+    tensors (rowptr int64 of q + 1 entries, col int32 and val float64 of
+    rowptr[q] entries, both triangles stored); `cols` a sequence of column
+    indices.  Raises CggmError on an error status."""
+    import torch
+    lib = load()
+    for t, name, dt in ((rowptr, "rowptr", torch.int64), (col, "col", torch.int32),
+                        (val, "val", torch.float64)):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{name} must be a torch tensor on a GPU device")
+        if t.dtype != dt or t.dim() != 1 or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous 1-D {dt} tensor")
+    q = rowptr.numel() - 1
+    if q < 1:
+        raise ValueError("rowptr must hold q + 1 >= 2 offsets")
+    nnz = int(rowptr[-1].item())
+    if col.numel() != nnz or val.numel() != nnz:
+        raise ValueError(f"col and val must hold rowptr[q] = {nnz} entries")
+    cidx = np.ascontiguousarray(np.asarray(cols, dtype=np.int64))
+    if cidx.ndim != 1 or (cidx.size and (cidx.min() < 0 or cidx.max() >= q)):
+        raise ValueError("cols must be a 1-D sequence of indices in [0, q)")
+    cidx = cidx.astype(np.int32)
+    k = int(cidx.size)
+    out = torch.empty((q, max(k, 1)), dtype=torch.float64, device=rowptr.device)[:, :k]
+    it, res = ctypes.c_int(0), ctypes.c_double(0.0)
+    st = _check(lib.cggm_sigma_columns(
+        ctypes.c_void_p(rowptr.data_ptr()), ctypes.c_void_p(col.data_ptr()),
+        ctypes.c_void_p(val.data_ptr()), q, cidx.ctypes.data_as(ctypes.c_void_p), k, tol,
+        max_iter, ctypes.c_void_p(out.data_ptr()), ctypes.byref(it), ctypes.byref(res),
+        _stream(stream)))
+    return SigmaColumns(out, int(it.value), float(res.value), st)
 
 
 def cggm_solve_workspace_bytes(n: int, p: int, q: int) -> int:

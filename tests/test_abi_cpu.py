@@ -192,3 +192,29 @@ def test_server_arguments_without_device(lib):
     st = m.ServerStats()
     assert lib.cggm_server_stats_get(None, ctypes.byref(st)) == m.CGGM_EINVAL
     lib.cggm_server_destroy(None)
+
+
+def test_sigma_columns_arguments_without_device(lib):
+    import numpy as np
+    import paper_1509_04681_amd as m
+    fake = ctypes.c_void_p(64)          # never dereferenced: validation fails first
+    cols = np.array([0, 3], dtype=np.int32)
+    cp = cols.ctypes.data_as(ctypes.c_void_p)
+    it, res = ctypes.c_int(7), ctypes.c_double(7.0)
+
+    def call(q, c, k, tol, max_iter, ptr=fake):
+        return lib.cggm_sigma_columns(ptr, fake, fake, q, c, k, tol, max_iter, fake,
+                                      ctypes.byref(it), ctypes.byref(res), None)
+
+    assert call(0, cp, 2, 1e-10, 100) == m.CGGM_EINVAL          # q >= 1
+    assert call(4, cp, -1, 1e-10, 100) == m.CGGM_EINVAL         # k >= 0
+    assert call(4, cp, 2, 1e-10, 0) == m.CGGM_EINVAL            # max_iter >= 1
+    assert call(4, cp, 2, -1.0, 100) == m.CGGM_EINVAL           # tol >= 0
+    assert call(4, cp, 2, float("nan"), 100) == m.CGGM_EINVAL
+    assert call(4, cp, 2, float("inf"), 100) == m.CGGM_EINVAL
+    assert call(3, cp, 2, 1e-10, 100) == m.CGGM_EINVAL          # column 3 outside [0, 3)
+    assert "column index 3" in m.load().cggm_last_error().decode()
+    assert call(4, cp, 2, 1e-10, 100, ptr=None) == m.CGGM_EINVAL
+    # no columns: nothing to do, outputs zeroed, no device access
+    assert call(4, None, 0, 1e-10, 100) == m.CGGM_OK
+    assert it.value == 0 and res.value == 0.0
