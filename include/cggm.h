@@ -393,8 +393,8 @@ int cggm_gradient(const void *X, const void *Y, int64_t n, int64_t p, int64_t q,
  * Returns CGGM_OK when every column reached tol, CGGM_MAXITER (result valid)
  * when some did not within max_iter, CGGM_ENOTPD when a search direction met
  * a curvature p^T Lambda p that is not positive (Lambda not positive
- * definite), CGGM_EINVAL, CGGM_ENOMEM (the call allocates 2 KiB per row of
- * Lambda plus 2 MiB, freed before it returns) or CGGM_EHIP.  Work is ordered
+ * definite), CGGM_EINVAL, CGGM_ENOMEM (the call allocates 2.5 KiB per row
+ * of Lambda plus 0.5 MiB, freed before it returns) or CGGM_EHIP.  Work is ordered
  * on `stream` and the call returns when it is done.
  */
 int cggm_sigma_columns(const int64_t *rowptr, const int32_t *col, const double *val,

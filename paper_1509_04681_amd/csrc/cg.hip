@@ -24,6 +24,7 @@ namespace {
 
 constexpr int CG_COLS = 64;                          // columns per batch: one per lane
 constexpr int CG_BLOCKS = 1024;                      // workgroups of the row kernels
+                                                     // (one partial each per column)
 constexpr int CG_WAVES = CG_BLOCKS * (BLOCK / WAVE); // waves of the row kernels
 constexpr int CG_CHECK = 8;                          // iterations between host checks
 
@@ -41,12 +42,13 @@ __global__ __launch_bounds__(BLOCK) void cg_check_cols_kernel(const int32_t *__r
     }
 }
 
-// X = 0, R = P = E (column c of the batch is e_{cols[c]}), rr = 1 for the
-// batch's columns; padding columns (c >= kb) start converged.
+// X = 0, R = E (column c of the batch is e_{cols[c]}), the previous
+// direction P0 = 0 (the first direction is then R), rr = 1 for the batch's
+// columns; padding columns (c >= kb) start converged.
 __global__ __launch_bounds__(BLOCK) void cg_init_kernel(int64_t q, const int32_t *__restrict__ cols,
                                                         int kb, double *__restrict__ X,
                                                         double *__restrict__ R,
-                                                        double *__restrict__ P,
+                                                        double *__restrict__ P0,
                                                         double *__restrict__ rr,
                                                         int *__restrict__ done,
                                                         int *__restrict__ flag) {
@@ -55,10 +57,9 @@ __global__ __launch_bounds__(BLOCK) void cg_init_kernel(int64_t q, const int32_t
          e += (int64_t)gridDim.x * BLOCK) {
         const int64_t i = e / CG_COLS;
         const int c = (int)(e % CG_COLS);
-        const double v = (c < kb && cols[c] == i) ? 1.0 : 0.0;
         X[e] = 0.0;
-        R[e] = v;
-        P[e] = v;
+        R[e] = (c < kb && cols[c] == i) ? 1.0 : 0.0;
+        P0[e] = 0.0;
     }
     if (blockIdx.x == 0 && threadIdx.x < CG_COLS) {
         const int c = threadIdx.x;
@@ -68,60 +69,120 @@ __global__ __launch_bounds__(BLOCK) void cg_init_kernel(int64_t q, const int32_t
     }
 }
 
-// AP = Lambda P, one wave per row (lane = column), and per-wave partial
-// sums of P .* AP per column into part[wave][c].
-__global__ __launch_bounds__(BLOCK) void cg_spmv_kernel(int64_t q, const int64_t *__restrict__ rowptr,
-                                                        const int32_t *__restrict__ col,
-                                                        const double *__restrict__ val,
-                                                        const double *__restrict__ P,
-                                                        double *__restrict__ AP,
-                                                        double *__restrict__ part) {
+// The four waves' per-lane values summed in wave order into
+// part[block][lane] (one partial per workgroup and column).
+__device__ __forceinline__ void block_partial(double v, double *__restrict__ part) {
+    __shared__ double red[BLOCK / WAVE][WAVE];
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    red[wid][lane] = v;
+    __syncthreads();
+    if (wid == 0)
+        part[(int64_t)blockIdx.x * CG_COLS + lane] =
+            (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+}
+
+// Row i of the new direction and of the product: every P entry the row
+// reads is formed on the fly as R + beta Pold (bit for bit the value row j
+// writes for itself), the entries of the row taken four at a time with the
+// index clamped into the row and the value of a missing entry zero.
+struct CgRow {
+    double ap, p;      // (Lambda Pnew)_i and Pnew_i of this lane's column
+};
+__device__ __forceinline__ CgRow cg_row(int64_t i, int lane, double beta,
+                                        const int64_t *__restrict__ rowptr,
+                                        const int32_t *__restrict__ col,
+                                        const double *__restrict__ val,
+                                        const double *__restrict__ R,
+                                        const double *__restrict__ Pold) {
+    const int64_t b = rowptr[i], e = rowptr[i + 1];
+    double s0 = 0.0, s1 = 0.0;
+    for (int64_t t = b; t < e; t += 4) {
+        int64_t j[4];
+        double v[4], pj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t tu = t + u < e ? t + u : e - 1;
+            j[u] = col[tu];
+            v[u] = t + u < e ? val[tu] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t o = j[u] * CG_COLS + lane;
+            pj[u] = fma(beta, Pold[o], R[o]);
+        }
+        s0 = fma(v[0], pj[0], s0);
+        s1 = fma(v[1], pj[1], s1);
+        s0 = fma(v[2], pj[2], s0);
+        s1 = fma(v[3], pj[3], s1);
+    }
+    const int64_t o = i * CG_COLS + lane;
+    return CgRow{s0 + s1, fma(beta, Pold[o], R[o])};
+}
+
+// Pnew = R + beta Pold with beta = rr / rr_prev (0 on the first iteration
+// and for converged columns), AP = Lambda Pnew, one wave per row (lane =
+// column; two rows of the wave in flight), and per-workgroup partial sums of
+// Pnew .* AP per column.
+__global__ __launch_bounds__(BLOCK) void cg_product_kernel(
+    int64_t q, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+    const double *__restrict__ val, const double *__restrict__ R,
+    const double *__restrict__ Pold, double *__restrict__ Pnew, double *__restrict__ AP,
+    const double *__restrict__ rr, const double *__restrict__ rr_prev,
+    const int *__restrict__ done, int first, double *__restrict__ part) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t gw = (int64_t)blockIdx.x * (BLOCK / WAVE) +
                        __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const double beta =
+        (first || done[lane] || !(rr_prev[lane] > 0.0)) ? 0.0 : rr[lane] / rr_prev[lane];
     double dot = 0.0;
-    for (int64_t i = gw; i < q; i += CG_WAVES) {
-        const int64_t b = rowptr[i], e = rowptr[i + 1];
-        double s0 = 0.0, s1 = 0.0;
-        int64_t t = b;
-        for (; t + 4 <= e; t += 4) {
-            const int64_t j0 = col[t], j1 = col[t + 1], j2 = col[t + 2], j3 = col[t + 3];
-            const double v0 = val[t], v1 = val[t + 1], v2 = val[t + 2], v3 = val[t + 3];
-            const double p0 = P[j0 * CG_COLS + lane], p1 = P[j1 * CG_COLS + lane];
-            const double p2 = P[j2 * CG_COLS + lane], p3 = P[j3 * CG_COLS + lane];
-            s0 = fma(v0, p0, s0);
-            s1 = fma(v1, p1, s1);
-            s0 = fma(v2, p2, s0);
-            s1 = fma(v3, p3, s1);
+    for (int64_t i = gw; i < q; i += 2 * CG_WAVES) {
+        const int64_t i2 = i + CG_WAVES;
+        const CgRow a = cg_row(i, lane, beta, rowptr, col, val, R, Pold);
+        if (i2 < q) {
+            const CgRow c = cg_row(i2, lane, beta, rowptr, col, val, R, Pold);
+            Pnew[i2 * CG_COLS + lane] = c.p;
+            AP[i2 * CG_COLS + lane] = c.ap;
+            dot = fma(c.p, c.ap, dot);
         }
-        for (; t < e; ++t) s0 = fma(val[t], P[(int64_t)col[t] * CG_COLS + lane], s0);
-        const double s = s0 + s1;
-        AP[i * CG_COLS + lane] = s;
-        dot = fma(P[i * CG_COLS + lane], s, dot);
+        Pnew[i * CG_COLS + lane] = a.p;
+        AP[i * CG_COLS + lane] = a.ap;
+        dot = fma(a.p, a.ap, dot);
     }
-    part[gw * CG_COLS + lane] = dot;
+    block_partial(dot, part);
 }
 
-// out[c] = sum over the waves of part[w][c], in wave order per thread and a
-// fixed tree over the threads: one workgroup per column.
+// out[c] = sum of the CG_BLOCKS partials of column c, in block order per
+// thread and a fixed tree over the threads: one workgroup per column.  With
+// `tail`, the column's step also ends here: a curvature that is not positive
+// is flagged, and the column is marked converged once its residual norm
+// sqrt(out[c]) is at most tol.
 __global__ __launch_bounds__(BLOCK) void cg_reduce_kernel(const double *__restrict__ part,
-                                                          double *__restrict__ out) {
+                                                          double *__restrict__ out, int tail,
+                                                          const double *__restrict__ pap,
+                                                          int *__restrict__ done,
+                                                          int *__restrict__ flag, double tol) {
     __shared__ double red[BLOCK];
     const int c = blockIdx.x, tid = threadIdx.x;
     double s = 0.0;
-    for (int w = tid; w < CG_WAVES; w += BLOCK) s += part[(int64_t)w * CG_COLS + c];
+    for (int w = tid; w < CG_BLOCKS; w += BLOCK) s += part[(int64_t)w * CG_COLS + c];
     red[tid] = s;
     __syncthreads();
     for (int h = BLOCK / 2; h > 0; h >>= 1) {
         if (tid < h) red[tid] += red[tid + h];
         __syncthreads();
     }
-    if (tid == 0) out[c] = red[0];
+    if (tid == 0) {
+        out[c] = red[0];
+        if (tail && !done[c]) {
+            if (!(pap[c] > 0.0)) flag[FLAG_NOTPD] = 1;
+            if (sqrt(red[0]) <= tol) done[c] = 1;
+        }
+    }
 }
 
 // alpha = rr / pAp per column (zero for converged columns and for a
-// curvature that is not positive); X += alpha P, R -= alpha AP, and per-wave
-// partial sums of R .* R.
+// curvature that is not positive); X += alpha P, R -= alpha AP (two rows of
+// the wave in flight), and per-workgroup partial sums of R .* R.
 __global__ __launch_bounds__(BLOCK) void cg_axpy_kernel(int64_t q, double *__restrict__ X,
                                                         double *__restrict__ R,
                                                         const double *__restrict__ P,
@@ -136,45 +197,31 @@ __global__ __launch_bounds__(BLOCK) void cg_axpy_kernel(int64_t q, double *__res
     const double den = pap[lane];
     const double alpha = (!done[lane] && den > 0.0) ? rr[lane] / den : 0.0;
     double dot = 0.0;
-    for (int64_t i = gw; i < q; i += CG_WAVES) {
-        const int64_t o = i * CG_COLS + lane;
-        double r = R[o];
+    for (int64_t i = gw; i < q; i += 2 * CG_WAVES) {
+        const int64_t o = i * CG_COLS + lane, o2 = o + (int64_t)CG_WAVES * CG_COLS;
+        const bool has2 = i + CG_WAVES < q;
+        double r = R[o], r2 = has2 ? R[o2] : 0.0;
         if (alpha != 0.0) {
-            X[o] = fma(alpha, P[o], X[o]);
-            r = fma(-alpha, AP[o], r);
+            const double x = X[o], p = P[o], ap = AP[o];
+            double x2 = 0.0, p2 = 0.0, ap2 = 0.0;
+            if (has2) {
+                x2 = X[o2];
+                p2 = P[o2];
+                ap2 = AP[o2];
+            }
+            X[o] = fma(alpha, p, x);
+            r = fma(-alpha, ap, r);
             R[o] = r;
+            if (has2) {
+                X[o2] = fma(alpha, p2, x2);
+                r2 = fma(-alpha, ap2, r2);
+                R[o2] = r2;
+            }
         }
         dot = fma(r, r, dot);
+        dot = fma(r2, r2, dot);
     }
-    part[gw * CG_COLS + lane] = dot;
-}
-
-// P = R + beta P with beta = rr_new / rr, for the columns not yet converged.
-__global__ __launch_bounds__(BLOCK) void cg_direction_kernel(int64_t q, const double *__restrict__ R,
-                                                             double *__restrict__ P,
-                                                             const double *__restrict__ rr,
-                                                             const double *__restrict__ rr_new,
-                                                             const int *__restrict__ done) {
-    const int64_t total = q * CG_COLS;
-    for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * BLOCK) {
-        const int c = (int)(e % CG_COLS);
-        if (done[c]) continue;
-        const double beta = rr[c] > 0.0 ? rr_new[c] / rr[c] : 0.0;
-        P[e] = fma(beta, P[e], R[e]);
-    }
-}
-
-// Per column: flag a curvature that is not positive, take rr = rr_new and
-// mark the column converged once its residual norm is at most tol.
-__global__ void cg_scalar_kernel(double *__restrict__ rr, const double *__restrict__ rr_new,
-                                 const double *__restrict__ pap, int *__restrict__ done,
-                                 int *__restrict__ flag, double tol) {
-    const int c = threadIdx.x;
-    if (c >= CG_COLS || done[c]) return;
-    if (!(pap[c] > 0.0)) flag[FLAG_NOTPD] = 1;
-    rr[c] = rr_new[c];
-    if (sqrt(rr_new[c]) <= tol) done[c] = 1;
+    block_partial(dot, part);
 }
 
 // out[i * ldo + c] = X[i][c] for the kb columns of the batch.
@@ -239,18 +286,18 @@ int sigma_columns_impl(const int64_t *rowptr, const int32_t *col, const double *
     const int64_t nnz = rp[q];
 
     const size_t zb = sizeof(double) * (size_t)q * CG_COLS;
-    const size_t partb = sizeof(double) * (size_t)CG_WAVES * CG_COLS;
-    DevBuf buf(4 * zb + partb + 3 * CG_COLS * sizeof(double) +
+    const size_t partb = sizeof(double) * (size_t)CG_BLOCKS * CG_COLS;
+    DevBuf buf(5 * zb + partb + 3 * CG_COLS * sizeof(double) +
                (CG_COLS + 2 + CG_COLS) * sizeof(int));
     char *base = static_cast<char *>(buf.p);
     double *X = reinterpret_cast<double *>(base);
     double *R = reinterpret_cast<double *>(base + zb);
-    double *P = reinterpret_cast<double *>(base + 2 * zb);
-    double *AP = reinterpret_cast<double *>(base + 3 * zb);
-    double *part = reinterpret_cast<double *>(base + 4 * zb);
-    double *rr = part + (size_t)CG_WAVES * CG_COLS;
-    double *rr_new = rr + CG_COLS;
-    double *pap = rr_new + CG_COLS;
+    double *Pb[2] = {reinterpret_cast<double *>(base + 2 * zb),
+                     reinterpret_cast<double *>(base + 3 * zb)};
+    double *AP = reinterpret_cast<double *>(base + 4 * zb);
+    double *part = reinterpret_cast<double *>(base + 5 * zb);
+    double *rrb = part + (size_t)CG_BLOCKS * CG_COLS;   // two slots of CG_COLS
+    double *pap = rrb + 2 * CG_COLS;
     int *done = reinterpret_cast<int *>(pap + CG_COLS);
     int *flag = done + CG_COLS;
     int32_t *cols_dev = flag + 2;
@@ -278,22 +325,26 @@ int sigma_columns_impl(const int64_t *rowptr, const int32_t *col, const double *
         std::copy(cols + t0, cols + t0 + kb, hcols.begin());
         CGGM_HIP(hipMemcpyAsync(cols_dev, hcols.data(), sizeof(int32_t) * CG_COLS,
                                 hipMemcpyHostToDevice, s));
-        cg_init_kernel<<<zblocks, BLOCK, 0, s>>>(q, cols_dev, kb, X, R, P, rr, done, flag);
+        cg_init_kernel<<<zblocks, BLOCK, 0, s>>>(q, cols_dev, kb, X, R, Pb[0], rrb, done, flag);
         CGGM_LAUNCH_CHECK();
         int it = 0;
         bool converged = false;
         while (it < max_iter) {
-            cg_spmv_kernel<<<CG_BLOCKS, BLOCK, 0, s>>>(q, rowptr, col, val, P, AP, part);
+            // iteration it: rr in slot it & 1 (the previous one in the other
+            // slot, which this iteration's new rr replaces); direction it - 1
+            // in Pb[it & 1], the new one into Pb[(it + 1) & 1]
+            double *rr = rrb + (it & 1) * CG_COLS, *rr_other = rrb + ((it + 1) & 1) * CG_COLS;
+            const double *Pold = Pb[it & 1];
+            double *Pnew = Pb[(it + 1) & 1];
+            cg_product_kernel<<<CG_BLOCKS, BLOCK, 0, s>>>(q, rowptr, col, val, R, Pold, Pnew, AP,
+                                                          rr, rr_other, done, it == 0, part);
             CGGM_LAUNCH_CHECK();
-            cg_reduce_kernel<<<CG_COLS, BLOCK, 0, s>>>(part, pap);
+            cg_reduce_kernel<<<CG_COLS, BLOCK, 0, s>>>(part, pap, 0, nullptr, nullptr, nullptr,
+                                                       tol);
             CGGM_LAUNCH_CHECK();
-            cg_axpy_kernel<<<CG_BLOCKS, BLOCK, 0, s>>>(q, X, R, P, AP, rr, pap, done, part);
+            cg_axpy_kernel<<<CG_BLOCKS, BLOCK, 0, s>>>(q, X, R, Pnew, AP, rr, pap, done, part);
             CGGM_LAUNCH_CHECK();
-            cg_reduce_kernel<<<CG_COLS, BLOCK, 0, s>>>(part, rr_new);
-            CGGM_LAUNCH_CHECK();
-            cg_direction_kernel<<<zblocks, BLOCK, 0, s>>>(q, R, P, rr, rr_new, done);
-            CGGM_LAUNCH_CHECK();
-            cg_scalar_kernel<<<1, CG_COLS, 0, s>>>(rr, rr_new, pap, done, flag, tol);
+            cg_reduce_kernel<<<CG_COLS, BLOCK, 0, s>>>(part, rr_other, 1, pap, done, flag, tol);
             CGGM_LAUNCH_CHECK();
             ++it;
             if (it % CG_CHECK == 0 || it == max_iter) {
@@ -309,8 +360,8 @@ int sigma_columns_impl(const int64_t *rowptr, const int32_t *col, const double *
         }
         cg_store_kernel<<<zblocks, BLOCK, 0, s>>>(q, kb, X, out + t0, k);
         CGGM_LAUNCH_CHECK();
-        CGGM_HIP(hipMemcpyAsync(hrr.data(), rr, sizeof(double) * CG_COLS, hipMemcpyDeviceToHost,
-                                s));
+        CGGM_HIP(hipMemcpyAsync(hrr.data(), rrb + (it & 1) * CG_COLS, sizeof(double) * CG_COLS,
+                                hipMemcpyDeviceToHost, s));
         CGGM_HIP(hipStreamSynchronize(s));
         for (int c = 0; c < kb; ++c) resid = std::max(resid, sqrt(hrr[c]));
         iters_max = std::max(iters_max, it);

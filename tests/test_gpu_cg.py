@@ -101,10 +101,10 @@ def test_sigma_columns_chain_full_size(cg):
     got = r.Sigma_C.cpu().numpy()
     err = np.abs(got - ref).max() / np.abs(ref).max()
     nnz = 3 * q - 2
-    # per iteration: the CSR arrays once, P read and AP written by the
-    # product, X, R read and written, P and AP read by the update, R read and
-    # P read and written by the new direction (64 columns of 8 bytes a row)
-    bytes_it = 12 * nnz + 8 * (q + 1) + 11 * q * 64 * 8
+    # per iteration: the CSR arrays once; R and the previous direction read,
+    # the new direction and Lambda P written by the product; X and R read and
+    # written, P and Lambda P read by the update (64 columns of 8 bytes a row)
+    bytes_it = 12 * nnz + 8 * (q + 1) + 10 * q * 64 * 8
     print(f"sigma_columns chain q={q} k=64: {el * 1e3:.2f} ms, {r.iters} iterations, "
           f"{el / r.iters * 1e6:.1f} us per iteration ({bytes_it * r.iters / el / 1e9:.0f} GB/s "
           f"algorithmic), resid {r.resid:.2e}, err {err:.2e}", flush=True)
