@@ -401,6 +401,31 @@ int cggm_sigma_columns(const int64_t *rowptr, const int32_t *col, const double *
                        int64_t q, const int32_t *cols, int64_t k, double tol, int max_iter,
                        double *Sigma_C, int *iters, double *resid, void *stream);
 
+/*
+ * Balanced k-way partition of a graph minimising the number of cut edges,
+ * for the column blocks of the block-wise method: Sec. 4.1 clusters the
+ * graph of Lambda's active set so that few active entries fall in
+ * off-diagonal blocks, and Sec. 4.2 clusters the columns of Theta through
+ * the graph of the nonzeros of Theta^T Theta; this takes the place of the
+ * external partitioning library the paper uses.  Host memory, computed on
+ * the host (recursive bisection: greedy growing from a peripheral vertex,
+ * then Fiduccia-Mattheyses refinement); deterministic.
+ *   n: vertices, 1 <= n < 2^31.
+ *   rowptr (n + 1 int64, starting at 0, not decreasing), col (rowptr[n]
+ *     int32 in [0, n)): the adjacency pattern in CSR.  The graph is the
+ *     undirected union of the listed pairs: (u, v) and (v, u) are one edge,
+ *     repeats and self loops are ignored, so a triangle or a full symmetric
+ *     pattern may be given.
+ *   nparts: 1 <= nparts <= n.
+ *   imbalance >= 0: every part gets at least one vertex and at most
+ *     max(ceil(n / nparts), floor((1 + imbalance) n / nparts)).
+ *   part (host, n int32): the part of each vertex, in [0, nparts).
+ *   cut (host, may be NULL): the number of edges between different parts.
+ * Returns CGGM_OK or CGGM_EINVAL (bad sizes or pattern; part untouched).
+ */
+int cggm_partition_graph(int64_t n, const int64_t *rowptr, const int32_t *col, int64_t nparts,
+                         double imbalance, int32_t *part, int64_t *cut);
+
 /* ---- request server (continuous batching on one GPU) --------------------
  *
  * Solves regularisation paths of many independent problems concurrently on

@@ -8,7 +8,7 @@ library, but every call raises if ``libcggm.so`` is missing.
 Entry points mirror ``include/cggm.h``: :func:`cggm_solve`,
 :func:`cggm_solve_path`, :func:`cggm_objective`,
 :func:`cggm_objective_noalloc`, :func:`cggm_lambda_direction`,
-:func:`cggm_gradient`, :func:`cggm_sigma_columns`, the
+:func:`cggm_gradient`, :func:`cggm_sigma_columns`, :func:`cggm_partition_graph`, the
 request server :class:`Server` (``cggm_server_*``), plus
 ``cggm_status_string`` and the workspace-size queries.
 """
@@ -176,6 +176,9 @@ def load() -> ctypes.CDLL:
                                        ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_int),
                                        ctypes.POINTER(ctypes.c_double), _vp]
     lib.cggm_sigma_columns.restype = ctypes.c_int
+    lib.cggm_partition_graph.argtypes = [_i64, _vp, _vp, _i64, ctypes.c_double, _vp,
+                                         ctypes.POINTER(_i64)]
+    lib.cggm_partition_graph.restype = ctypes.c_int
     lib.cggm_status_string.argtypes = [ctypes.c_int]
     lib.cggm_status_string.restype = ctypes.c_char_p
     lib.cggm_last_error.argtypes = []
@@ -526,6 +529,25 @@ def cggm_sigma_columns(rowptr, col, val, cols, tol=1e-12, max_iter=1000, stream=
         max_iter, ctypes.c_void_p(out.data_ptr()), ctypes.byref(it), ctypes.byref(res),
         _stream(stream)))
     return SigmaColumns(out, int(it.value), float(res.value), st)
+
+
+def cggm_partition_graph(rowptr, col, nparts: int, imbalance: float = 0.05):
+    """Balanced partition of a graph into `nparts` parts with few cut edges
+    (the block-wise method's graph clustering, Sec. 4.1 and 4.2), computed on
+    the host: `rowptr` (n + 1) and `col` (rowptr[n]) are the adjacency
+    pattern in CSR as host arrays, taken as undirected.  Returns (part of
+    each vertex as an int32 array, number of cut edges)."""
+    lib = load()
+    rp = np.ascontiguousarray(rowptr, dtype=np.int64)
+    cl = np.ascontiguousarray(col, dtype=np.int32)
+    n = rp.size - 1
+    if n < 1 or cl.size != int(rp[-1]):
+        raise ValueError("rowptr must hold n + 1 >= 2 offsets and col rowptr[n] entries")
+    part = np.empty(n, dtype=np.int32)
+    cut = _i64(0)
+    _check(lib.cggm_partition_graph(n, rp.ctypes.data_as(_vp), cl.ctypes.data_as(_vp), nparts,
+                                    imbalance, part.ctypes.data_as(_vp), ctypes.byref(cut)))
+    return part, int(cut.value)
 
 
 def cggm_solve_workspace_bytes(n: int, p: int, q: int) -> int:

@@ -12,7 +12,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libcggm.so")
-SOURCES = ["la.hip", "cd.hip", "mixed.hip", "engine.hip", "serve.hip", "cg.hip"]
+SOURCES = ["la.hip", "cd.hip", "mixed.hip", "engine.hip", "serve.hip", "cg.hip",
+           "partition.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", f"-I{INCLUDE}"]

@@ -1,7 +1,8 @@
 """Host tests of plain C++ parts of the library, compiled with g++ under
 AddressSanitizer and UndefinedBehaviorSanitizer and run (no GPU): the request
 server's device-pool allocator and admission rule
-(paper_1509_04681_amd/csrc/admission.hpp) and the sweeps' wave schedules; and
+(paper_1509_04681_amd/csrc/admission.hpp), the sweeps' wave schedules and the
+graph partitioner; and
 the CPU oracle (oracle/cggm_oracle.c) under the same sanitizers."""
 import os
 import shutil
@@ -38,6 +39,22 @@ def test_wave_schedules(tmp_path):
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "checks passed" in r.stdout
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+def test_graph_partitioner(tmp_path):
+    """The block-wise method's graph partitioner
+    (paper_1509_04681_amd/csrc/partition.hpp): valid parts within the size
+    bound, the optimal cut on paths, grids and disjoint cliques, malformed
+    patterns rejected, deterministic."""
+    exe = tmp_path / "partition_test"
+    subprocess.run(["g++", "-std=c++17", "-O1", "-Wall", "-Werror", *SANITIZE,
+                    "-I", os.path.join(ROOT, "paper_1509_04681_amd", "csrc"),
+                    os.path.join(ROOT, "tests", "cpp", "partition_test.cpp"), "-o", str(exe)],
+                   check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "all checks passed" in r.stdout
 
 
 @pytest.mark.skipif(shutil.which("gcc") is None, reason="needs gcc")
