@@ -24,11 +24,12 @@
  *   - Return value: CGGM_OK (0), a warning (> 0: results are valid) or an error
  *     (< 0: outputs are left untouched).  cggm_last_error() gives a message for
  *     the last failing call on the calling thread.
- *   - No entry point throws.  The solve entry points allocate their device
- *     workspace per call with hipMalloc and free it before returning; the
- *     request server allocates one device pool when it is created and carves
- *     every request's workspace out of it; cggm_objective_noalloc uses a
- *     static device array and allocates nothing.
+ *   - No entry point throws.  The solve entry points (and cggm_sigma_columns)
+ *     allocate their device workspace per call with hipMalloc and free it
+ *     before returning; the request server allocates one device pool when it
+ *     is created and carves every request's workspace out of it;
+ *     cggm_objective_noalloc uses a static device array and allocates
+ *     nothing; cggm_partition_graph works in host memory only.
  */
 #ifndef CGGM_H
 #define CGGM_H
