@@ -1455,9 +1455,9 @@ int direction_impl(const void *X, const void *Y, int64_t n, int64_t p, int64_t q
 // the given shape (X and Y standard normal from a counter-based generator,
 // lambda = 0.02, at which the screen is near-dense -- the hard case) for each
 // candidate edge, one warm-up iteration and `iters` timed ones from
-// Lambda = I, Theta = 0, and returns the fastest.  Smaller tiles shorten the
-// in-tile Gauss-Seidel chains (R x C dependent steps) and put more tiles in a
-// wave; larger ones need fewer waves and launches.
+// Lambda = I, Theta = 0, and returns the fastest by the rule below.  Smaller
+// tiles shorten the in-tile Gauss-Seidel chains (R x C dependent steps) and
+// put more tiles in a wave; larger ones need fewer waves and launches.
 int autotune_impl(int64_t n, int64_t p, int64_t q, const cggm_options *opt_in, int iters,
                   int *tile_out, double *ms_out, hipStream_t s) {
     if (!tile_out) fail(CGGM_EINVAL, "NULL pointer argument");
