@@ -151,6 +151,29 @@ int main() {
         printf("grid %dx%d k=4: cut %lld\n", w, w, (long long)cut);
         CHECK(cut == 80);
     }
+    // random small graphs of every shape: sizes from 1, k from 1 to n,
+    // densities from empty to dense, several components, repeats and self
+    // loops; every partition valid (checked inside run) and repeatable
+    {
+        std::mt19937 rng(2024);
+        for (int trial = 0; trial < 250; ++trial) {
+            const int n = 1 + (int)(rng() % 160);
+            const int k = 1 + (int)(rng() % n);
+            const double dens[4] = {0.0, 0.01, 0.05, 0.4};
+            const double dp = dens[rng() % 4];
+            const double imbs[3] = {0.0, 0.03, 0.25};
+            const double imb = imbs[rng() % 3];
+            std::bernoulli_distribution coin(dp);
+            std::vector<std::pair<int, int>> e;
+            for (int a = 0; a < n; ++a)
+                for (int b = 0; b < n; ++b)
+                    if (coin(rng)) e.push_back({a, b});   // both orders, self loops
+            std::vector<int32_t> p1, p2;
+            const int64_t c1 = run(n, e, k, imb, p1);
+            const int64_t c2 = run(n, e, k, imb, p2);
+            CHECK(c1 == c2 && p1 == p2);
+        }
+    }
     // malformed patterns
     {
         Graph g;
