@@ -68,6 +68,23 @@ def load(name: str) -> dict:
 TAIL_WINDOWS = (10, 20, 40, 80)
 
 
+def fit_tail(f):
+    """Geometric-tail extrapolations of the limit of a decreasing sequence f:
+    for each window w, the factor r by which the last w decreases shrink
+    (least squares on their logarithms) and f[-1] - d_last r / (1 - r)."""
+    f = np.asarray(f, dtype=np.float64)
+    d = -np.diff(f)
+    assert d.size >= max(TAIL_WINDOWS), "too short a sequence"
+    assert (d[-max(TAIL_WINDOWS):] > 0).all(), "the tail is not strictly decreasing"
+    fits = []
+    for w in TAIL_WINDOWS:
+        rate = float(np.exp(np.polyfit(np.arange(w), np.log(d[-w:]), 1)[0]))
+        assert rate < 1.0
+        gap = float(d[-1] * rate / (1.0 - rate))
+        fits.append({"window": w, "rate": rate, "gap": gap, "f_star": float(f[-1]) - gap})
+    return fits
+
+
 def tail_estimate(args, pr):
     """Summarise a saved oracle run (see the module docstring)."""
     state = args.state_dir
@@ -80,13 +97,7 @@ def tail_estimate(args, pr):
     assert f_K is not None, "saved Lambda is not positive definite"
     f = np.array(fs + [f_K])          # f at the top of iterations 0 .. done
     d = -np.diff(f)
-    assert (d[-max(TAIL_WINDOWS):] > 0).all(), "the tail is not strictly decreasing"
-    fits = []
-    for w in TAIL_WINDOWS:
-        rate = float(np.exp(np.polyfit(np.arange(w), np.log(d[-w:]), 1)[0]))
-        assert rate < 1.0
-        gap = float(d[-1] * rate / (1.0 - rate))
-        fits.append({"window": w, "rate": rate, "gap": gap, "f_star": f_K - gap})
+    fits = fit_tail(f)
     est = [x["f_star"] for x in fits]
     out = {
         "workload": args.workload, "seed": args.seed, "n": pr.n, "p": pr.p, "q": pr.q,
