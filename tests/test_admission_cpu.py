@@ -61,7 +61,8 @@ def test_graph_partitioner(tmp_path):
 def test_oracle_under_sanitizers(tmp_path):
     """Every oracle entry point on small problems (incl. n < p and the
     huge-page allocation path) with ASan/UBSan: no invalid access, leak or
-    undefined arithmetic.  OpenMP is left out of this build (pragmas ignored)."""
+    undefined arithmetic.  OpenMP is left out of this sanitizer build (pragmas
+    ignored)."""
     exe = tmp_path / "oracle_sanitize"
     subprocess.run(["gcc", "-std=c11", "-O1", "-Wall", "-Werror", "-Wno-unknown-pragmas",
                     *SANITIZE, "-I", os.path.join(ROOT, "oracle"),
