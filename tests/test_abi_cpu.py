@@ -218,3 +218,36 @@ def test_sigma_columns_arguments_without_device(lib):
     # no columns: nothing to do, outputs zeroed, no device access
     assert call(4, None, 0, 1e-10, 100) == m.CGGM_OK
     assert it.value == 0 and res.value == 0.0
+
+
+def test_remaining_entry_points_reject_bad_arguments_without_device(lib):
+    """The gradient, the Newton-direction probe, the tile tuner and the result
+    accessors validate their arguments before any device work."""
+    import paper_1509_04681_amd as m
+    fake = ctypes.c_void_p(64)          # never dereferenced: validation fails first
+    assert lib.cggm_gradient(None, fake, 4, 3, 2, 0, fake, fake, fake, fake, None) \
+        == m.CGGM_EINVAL
+    assert lib.cggm_gradient(fake, fake, 4, 3, 2, 0, fake, fake, None, fake, None) \
+        == m.CGGM_EINVAL
+    assert lib.cggm_gradient(fake, fake, 0, 3, 2, 0, fake, fake, fake, fake, None) \
+        == m.CGGM_EINVAL
+    assert lib.cggm_gradient(fake, fake, 4, 3, 2, 7, fake, fake, fake, fake, None) \
+        == m.CGGM_EINVAL
+    assert lib.cggm_lambda_direction(fake, fake, 4, 3, 2, 0, None, fake, 0.1, 0.1, None,
+                                     fake, None, None, None) == m.CGGM_EINVAL
+    assert lib.cggm_lambda_direction(fake, fake, 4, 3, 2, 0, fake, fake, -0.1, 0.1, None,
+                                     fake, None, None, None) == m.CGGM_EINVAL
+    assert lib.cggm_lambda_direction(fake, fake, 4, -3, 2, 0, fake, fake, 0.1, 0.1, None,
+                                     fake, None, None, None) == m.CGGM_EINVAL
+    tile = ctypes.c_int()
+    assert lib.cggm_autotune_tile(100, 50, 50, None, 4, None, None, None) == m.CGGM_EINVAL
+    assert lib.cggm_autotune_tile(100, 50, 50, None, 0, ctypes.byref(tile), None, None) \
+        == m.CGGM_EINVAL
+    assert lib.cggm_autotune_tile(0, 50, 50, None, 4, ctypes.byref(tile), None, None) \
+        == m.CGGM_EINVAL
+    nL, nT, it, f = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int(), ctypes.c_double()
+    st = ctypes.c_int()
+    assert lib.cggm_result_info(None, ctypes.byref(nL), ctypes.byref(nT), ctypes.byref(it),
+                                ctypes.byref(f), ctypes.byref(st)) == m.CGGM_EINVAL
+    assert lib.cggm_result_dense(None, fake, fake, 0) == m.CGGM_EINVAL
+    lib.cggm_result_free(None)            # a no-op
