@@ -283,9 +283,10 @@ def test_chain2k_against_oracle_tail(cg):
     with open(path) as fh:
         tail = json.load(fh)
     pr = synth.workload("chain2k")
-    # f no longer changes in its 12th digit after ~600 iterations here
+    # after 500 iterations f is within 1e-11 (relative) of its limit here,
+    # far inside the tolerance below
     g = cg.cggm_solve(dev(pr.X), dev(pr.Y), pr.lam_Lambda, pr.lam_Theta, tol=0.0,
-                      max_iter=800, trace_cap=0)
+                      max_iter=500, trace_cap=0)
     nL = int(np.count_nonzero(np.abs(g.Lambda.cpu().numpy()) > SUPPORT_EPS))
     nT = int(np.count_nonzero(np.abs(g.Theta.cpu().numpy()) > SUPPORT_EPS))
     est, tol = tail["f_star_estimate"], 2.0 * tail["f_star_spread"]
